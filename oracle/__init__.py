@@ -1,0 +1,277 @@
+"""Reference oracle (test infrastructure only).
+
+Plain FP64 CPU implementation of what the GPU path computes.  Only the test
+suite, the smoke check and the benchmark's CPU-baseline leg may import it;
+the GPU library and its Python binding never do.  It shares no code with the
+GPU library: the compiled part (``oracle.c``) defines the field, the
+finite-volume system, the banded Cholesky solve, the quantity of interest,
+the Algorithm 2.1 refinement reference and the adjoint gradient; this module
+adds the ctypes marshalling and the statistical layer (sec. 4.1 estimator,
+the accuracy rule of sec. 4.5 and Algorithm 4.1 of sec. 4.3).
+
+Functions and the passage each follows:
+  kl_roots / kl_basis      -- KL expansion of the separable exponential
+                              covariance (field of the workloads; the paper's
+                              own field is the trigonometric one of sec. 5.1)
+  solve_batch              -- exact discrete solution, Q = integral of u
+                              (sec. 5.1 QoI)
+  ir_f32_batch             -- Algorithm 2.1 with (u_f,u_s,u,u_r) = (s,s,d,d)
+  grad_batch               -- adjoint dQ/dxi (not in the paper; exact
+                              derivative of the discrete Q)
+  accuracy_targets         -- delta_l of sec. 4.5 (sqrt(k_p) h_l^2, k_p h_L^2)
+  level_estimates          -- Y-hat_l and s_l^2 of sec. 4.1
+  adaptive_mpml            -- Algorithm 4.1 (sec. 4.3)
+  cost_ratio_bound         -- bound of the cost-savings corollary, sec. 4.4
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile oracle.c into liboracle.so with gcc (OpenMP over samples)."""
+    src = os.path.join(_HERE, "oracle.c")
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", _LIB_PATH + ".tmp", src, "-lm"]
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.POINTER(ctypes.c_int)
+        c_int, c_double = ctypes.c_int, ctypes.c_double
+        lib.oracle_kl_roots.argtypes = [c_double, c_int, D]
+        lib.oracle_kl_modes.argtypes = [c_double, c_int, c_int, I, I]
+        lib.oracle_kl_basis.argtypes = [c_int, c_int, c_double, c_double, D]
+        lib.oracle_kl_mu.argtypes = [c_double, c_double]
+        lib.oracle_kl_mu.restype = c_double
+        lib.oracle_kl_phi1d.argtypes = [c_double, c_double, c_double]
+        lib.oracle_kl_phi1d.restype = c_double
+        lib.oracle_solve_batch.argtypes = [c_int, c_int, D, c_int, D, D, c_double, D, D, D]
+        lib.oracle_relres_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, D, D]
+        lib.oracle_ir_f32_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, c_double, c_int,
+                                            D, I, D]
+        lib.oracle_grad_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, D, D, D]
+        lib.oracle_energy.argtypes = [c_int, c_int, D, D, D]
+        lib.oracle_energy.restype = c_double
+        lib.oracle_dense_matrix.argtypes = [c_int, c_int, D, D, D]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _pi(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- KL field
+
+def kl_roots(corr_len, M=64):
+    w = np.zeros(M)
+    if _load().oracle_kl_roots(corr_len, M, _p(w)):
+        raise RuntimeError("bracketing failed")
+    return w
+
+
+def kl_mu(corr_len, w):
+    return np.array([_load().oracle_kl_mu(corr_len, float(x)) for x in np.atleast_1d(w)])
+
+
+def kl_phi1d(corr_len, w, x):
+    return np.array([_load().oracle_kl_phi1d(corr_len, float(w), float(t)) for t in np.atleast_1d(x)])
+
+
+def kl_modes(corr_len, K, M=64):
+    mi = np.zeros(K, dtype=np.int32)
+    mj = np.zeros(K, dtype=np.int32)
+    rc = _load().oracle_kl_modes(corr_len, K, M, _pi(mi), _pi(mj))
+    if rc:
+        raise RuntimeError("mode selection failed (%d)" % rc)
+    return mi, mj
+
+
+def kl_basis(n, K, sigma2, corr_len):
+    """Phi[(n+1)^2, K] on the nodes of the n x n grid (node p = iy*(n+1)+ix)."""
+    Phi = np.zeros(((n + 1) * (n + 1), K))
+    if _load().oracle_kl_basis(n, K, sigma2, corr_len, _p(Phi)):
+        raise RuntimeError("KL basis failed")
+    return Phi
+
+
+# ---------------------------------------------------------------- solves
+
+def solve_batch(n, Phi, xi, f=1.0, a_nodes=None, rhs_nodal=None, want_u=False):
+    """Exact FP64 solve; returns Q[S] (and u[S, (n-1)^2] if want_u)."""
+    K = Phi.shape[1] if Phi is not None else 0
+    if a_nodes is not None:
+        a_nodes = _f64(np.atleast_2d(a_nodes))
+        S = a_nodes.shape[0]
+    else:
+        xi = _f64(np.atleast_2d(xi))
+        S = xi.shape[0]
+    Q = np.zeros(S)
+    u = np.zeros((S, (n - 1) ** 2)) if want_u else None
+    rc = _load().oracle_solve_batch(n, K, _p(_f64(Phi)) if Phi is not None else None, S,
+                                    _p(xi) if a_nodes is None else None, _p(a_nodes), f,
+                                    _p(_f64(rhs_nodal)) if rhs_nodal is not None else None,
+                                    _p(Q), _p(u))
+    if rc:
+        raise RuntimeError("Cholesky breakdown in sample %d" % (rc - 1))
+    return (Q, u) if want_u else Q
+
+
+def relres_batch(n, Phi, xi, x, f=1.0):
+    xi = _f64(np.atleast_2d(xi))
+    x = _f64(np.atleast_2d(x))
+    rr = np.zeros(xi.shape[0])
+    _load().oracle_relres_batch(n, Phi.shape[1], _p(_f64(Phi)), xi.shape[0], _p(xi), f, _p(x), _p(rr))
+    return rr
+
+
+def ir_f32_batch(n, Phi, xi, delta, imax=10, f=1.0):
+    """Algorithm 2.1 with a single-precision factor; returns (Q, trips, relres, n_fail)."""
+    xi = _f64(np.atleast_2d(xi))
+    S = xi.shape[0]
+    Q = np.zeros(S)
+    trips = np.zeros(S, dtype=np.int32)
+    rr = np.zeros(S)
+    nf = _load().oracle_ir_f32_batch(n, Phi.shape[1], _p(_f64(Phi)), S, _p(xi), f, delta, imax,
+                                     _p(Q), _pi(trips), _p(rr))
+    return Q, trips, rr, nf
+
+
+def grad_batch(n, Phi, xi, f=1.0, want_gz=False, want_lambda=False):
+    xi = _f64(np.atleast_2d(xi))
+    S, K = xi.shape
+    g = np.zeros((S, K))
+    gz = np.zeros((S, (n + 1) ** 2)) if want_gz else None
+    lam = np.zeros((S, (n - 1) ** 2)) if want_lambda else None
+    rc = _load().oracle_grad_batch(n, K, _p(_f64(Phi)), S, _p(xi), f, _p(g), _p(gz), _p(lam))
+    if rc:
+        raise RuntimeError("Cholesky breakdown in sample %d" % (rc - 1))
+    out = [g]
+    if want_gz:
+        out.append(gz)
+    if want_lambda:
+        out.append(lam)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def energy(n, Phi, xi, u):
+    return _load().oracle_energy(n, Phi.shape[1], _p(_f64(Phi)), _p(_f64(xi)), _p(_f64(u)))
+
+
+def dense_matrix(n, Phi, xi):
+    N = (n - 1) ** 2
+    A = np.zeros((N, N))
+    _load().oracle_dense_matrix(n, Phi.shape[1], _p(_f64(Phi)), _p(_f64(xi)), _p(A))
+    return A
+
+
+# ---------------------------------------------------------------- MLMC layer
+
+def accuracy_targets(h, L, k_p=0.05):
+    """delta_l, l = 0..L, from the rule of sec. 4.5:
+    delta_l = sqrt(k_p) h_l^2 for l < L and delta_L = k_p h_L^2."""
+    return [math.sqrt(k_p) * h[l] ** 2 if l < L else k_p * h[l] ** 2 for l in range(L + 1)]
+
+
+def level_estimates(y):
+    """Y-hat_l = mean and s_l^2 = (1/N_l) sum (Y - Y-hat)^2 (sec. 4.1)."""
+    y = np.asarray(y, dtype=np.float64)
+    yhat = y.sum() / y.size
+    return yhat, ((y - yhat) ** 2).sum() / y.size
+
+
+def factor_cost(n):
+    """Deterministic cost units of one grid solve: (n-1)^4 (flops of the factor)."""
+    return float((n - 1) ** 4)
+
+
+def level_cost(n0, l, m=2):
+    c = factor_cost(n0 * m ** l)
+    if l > 0:
+        c += factor_cost(n0 * m ** (l - 1))
+    return c
+
+
+def cost_ratio_bound(q, beta, gamma, m=2):
+    """Asymptotic bound q + m^((gamma-beta)/2) (1 - q) of the cost-savings corollary (sec. 4.4)."""
+    r = m ** ((gamma - beta) / 2.0)
+    return q + r * (1.0 - q)
+
+
+def adaptive_mpml(sample_fn, n0, tol, L_max, n_init=1000, m=2, alpha=2.0, k_p=0.05, mixed=True,
+                  max_rounds=100):
+    """Algorithm 4.1 (adaptive MPML), sec. 4.3, in the paper's order.
+
+    sample_fn(level, first, count, delta_fine, delta_coarse) -> array Y of the
+    new samples (Y_0 = Q_0; Y_l = Q_l - Q_{l-1} on one shared xi row).  With
+    mixed=False the accuracy step is skipped (standard MLMC) and deltas are 0.
+    Readings: r = 1 in the bias test; V_l = s_l^2; C_l from level_cost; the
+    coarse partner of Y_l is solved to delta_{l-1}; returns once the bias test
+    and the variance test both hold and no level needs more samples.
+    """
+    h = [1.0 / (n0 * m ** l) for l in range(L_max + 1)]
+    L = 1
+    N = [n_init, n_init]
+    done = [0, 0]
+    s1 = [0.0, 0.0]
+    s2 = [0.0, 0.0]
+    bias_c = (m ** alpha - 1.0) / math.sqrt(2.0) * tol
+    rounds = 0
+    history = []
+    while L <= L_max and rounds < max_rounds:
+        rounds += 1
+        eps = accuracy_targets(h, L, k_p) if mixed else [0.0] * (L + 1)
+        for l in range(L + 1):
+            dn = max(0, int(N[l]) - done[l])
+            if dn > 0:
+                y = np.asarray(sample_fn(l, done[l], dn, eps[l], eps[l - 1] if l > 0 else 0.0))
+                s1[l] += float(y.sum())
+                s2[l] += float((y * y).sum())
+                done[l] += dn
+        yhat = [s1[l] / done[l] for l in range(L + 1)]
+        var = [max(s2[l] / done[l] - yhat[l] ** 2, 0.0) for l in range(L + 1)]
+        C = [level_cost(n0, l, m) for l in range(L + 1)]
+        tot = sum(math.sqrt(var[k] * C[k]) for k in range(L + 1))
+        N = [max(done[l], int(math.ceil(math.sqrt(var[l] / C[l]) * 2.0 / tol ** 2 * tot)))
+             for l in range(L + 1)]
+        history.append(dict(L=L, N=list(N), done=list(done), yhat=list(yhat), var=list(var)))
+        if abs(yhat[L]) > bias_c and L < L_max:
+            L += 1
+            N.append(n_init)
+            done.append(0)
+            s1.append(0.0)
+            s2.append(0.0)
+            continue
+        need_more = any(N[l] > done[l] for l in range(L + 1))
+        var_ok = sum(var[l] / done[l] for l in range(L + 1)) <= tol ** 2 / 2.0
+        if not need_more:
+            return dict(estimate=sum(yhat), L=L, N=list(done), yhat=yhat, s2=var,
+                        bias_ok=abs(yhat[L]) <= bias_c, var_ok=var_ok, rounds=rounds,
+                        history=history)
+    raise RuntimeError("adaptive MPML did not terminate")

@@ -1,0 +1,32 @@
+"""The synthetic workloads (grid sizes, field parameters, sample counts, seeds).
+
+Domain (0,1)^2, f = 1, u = 0 on the boundary, nodal lognormal coefficient
+a = exp(Z) with Z a truncated separable exponential-covariance KL expansion.
+Level l has n_l = n0 * 2**l cells per side.  Seeds are 1000 + workload id.
+"""
+
+WORKLOADS = {
+    # single level, FP64 direct, n=32, K=16
+    "single_n32_K16": dict(id=0, n0=32, levels=[0], K=16, sigma2=1.0, corr_len=0.3,
+                           N=[1000], seed=1000),
+    # four-level MLMC, 16..128 cells per side, coarse partner shares xi
+    "mlmc4_n16-128_K64": dict(id=1, n0=16, levels=[0, 1, 2, 3], K=64, sigma2=1.0,
+                              corr_len=0.3, N=[20000, 5000, 1250, 300], seed=1001),
+    # precision sweep over five levels, 16..256 cells per side
+    "sweep5_n16-256_K128": dict(id=2, n0=16, levels=[0, 1, 2, 3, 4], K=128, sigma2=2.0,
+                                corr_len=0.1, N=[40000, 10637, 2828, 752, 200], seed=1002),
+    # all five levels batched together, geometric sample counts
+    "batched5_n16-256_K128": dict(id=3, n0=16, levels=[0, 1, 2, 3, 4], K=128, sigma2=2.0,
+                                  corr_len=0.1, N=[40000, 10637, 2828, 752, 200], seed=1003),
+    # adjoint gradient at n=128, 4096 samples
+    "adjoint_n128_K128": dict(id=4, n0=128, levels=[0], K=128, sigma2=2.0, corr_len=0.1,
+                              N=[4096], seed=1004),
+}
+
+
+def workload(name):
+    return dict(WORKLOADS[name])
+
+
+def level_cells(n0, level, m=2):
+    return n0 * m ** level

@@ -1,0 +1,347 @@
+"""Pins of the CPU oracle against values fixed by the paper and by mathematics.
+
+Each test pins a part of the oracle to something other than the oracle:
+printed values (Table 1), closed forms, a manufactured solution, the KL
+eigen-equation and an independent Nystrom eigensolve, dense/LAPACK solves,
+invariants (energy identity, mirror symmetry, adjoint identities) and
+finite differences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+import seeded_inputs as si
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.strip() and not line.startswith("#"):
+            out.append(line.split())
+    return out
+
+
+# ------------------------------------------------------------- accuracy rule
+
+def test_delta_rule_reproduces_table1():
+    """Sec. 4.5 rule vs Table 1 (left): h0 = 1/8, k_p = 0.05, L = 1..4."""
+    h = [1.0 / (8 * 2 ** l) for l in range(5)]
+    for row in _rows("table1_delta.txt"):
+        L = int(row[0])
+        printed = [float(v) for v in row[1:]]
+        got = oracle.accuracy_targets(h, L, 0.05)
+        assert len(got) == L + 1
+        for g, p in zip(got, printed):
+            # two significant digits as printed (rounded, or truncated for delta_1 at L=1)
+            assert abs(g - p) <= 0.031 * p, (L, g, p)
+
+
+def test_delta_rule_structure():
+    h = [1.0 / (16 * 2 ** l) for l in range(5)]
+    d = oracle.accuracy_targets(h, 4, 0.05)
+    # interior levels shrink by 4 per level, the finest uses k_p instead of sqrt(k_p)
+    for l in range(3):
+        assert d[l] / d[l + 1] == pytest.approx(4.0, rel=1e-14)
+    assert d[4] == pytest.approx(0.05 * h[4] ** 2, rel=1e-15)
+    assert d[3] == pytest.approx(math.sqrt(0.05) * h[3] ** 2, rel=1e-15)
+    assert d == pytest.approx([8.735e-4, 2.184e-4, 5.459e-5, 1.365e-5, 7.629e-7], rel=1e-3)
+
+
+def test_cost_ratio_bound_matches_sec_4_5_example():
+    """q = 1/4, beta = 4, gamma = 2, m = 2 gives a reduction of at least 1.6 (Sec. 4.5)."""
+    r = oracle.cost_ratio_bound(0.25, 4.0, 2.0, 2)
+    assert 1.0 / r == pytest.approx(1.6, rel=1e-12)
+    # beta == gamma: the bound gives no asymptotic reduction
+    assert oracle.cost_ratio_bound(0.25, 4.0, 4.0, 2) == pytest.approx(1.0)
+
+
+# ------------------------------------------------------------- KL expansion
+
+@pytest.mark.parametrize("lam", [0.3, 0.1])
+def test_kl_roots_solve_eigen_equation(lam):
+    w = oracle.kl_roots(lam, 64)
+    for k, wk in enumerate(w, start=1):
+        assert (k - 1) * math.pi < wk < k * math.pi
+        g = (lam * lam * wk * wk - 1) * math.sin(wk) - 2 * lam * wk * math.cos(wk)
+        scale = (lam * lam * wk * wk + 1) + 2 * lam * wk
+        assert abs(g) <= 1e-13 * scale
+    # eigenvalues sum to the trace of the kernel (= 1) as the number of roots grows
+    w400 = oracle.kl_roots(lam, 400)
+    tr = oracle.kl_mu(lam, w400).sum()
+    assert 0.99 < tr < 1.0
+
+
+def test_kl_values_known():
+    w = oracle.kl_roots(0.3, 4)
+    assert w == pytest.approx([2.0422278, 4.4314146, 7.1551251, 10.0644353], abs=5e-7)
+    assert oracle.kl_mu(0.3, w) == pytest.approx([0.4362486, 0.2168124, 0.1069972, 0.0593099],
+                                                   abs=5e-7)
+
+
+@pytest.mark.parametrize("lam", [0.3, 0.1])
+def test_kl_against_nystrom(lam):
+    """Independent check: dense eigensolve of the kernel on a midpoint grid."""
+    P = 2000
+    x = (np.arange(P) + 0.5) / P
+    C = np.exp(-np.abs(x[:, None] - x[None, :]) / lam) / P
+    ev, V = np.linalg.eigh(C)
+    ev = ev[::-1][:6]
+    V = V[:, ::-1][:, :6] * math.sqrt(P)
+    w = oracle.kl_roots(lam, 6)
+    mu = oracle.kl_mu(lam, w)
+    assert mu == pytest.approx(ev, rel=2e-5)
+    for k in range(4):
+        phi = oracle.kl_phi1d(lam, w[k], x)
+        # orthonormal eigenfunctions: match the Nystrom vector up to sign
+        s = np.sign(np.dot(phi, V[:, k]))
+        assert np.max(np.abs(phi - s * V[:, k])) < 2e-3
+        assert np.mean(phi * phi) == pytest.approx(1.0, abs=1e-5)
+
+
+def test_kl_mirror_parity():
+    """phi_i(1 - x) = (-1)^(i+1) phi_i(x) for the normalised eigenfunctions."""
+    lam = 0.3
+    w = oracle.kl_roots(lam, 6)
+    x = np.linspace(0, 1, 17)
+    for i in range(6):
+        a = oracle.kl_phi1d(lam, w[i], x)
+        b = oracle.kl_phi1d(lam, w[i], 1 - x)
+        assert np.allclose(b, (-1) ** i * a, atol=1e-13)
+
+
+def test_kl_mode_order_and_tie_break():
+    lam = 0.3
+    mi, mj = oracle.kl_modes(lam, 16)
+    w = oracle.kl_roots(lam, 64)
+    mu = oracle.kl_mu(lam, w)
+    prods = mu[mi - 1] * mu[mj - 1]
+    assert np.all(np.diff(prods) <= 0)
+    assert (mi[0], mj[0]) == (1, 1)
+    # symmetric pairs: (i, j) precedes (j, i) when i < j
+    for k in range(15):
+        if prods[k] == prods[k + 1]:
+            assert (mi[k], mj[k]) < (mi[k + 1], mj[k + 1])
+    # the largest excluded product is no larger than the smallest included one
+    allp = np.sort(np.outer(mu, mu).ravel())[::-1]
+    assert allp[16] <= prods[-1]
+
+
+# ------------------------------------------------------------- discrete solve
+
+def test_sigma0_matches_closed_form():
+    """a == 1: the 5-point Laplacian; Q_h against the sine-series closed form."""
+    for row in _rows("laplace_sigma0.txt"):
+        n, q = int(row[0]), float(row[1])
+        if n > 128:
+            continue
+        Phi = oracle.kl_basis(n, 4, 0.0, 0.3)
+        got = oracle.solve_batch(n, Phi, np.zeros((1, 4)))[0]
+        assert abs(got - q) <= 1e-13 * q, (n, got, q)
+    assert oracle.solve_batch(4, oracle.kl_basis(4, 1, 0.0, 0.3), np.zeros((1, 1)))[0] == \
+        pytest.approx(59.0 / 2048.0, rel=1e-15)
+
+
+def test_sigma0_converges_to_continuous_value():
+    # 64/pi^6 sum over odd m, k of 1/(m^2 k^2 (m^2 + k^2))
+    odd = np.arange(1, 4001, 2, dtype=np.float64)
+    m2 = odd[:, None] ** 2
+    k2 = odd[None, :] ** 2
+    qc = 64 / math.pi ** 6 * np.sum(1.0 / (m2 * k2 * (m2 + k2)))
+    errs = []
+    for n in (16, 32, 64):
+        q = oracle.solve_batch(n, oracle.kl_basis(n, 1, 0.0, 0.3), np.zeros((1, 1)))[0]
+        errs.append(qc - q)
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.02)
+    assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.02)
+
+
+def _manufactured(n):
+    x = np.arange(n + 1) / n
+    X, Y = np.meshgrid(x, x)  # [iy, ix]
+    g = 0.5 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    a = np.exp(g)
+    u = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    ux = np.pi * np.cos(np.pi * X) * np.sin(np.pi * Y)
+    uy = np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y)
+    ax = a * np.pi * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    ay = -a * np.pi * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    f = a * 2 * np.pi ** 2 * u - ax * ux - ay * uy
+    return a.ravel(), f[1:n, 1:n].ravel(), u[1:n, 1:n].ravel()
+
+
+def test_manufactured_solution_second_order():
+    errs = []
+    for n in (16, 32, 64, 128):
+        a, f, uex = _manufactured(n)
+        _, u = oracle.solve_batch(n, None, None, a_nodes=a, rhs_nodal=f, want_u=True)
+        errs.append(np.max(np.abs(u[0] - uex)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.7 < r < 4.3 for r in ratios), ratios
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_band_solve_vs_dense(n):
+    K = 16
+    Phi = oracle.kl_basis(n, K, 2.0, 0.1)
+    xi = si.splitmix64_normals(7, 0, 0, 3, K)
+    Q, u = oracle.solve_batch(n, Phi, xi, want_u=True)
+    for s in range(3):
+        A = oracle.dense_matrix(n, Phi, xi[s])
+        assert np.allclose(A, A.T)
+        assert np.all(np.linalg.eigvalsh(A) > 0)
+        ref = np.linalg.solve(A, np.full((n - 1) ** 2, 1.0 / n ** 2))
+        assert np.max(np.abs(u[s] - ref)) <= 1e-14 * np.max(np.abs(ref))
+        assert Q[s] == pytest.approx(ref.sum() / n ** 2, rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_band_solve_vs_lapack_banded(n):
+    K = 64
+    Phi = oracle.kl_basis(n, K, 2.0, 0.1)
+    xi = si.splitmix64_normals(11, 1, 0, 2, K)
+    Q, u = oracle.solve_batch(n, Phi, xi, want_u=True)
+    m = n - 1
+    for s in range(2):
+        A = oracle.dense_matrix(n, Phi, xi[s])
+        ab = np.zeros((m + 1, m * m))
+        for d in range(m + 1):
+            ab[d, : m * m - d] = np.diagonal(A, -d)
+        c = sla.cholesky_banded(ab, lower=True)
+        ref = sla.cho_solve_banded((c, True), np.full(m * m, 1.0 / n ** 2))
+        assert np.max(np.abs(u[s] - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_energy_identity():
+    """With f = 1, b = h^2 1, so Q = b^T u = u^T A u = sum over edges a_e (du)^2."""
+    n, K = 32, 16
+    Phi = oracle.kl_basis(n, K, 1.0, 0.3)
+    xi = si.splitmix64_normals(3, 0, 0, 4, K)
+    Q, u = oracle.solve_batch(n, Phi, xi, want_u=True)
+    for s in range(4):
+        assert oracle.energy(n, Phi, xi[s], u[s]) == pytest.approx(Q[s], rel=1e-12)
+
+
+def test_mirror_invariance():
+    """Flipping xi_k of modes with even x-index mirrors the field x -> 1-x; Q is unchanged."""
+    n, K = 32, 64
+    Phi = oracle.kl_basis(n, K, 1.0, 0.3)
+    mi, mj = oracle.kl_modes(0.3, K)
+    xi = si.splitmix64_normals(5, 2, 0, 3, K)
+    flip_x = np.where(mi % 2 == 0, -1.0, 1.0)
+    flip_y = np.where(mj % 2 == 0, -1.0, 1.0)
+    q0 = oracle.solve_batch(n, Phi, xi)
+    assert np.allclose(oracle.solve_batch(n, Phi, xi * flip_x), q0, rtol=1e-13, atol=0)
+    assert np.allclose(oracle.solve_batch(n, Phi, xi * flip_y), q0, rtol=1e-13, atol=0)
+    # a sign error anywhere in the field would break the invariance
+    assert not np.allclose(oracle.solve_batch(n, Phi, -xi), q0, rtol=1e-6, atol=0)
+
+
+def test_relres_of_exact_solution_is_tiny():
+    n, K = 32, 16
+    Phi = oracle.kl_basis(n, K, 1.0, 0.3)
+    xi = si.splitmix64_normals(9, 0, 0, 3, K)
+    _, u = oracle.solve_batch(n, Phi, xi, want_u=True)
+    assert np.all(oracle.relres_batch(n, Phi, xi, u) < 1e-13)
+
+
+# ------------------------------------------------------------- adjoint
+
+def test_adjoint_vs_central_differences():
+    n, K = 16, 16
+    Phi = oracle.kl_basis(n, K, 2.0, 0.1)
+    xi = si.splitmix64_normals(13, 0, 0, 2, K)
+    g, gz, lam = oracle.grad_batch(n, Phi, xi, want_gz=True, want_lambda=True)
+    _, u = oracle.solve_batch(n, Phi, xi, want_u=True)
+    hfd = 1e-6
+    for s in range(2):
+        fd = np.zeros(K)
+        for k in range(K):
+            e = np.zeros(K)
+            e[k] = hfd
+            fd[k] = (oracle.solve_batch(n, Phi, xi[s] + e)[0] - oracle.solve_batch(n, Phi, xi[s] - e)[0]) / (2 * hfd)
+        assert np.linalg.norm(g[s] - fd) <= 1e-6 * np.linalg.norm(fd)
+        # w = b, so the adjoint state equals the solution, and raising a lowers Q
+        assert np.allclose(lam[s], u[s], rtol=1e-12, atol=1e-18)
+        assert np.all(gz[s] <= 1e-18)
+
+
+# ------------------------------------------------------------- Algorithm 2.1
+
+def test_ir_reference_reaches_delta_and_bounds_q():
+    n, K = 32, 64
+    Phi = oracle.kl_basis(n, K, 2.0, 0.1)
+    xi = si.splitmix64_normals(17, 1, 0, 16, K)
+    Qx, u = oracle.solve_batch(n, Phi, xi, want_u=True)
+    for delta in (1e-3, 1e-6, 1e-10):
+        Q, trips, rr, nf = oracle.ir_f32_batch(n, Phi, xi, delta, imax=10)
+        assert nf == 0
+        assert np.all(rr < delta)
+        # Q - Q~ = u^T r  =>  |dQ|/Q <= (||r||/||b||) ||u|| ||b|| / (b^T u)
+        nb = math.sqrt(u.shape[1]) / n ** 2
+        cos_bound = np.linalg.norm(u, axis=1) * nb / Qx
+        assert np.all(np.abs(Q - Qx) / Qx <= rr * cos_bound * (1 + 1e-9) + 1e-14)
+    # a tighter target needs at least as many corrections
+    _, t3, _, _ = oracle.ir_f32_batch(n, Phi, xi, 1e-3)
+    _, t10, _, _ = oracle.ir_f32_batch(n, Phi, xi, 1e-10)
+    assert np.all(t10 >= t3) and np.all(t10 >= 1)
+
+
+def test_ir_reference_imax_zero_and_unreachable():
+    n, K = 16, 16
+    Phi = oracle.kl_basis(n, K, 1.0, 0.3)
+    xi = si.splitmix64_normals(19, 0, 0, 4, K)
+    _, trips, rr, nf = oracle.ir_f32_batch(n, Phi, xi, 1e-12, imax=0)
+    assert np.all(trips == 0) and nf == 4
+    _, trips, rr, nf = oracle.ir_f32_batch(n, Phi, xi, 1e-30, imax=3)
+    assert np.all(trips == 3) and nf == 4
+
+
+# ------------------------------------------------------------- Algorithm 4.1
+
+def test_adaptive_mpml_on_synthetic_levels():
+    """Algorithm 4.1 on synthetic Y with known means/variances (bias 4^-l, var 16^-l)."""
+    rng = np.random.default_rng(0)
+    c_mean, c_var = 0.01, 1e-4
+
+    def sample_fn(l, first, count, dfine, dcoarse):
+        mean = 1.0 if l == 0 else c_mean * 4.0 ** (-l)
+        sd = math.sqrt(c_var * 16.0 ** (-l))
+        return rng.normal(mean, sd, size=count)
+
+    tol = 2e-4
+    res = oracle.adaptive_mpml(sample_fn, 16, tol, L_max=6, n_init=200)
+    bias_c = 3 / math.sqrt(2) * tol
+    L = res["L"]
+    # the chosen L is the first level whose mean passes the bias test
+    assert c_mean * 4.0 ** (-L) <= bias_c * 1.5
+    assert c_mean * 4.0 ** (-(L - 1)) > bias_c * 0.5
+    # the final sample counts satisfy the variance constraint of the stop test
+    assert sum(res["s2"][l] / res["N"][l] for l in range(L + 1)) <= tol ** 2 / 2 * 1.0001
+    # N_l follows the optimal allocation: N_l C_l / sqrt(V_l C_l) is level-independent
+    C = [oracle.level_cost(16, l) for l in range(L + 1)]
+    # (levels still at their initial N_init are floored, not optimised)
+    ratio = [res["N"][l] / math.sqrt(res["s2"][l] / C[l]) for l in range(L + 1)
+             if res["N"][l] > 200]
+    assert len(ratio) >= 2 and max(ratio) / min(ratio) < 1.2
+    assert res["bias_ok"] and res["var_ok"]
+
+
+def test_adaptive_mpml_passes_deltas():
+    seen = []
+
+    def sample_fn(l, first, count, dfine, dcoarse):
+        seen.append((l, dfine, dcoarse))
+        return np.full(count, 1.0 if l == 0 else 1e-9)
+
+    oracle.adaptive_mpml(sample_fn, 8, 1e-2, L_max=3, n_init=10)
+    h = [1.0 / (8 * 2 ** l) for l in range(4)]
+    for l, df, dc in seen:
+        assert df > 0
+        if l > 0:
+            assert dc == pytest.approx(math.sqrt(0.05) * h[l - 1] ** 2)
