@@ -1,0 +1,210 @@
+/*
+ * mlmc.h -- C ABI of the MI355X (gfx950) library for the batched per-level
+ * sample solve of the inexact (mixed-precision) multilevel Monte Carlo
+ * method for -div(a grad u) = f on (0,1)^2, u = 0 on the boundary, with a
+ * lognormal coefficient a = exp(Z).
+ *
+ * Discrete problem (the model PDE of Sec. 5.1 with the quantity of interest
+ * Q = integral of u over D; vertex-centred 5-point finite volumes):
+ *   level l has n_l = n0 * m^l cells per side, h_l = 1/n_l; the unknowns are
+ *   the (n_l - 1)^2 interior nodes, ordered P = (iy-1)(n_l-1) + (ix-1);
+ *   the coefficient is nodal, a_p = exp(Z_p), Z = xi . Phi_l^T with Phi_l the
+ *   separable exponential-covariance KL basis on the (n_l+1)^2 nodes; the
+ *   edge coefficient is the harmonic mean of its end nodes; b = h^2 f;
+ *   Q = h^2 * sum_P u_P.
+ *
+ * Conventions for every entry point:
+ *   - All *_dev pointers are device pointers owned by the caller, contiguous
+ *     and row-major, at least 8-byte aligned (the workspace: 256-byte aligned).
+ *     The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it unless stated otherwise.
+ *   - Return codes: MLMC_OK (0); MLMC_ENOCONV (1): the call completed but at
+ *     least one sample did not reach its target (see its status bits);
+ *     negative codes mean the call failed and outputs are undefined.  The
+ *     text of the last error of a context is returned by mlmc_last_error.
+ *   - One context per host thread; calls on one context are not re-entrant.
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLMC_OK 0
+#define MLMC_ENOCONV 1
+#define MLMC_EINVAL (-1)  /* bad argument: null/misaligned pointer, level out of range, NaN */
+#define MLMC_ENOMEM (-2)  /* workspace smaller than mlmc_workspace_bytes */
+#define MLMC_EHIP (-3)    /* HIP runtime error (text via mlmc_last_error) */
+#define MLMC_ENOTIMPL (-4)
+
+/* Per-sample status bits (uint8). */
+#define MLMC_ST_CONVERGED 1u  /* relative residual < target */
+#define MLMC_ST_PROMOTED 2u   /* re-factorised in a higher precision */
+#define MLMC_ST_NONFINITE 4u  /* a non-finite value was met */
+#define MLMC_ST_IMAX 8u       /* iteration limit reached without convergence */
+
+typedef struct mlmc_ctx mlmc_ctx;
+
+/* Storage/arithmetic precision u_f of the factor (Algorithm 2.1, Sec. 2.3). */
+typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3 } mlmc_dtype;
+
+/* Linear solver of one sample:
+ *   MLMC_DIRECT    FP64 factorisation and solve, no refinement loop.
+ *   MLMC_DIRECT_IR factorisation in factor_dtype, then Algorithm 2.1:
+ *                  FP64 residual, correction solve with the stored factor
+ *                  (FP32 arithmetic), FP64 update, stop when
+ *                  ||b - A x||_2 / ||b||_2 < eps (strict), at most
+ *                  ir_max_iter corrections (Sec. 2.3).
+ *   MLMC_MINRES    Jacobi-scaled MINRES in FP64 (Sec. 2.2) stopped on the
+ *                  unscaled relative residual < eps. */
+typedef enum { MLMC_DIRECT = 0, MLMC_DIRECT_IR = 1, MLMC_MINRES = 2 } mlmc_solver;
+
+typedef struct {
+    int32_t n0;              /* cells per side on level 0 (power of two, >= 4) */
+    int32_t m;               /* refinement factor; only 2 is supported */
+    int32_t L_max;           /* finest level; n0 * 2^L_max <= 256 */
+    int32_t K;               /* number of KL modes, 1..512 */
+    double sigma2;           /* variance of Z */
+    double corr_len;         /* correlation length lambda of exp(-|x-y|/lambda) */
+    double f;                /* constant right-hand side */
+    double k_p;              /* accuracy constant of Sec. 4.3 (0.05) */
+    double alpha, beta, gamma; /* MLMC rates (2, 4, cost exponent) */
+    int32_t ir_max_iter;     /* Algorithm 2.1 i_max (10) */
+    int32_t minres_max_iter; /* MINRES iteration cap (e.g. 5000) */
+    uint64_t seed;           /* seed of the counter-based xi generator */
+} mlmc_config;
+
+typedef struct {
+    mlmc_dtype factor_dtype; /* u_f; ignored by MLMC_DIRECT (always FP64) */
+    mlmc_solver solver;
+    double eps_fine;         /* target relative residual of the level-l solve */
+    double eps_coarse;       /* target of the coarse partner (level l-1) */
+    int32_t promote;         /* 1: re-solve non-converged samples in the next precision */
+} mlmc_level_opts;
+
+typedef struct {
+    int64_t n;                       /* samples in this call */
+    double sum_y, sum_y2;            /* sums of Y_l and Y_l^2 (FP64, fixed order) */
+    double sum_qf, sum_qc;           /* sums of Q_l and Q_{l-1} */
+    int64_t n_promoted, n_noconv;    /* samples re-solved / not converged */
+    double mean_iters;               /* mean corrections (IR) or iterations (MINRES), fine grid */
+    double gpu_ms;                   /* device time of the call (event-timed) */
+} mlmc_level_stats;
+
+typedef struct {
+    double estimate;   /* Q-hat = sum_l Y-hat_l (eq. of the MLMC estimator, Sec. 4.1) */
+    double var_est;    /* sum_l s_l^2 / N_l */
+    int32_t L;         /* finest level used */
+    int32_t converged; /* bias and variance tests both met */
+    int64_t N[16];     /* samples per level */
+    double Yhat[16], s2[16], C[16], eps[16];
+    double wall_s;     /* host wall time of the call */
+    double gpu_ms;     /* sum of device times of the level calls */
+} mlmc_result;
+
+/* Create a context: solves the KL eigen-equation on the host, builds Phi_l
+ * for every level 0..L_max in FP64 and uploads it (the only host->device
+ * traffic of the set-up).  No sample work.  Returns MLMC_EINVAL for an
+ * unsupported configuration. */
+int mlmc_create(const mlmc_config *cfg, mlmc_ctx **out);
+int mlmc_destroy(mlmc_ctx *ctx);
+const char *mlmc_last_error(const mlmc_ctx *ctx);
+
+/* Cells per side of level `level`, or -1. */
+int32_t mlmc_level_cells(const mlmc_ctx *ctx, int32_t level);
+
+/* delta_0..delta_L of the accuracy rule of Sec. 4.5 (delta_l = sqrt(k_p) h_l^2
+ * for l < L, delta_L = k_p h_L^2) into eps_out[0..L] (host memory). */
+int mlmc_accuracy_targets(const mlmc_ctx *ctx, int32_t L, double *eps_out);
+
+/* Copy Phi_level, stored transposed as [K][(n+1)^2] FP64 (node
+ * p = iy*(n+1)+ix), into the caller's device buffer phit_dev (async on
+ * stream).  Phi[p,k] = sigma sqrt(mu_i mu_j) phi_i(x_p) phi_j(y_p) for the
+ * k-th selected mode (i, j) in the order of decreasing mu_i mu_j, ties by
+ * (i, j). */
+int mlmc_get_kl_basis(const mlmc_ctx *ctx, int32_t level, double *phit_dev, void *stream);
+
+/* Bytes of device workspace that mlmc_sample_level (level >= 0), or
+ * mlmc_solve / mlmc_grad on grid `level`, need for n_samples samples with
+ * these options.  The same workspace serves a following mlmc_grad. */
+size_t mlmc_workspace_bytes(const mlmc_ctx *ctx, int32_t level, int64_t n_samples,
+                            const mlmc_level_opts *opts);
+
+/* xi[n x K] (FP64) for samples first_sample .. first_sample+n-1 of `level`,
+ * from the counter-based generator: SplitMix64 output i for seed s is
+ * mix(s + (i+1) 0x9E3779B97F4A7C15); coefficient k of sample j uses pair
+ * p = k/2 and outputs i_w = ((((level<<32)|j)<<8|p)<<1)|w, w = 0,1;
+ * u1 = ((o0>>11)+1) 2^-53, u2 = (o1>>11) 2^-53, r = sqrt(-2 ln u1),
+ * xi_2p = r cos(2 pi u2), xi_2p+1 = r sin(2 pi u2).  Requires K <= 512,
+ * sample index < 2^32. */
+int mlmc_fill_xi(const mlmc_ctx *ctx, int32_t level, int64_t first_sample, int64_t n,
+                 double *xi_dev, void *stream);
+
+/* Batched solve of n samples on the grid of level `level` (no pairing):
+ * field GEMM, assembly, factorisation, solve to opts->eps_fine with
+ * opts->solver, and Q.  Outputs: q_dev[n]; u_dev[n x (n_l-1)^2] (optional,
+ * FP64 solution); status_dev[n] (optional); iters_dev[n] (optional).
+ * The workspace keeps the factor, scaling, coefficient and solution for a
+ * following mlmc_grad on the same samples. */
+int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+               const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes, double *q_dev,
+               double *u_dev, uint8_t *status_dev, int32_t *iters_dev, void *stream);
+
+/* One MLMC level (eq. of the MLMC estimator and Algorithm 4.1, Secs. 4.1
+ * and 4.3): for each xi row s, Q_l(s) on grid l solved to eps_fine and, for
+ * l >= 1, Q_{l-1}(s) on grid l-1 from the same xi row solved to eps_coarse;
+ * Y_l = Q_l - Q_{l-1} (Y_0 = Q_0).  q_coarse_dev may be NULL for l = 0.
+ * status_dev (optional) holds the fine status in bits 0-3 and the coarse
+ * status in bits 4-7.  If stats_host is not NULL the call synchronises the
+ * stream and fills it (level sums in FP64, fixed summation order). */
+int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                      const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes,
+                      double *q_fine_dev, double *q_coarse_dev, double *y_dev,
+                      uint8_t *status_dev, mlmc_level_stats *stats_host, void *stream);
+
+/* Algorithm 4.1 (adaptive MPML, Sec. 4.3) driven on the GPU: L starts at 1,
+ * N_0 = N_1 = n_init; each round recomputes delta_l (Sec. 4.5), tops every
+ * level up to N_l with fresh counter-based xi, updates
+ * N_l = ceil(sqrt(V_l/C_l) (2/TOL^2) sum_k sqrt(V_k C_k)) with V_l = s_l^2
+ * and the deterministic cost C_l = (n_l-1)^4 + (n_{l-1}-1)^4, adds a level
+ * while |Y-hat_L| > (m^alpha - 1)/sqrt(2) TOL, and stops when that test and
+ * sum_l s_l^2/N_l <= TOL^2/2 hold and no level needs more samples.
+ * dtype_per_level[0..L_max] selects u_f per level (ignored for
+ * MLMC_DIRECT/MLMC_MINRES).  mixed = 0 runs standard MLMC: every solve
+ * uses eps = 0 targets replaced by the FP64 direct solve.  Allocates its own
+ * device memory; synchronises once per round. */
+int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
+                  mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream);
+
+/* Adjoint gradient dQ/dxi on grid `level` for the n samples of the
+ * preceding mlmc_solve on the same workspace (which must have used
+ * MLMC_DIRECT or MLMC_DIRECT_IR): solves A lambda = h^2 1 with the stored
+ * factor and FP64 refinement to eps_adjoint, forms
+ * dQ/dZ_e = -sum_{edges (e,o)} (lambda_e - lambda_o)(u_e - u_o)
+ *          2 a_o^2 a_e / (a_e + a_o)^2
+ * and grad_xi[s,k] = grad_q[s] * sum_e dQ/dZ_e Phi[e,k].
+ * grad_q_dev[n] may be NULL (taken as 1). */
+int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+              const double *grad_q_dev, double eps_adjoint, void *ws_dev, size_t ws_bytes,
+              double *grad_xi_dev, void *stream);
+
+/* Kernel timing for measurement.  While enabled, the library brackets each
+ * launch of the field, assembly, factor, solve and residual kernels with HIP
+ * events on the caller's stream and records (kernel kind, grid n, samples).
+ * mlmc_profile_read synchronises, and for kind (0 field, 1 assembly,
+ * 2 factor, 3 solve, 4 residual) and grid n returns the summed device time,
+ * the number of launches and the summed samples over all recorded launches,
+ * then keeps the records (reset with mlmc_profile(ctx, 1) again). */
+int mlmc_profile(mlmc_ctx *ctx, int32_t enable);
+int mlmc_profile_read(mlmc_ctx *ctx, int32_t kind, int32_t n, double *total_ms, int64_t *launches,
+                      int64_t *samples);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLMC_H */

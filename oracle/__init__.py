@@ -69,6 +69,7 @@ def _load():
         lib.oracle_energy.argtypes = [c_int, c_int, D, D, D]
         lib.oracle_energy.restype = c_double
         lib.oracle_dense_matrix.argtypes = [c_int, c_int, D, D, D]
+        lib.oracle_num_threads.restype = c_int
         _lib = lib
     return _lib
 
@@ -85,6 +86,10 @@ def _pi(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads():
+    return _load().oracle_num_threads()
 
 
 # ---------------------------------------------------------------- KL field

@@ -41,6 +41,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_PI 3.14159265358979323846
 
@@ -548,4 +551,14 @@ int oracle_dense_matrix(int n, int K, const double *Phi, const double *xi, doubl
         }
     free(a); free(aE); free(aN); free(Ab); free(b);
     return 0;
+}
+
+/* Threads an OpenMP parallel region of this library uses. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

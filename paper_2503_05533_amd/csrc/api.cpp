@@ -1,0 +1,758 @@
+// Host side of libmlmc: context, KL set-up, workspace layout, the per-grid
+// solve driver (factorisation, Algorithm 2.1 refinement, promotion, MINRES),
+// the MLMC level pairing, the Algorithm 4.1 driver and the adjoint gradient.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mlmc.h"
+#include "kernels.h"
+
+using namespace mlmc;
+
+struct mlmc_ctx {
+    mlmc_config cfg;
+    int device = 0;
+    std::vector<double *> phit;  // per level: [K][(n+1)^2] FP64 on the device
+    std::string err;
+    int *d_counter = nullptr;    // device scratch: active-sample counters
+    double *d_sums = nullptr;    // device scratch: level sums (16 doubles)
+    int *h_counter = nullptr;    // pinned host mirror
+    double *h_sums = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // kernel timing records (mlmc_profile)
+    struct prof_rec { int kind, n; int64_t samples; hipEvent_t a, b; };
+    bool prof_on = false;
+    std::vector<prof_rec> prof;
+    std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+int fail(mlmc_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, MLMC_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                               \
+    } while (0)
+
+#define PROF(kind, n_, cnt_, expr)                                                         \
+    do {                                                                                   \
+        prof_scope ps_(ctx, kind, n_, cnt_, st);                                           \
+        HIPCHK(expr);                                                                      \
+    } while (0)
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : 2); }
+inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------- kernel timing
+
+hipEvent_t pool_event(mlmc_ctx *c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket one launch with events when profiling is on.
+struct prof_scope {
+    mlmc_ctx *c;
+    hipStream_t st;
+    int kind, n;
+    int64_t samples;
+    hipEvent_t a = nullptr;
+    prof_scope(mlmc_ctx *c_, int kind_, int n_, int64_t s_, hipStream_t st_)
+        : c(c_), st(st_), kind(kind_), n(n_), samples(s_)
+    {
+        if (c->prof_on && (a = pool_event(c))) (void)hipEventRecord(a, st);
+    }
+    ~prof_scope()
+    {
+        if (!a) return;
+        hipEvent_t b = pool_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        c->prof.push_back({kind, n, samples, a, b});
+    }
+};
+
+// ---------------------------------------------------------------- KL set-up
+// Separable exponential covariance sigma^2 exp(-|x1-y1|/lam) exp(-|x2-y2|/lam).
+// 1D eigenvalues mu = 2 lam / (1 + lam^2 w^2) where w solves
+// (lam^2 w^2 - 1) sin w = 2 lam w cos w, one root per ((k-1) pi, k pi);
+// eigenfunctions (sin w x + lam w cos w x) / ||.||.
+
+double kl_eq(double w, double lam) { return (lam * lam * w * w - 1.0) * std::sin(w) - 2.0 * lam * w * std::cos(w); }
+
+// Illinois (modified regula falsi) on a sign-changing bracket.
+double kl_root(int k, double lam)
+{
+    const double pi = 3.14159265358979323846;
+    double lo = (k - 1) * pi, hi = k * pi;
+    double flo = k == 1 ? -1.0 : kl_eq(lo, lam), fhi = kl_eq(hi, lam);
+    if (k == 1) lo = 0.0;
+    int side = 0;
+    for (int it = 0; it < 300 && hi - lo > 4e-16 * hi; ++it) {
+        double w = (lo * fhi - hi * flo) / (fhi - flo);
+        if (!(w > lo && w < hi)) w = 0.5 * (lo + hi);
+        const double fw = kl_eq(w, lam);
+        if (fw == 0.0) return w;
+        if ((fw < 0) == (flo < 0)) {
+            lo = w;
+            flo = fw;
+            if (side == -1) fhi *= 0.5;
+            side = -1;
+        } else {
+            hi = w;
+            fhi = fw;
+            if (side == 1) flo *= 0.5;
+            side = 1;
+        }
+    }
+    return 0.5 * (lo + hi);
+}
+
+struct kl_mode { double prod; int i, j; };
+
+int build_phit(mlmc_ctx *ctx, std::vector<std::vector<double>> &out)
+{
+    const mlmc_config &c = ctx->cfg;
+    const double lam = c.corr_len;
+    int R = 64;
+    std::vector<double> w, mu, nu;
+    std::vector<kl_mode> sel;
+    for (;;) {
+        w.resize(R);
+        mu.resize(R);
+        nu.resize(R);
+        for (int k = 0; k < R; ++k) {
+            w[k] = kl_root(k + 1, lam);
+            mu[k] = 2.0 * lam / (1.0 + lam * lam * w[k] * w[k]);
+            const double s2 = std::sin(2.0 * w[k]), c2 = std::cos(2.0 * w[k]);
+            nu[k] = 0.5 - s2 / (4.0 * w[k]) + lam * lam * w[k] * w[k] * (0.5 + s2 / (4.0 * w[k])) +
+                    0.5 * lam * (1.0 - c2);
+        }
+        std::vector<kl_mode> all;
+        all.reserve((size_t)R * R);
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < R; ++j) all.push_back({mu[i] * mu[j], i, j});
+        std::sort(all.begin(), all.end(), [](const kl_mode &a, const kl_mode &b) {
+            if (a.prod != b.prod) return a.prod > b.prod;
+            if (a.i != b.i) return a.i < b.i;
+            return a.j < b.j;
+        });
+        sel.assign(all.begin(), all.begin() + c.K);
+        // every pair touching an index >= R has product <= mu_0 mu_{R-1}
+        if (mu[0] * mu[R - 1] < sel.back().prod) break;
+        R *= 2;
+        if (R > 4096) return fail(ctx, MLMC_EINVAL, "KL: too many modes requested");
+    }
+    const double sigma = std::sqrt(c.sigma2);
+    out.assign(c.L_max + 1, {});
+    for (int l = 0; l <= c.L_max; ++l) {
+        const int n = c.n0 << l, P = (n + 1) * (n + 1);
+        std::vector<double> f1((size_t)R * (n + 1));  // phi_r(t/n)
+        for (int r = 0; r < R; ++r) {
+            const double inv = 1.0 / std::sqrt(nu[r]);
+            for (int t = 0; t <= n; ++t) {
+                const double x = (double)t / n;
+                f1[(size_t)r * (n + 1) + t] = (std::sin(w[r] * x) + lam * w[r] * std::cos(w[r] * x)) * inv;
+            }
+        }
+        std::vector<double> &ph = out[l];
+        ph.assign((size_t)c.K * P, 0.0);
+        for (int k = 0; k < c.K; ++k) {
+            const int i = sel[k].i, j = sel[k].j;
+            const double amp = sigma * std::sqrt(mu[i] * mu[j]);
+            for (int iy = 0; iy <= n; ++iy)
+                for (int ix = 0; ix <= n; ++ix)
+                    ph[(size_t)k * P + iy * (n + 1) + ix] =
+                        amp * f1[(size_t)i * (n + 1) + ix] * f1[(size_t)j * (n + 1) + iy];
+        }
+    }
+    return MLMC_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct grid_layout {
+    int n, m, M;
+    int64_t S;
+    size_t vec;  // padded vector length per sample
+    size_t off_a, off_sc, off_gam, off_beta, off_x, off_r, off_z, off_lam, off_gz;
+    size_t off_factor, off_promo, off_state, off_relres, off_q, off_iters, off_idx;
+    size_t off_mr;  // MINRES vectors (5 per sample)
+    int64_t promo_slots;
+    size_t bytes;
+};
+
+grid_layout make_layout(int n, int64_t S, const mlmc_level_opts &o)
+{
+    grid_layout L{};
+    L.n = n;
+    L.m = n - 1;
+    L.M = n;
+    L.S = S;
+    L.vec = (size_t)L.m * L.M;
+    const size_t vb = align256(S * L.vec * 8);
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o2 = off; off += align256(b); return o2; };
+    L.off_a = take(S * (size_t)(n + 1) * (n + 1) * 8);
+    L.off_gz = take(S * (size_t)(n + 1) * (n + 1) * 8);
+    L.off_sc = take(vb);
+    L.off_gam = take(vb);
+    L.off_beta = take(vb);
+    L.off_x = take(vb);
+    L.off_r = take(vb);
+    L.off_z = take(vb);
+    L.off_lam = take(vb);
+    const bool direct = o.solver != MLMC_MINRES;
+    const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
+    L.off_factor = take(direct ? S * factor_entries_per_sample(n) * dtype_bytes(dt) : 0);
+    L.promo_slots = (direct && dt != MLMC_F64 && o.promote) ? std::max<int64_t>(1, (S + 15) / 16) : 0;
+    L.off_promo = take(L.promo_slots * factor_entries_per_sample(n) * 8);
+    L.off_mr = take(o.solver == MLMC_MINRES ? 5 * S * L.vec * 8 : 0);
+    L.off_state = take(S * 4);
+    L.off_relres = take(S * 8);
+    L.off_q = take(S * 8);
+    L.off_iters = take(S * 4);
+    L.off_idx = take(S * 4);
+    L.bytes = off;
+    return L;
+}
+
+struct level_layout {
+    grid_layout fine, coarse;
+    size_t off_fine, off_coarse, off_qf, off_qc, off_y, bytes;
+};
+
+level_layout make_level_layout(const mlmc_config &c, int level, int64_t S, const mlmc_level_opts &o)
+{
+    level_layout L{};
+    const int nf = c.n0 << level;
+    L.fine = make_layout(nf, S, o);
+    size_t off = 0;
+    L.off_fine = off;
+    off += align256(L.fine.bytes);
+    if (level > 0) {
+        L.coarse = make_layout(nf / 2, S, o);
+        L.off_coarse = off;
+        off += align256(L.coarse.bytes);
+    }
+    L.off_qf = off;
+    off += align256(S * 8);
+    L.off_qc = off;
+    off += align256(S * 8);
+    L.off_y = off;
+    off += align256(S * 8);
+    L.bytes = off;
+    return L;
+}
+
+template <typename T> T *at(void *base, size_t off) { return (T *)((char *)base + off); }
+
+int check_level(mlmc_ctx *ctx, int level)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (level < 0 || level > ctx->cfg.L_max) return fail(ctx, MLMC_EINVAL, "level %d out of range", level);
+    return MLMC_OK;
+}
+
+int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o)
+{
+    if (!o) return fail(ctx, MLMC_EINVAL, "opts is NULL");
+    if (o->factor_dtype < MLMC_F64 || o->factor_dtype > MLMC_F16)
+        return fail(ctx, MLMC_EINVAL, "bad factor dtype");
+    if (o->solver < MLMC_DIRECT || o->solver > MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "bad solver");
+    if (!(o->eps_fine >= 0.0) || !(o->eps_coarse >= 0.0)) return fail(ctx, MLMC_EINVAL, "bad eps");
+    return MLMC_OK;
+}
+
+// Refinement loop of Algorithm 2.1 for the samples in idx (or all when idx is
+// NULL): residual -> stop test -> correction solve -> update.  Stops early
+// when no sample is active.
+int ir_loop(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dtype, const void *factor,
+            int64_t slot_base, const int *idx, int nb, double eps, double *q, int32_t *iters,
+            hipStream_t st)
+{
+    const int imax = ctx->cfg.ir_max_iter;
+    for (int trip = 0; trip <= imax; ++trip) {
+        HIPCHK(hipMemsetAsync(ctx->d_counter, 0, sizeof(int), st));
+        PROF(4, L.n, nb, launch_residual(L.n, nb, ctx->cfg.f, at<double>(ws, L.off_a), at<double>(ws, L.off_x),
+                               at<double>(ws, L.off_r), eps, trip, imax, 0, idx,
+                               at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), q, iters,
+                               ctx->d_counter, st));
+        if (trip == imax) break;
+        HIPCHK(hipMemcpyAsync(ctx->h_counter, ctx->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (*ctx->h_counter == 0) break;
+        PROF(3, L.n, nb, launch_solve(dtype, L.n, nb, at<double>(ws, L.off_sc), at<double>(ws, L.off_beta),
+                            factor, at<double>(ws, L.off_r), 0.0, at<double>(ws, L.off_x), 1,
+                            at<double>(ws, L.off_z), idx, slot_base, at<uint32_t>(ws, L.off_state),
+                            st));
+    }
+    return MLMC_OK;
+}
+
+int minres_solve(mlmc_ctx *ctx, const grid_layout &L, void *ws, double eps, hipStream_t st);
+
+// Solve one batch on one grid.  q (S doubles, device) receives Q.
+int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
+               const mlmc_level_opts &o, double eps, void *ws, double *q, int32_t *iters,
+               hipStream_t st)
+{
+    const int n = L.n, S = (int)L.S, K = ctx->cfg.K, P = (n + 1) * (n + 1);
+    if (S == 0) return MLMC_OK;
+    double *a = at<double>(ws, L.off_a);
+    PROF(0, n, S, launch_field(S, K, P, xi, ctx->phit[level], a, st));
+    PROF(1, n, S, launch_coeffs(n, S, a, at<double>(ws, L.off_sc), at<double>(ws, L.off_gam),
+                         at<double>(ws, L.off_beta), st));
+    HIPCHK(launch_init_state(S, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), st));
+    if (o.solver == MLMC_MINRES) {
+        int rc = minres_solve(ctx, L, ws, eps, st);
+        if (rc) return rc;
+        PROF(4, n, S, launch_residual(n, S, ctx->cfg.f, a, at<double>(ws, L.off_x), nullptr, eps, 0, 0, 0,
+                               nullptr, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres),
+                               q, nullptr, nullptr, st));
+        return MLMC_OK;
+    }
+    const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
+    void *factor = at<void>(ws, L.off_factor);
+    PROF(2, n, S, launch_factor(dt, n, S, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam), factor,
+                         nullptr, 0, at<uint32_t>(ws, L.off_state), st));
+    PROF(3, n, S, launch_solve(dt, n, S, at<double>(ws, L.off_sc), at<double>(ws, L.off_beta), factor,
+                        nullptr, (1.0 / n) * (1.0 / n) * ctx->cfg.f, at<double>(ws, L.off_x), 0,
+                        at<double>(ws, L.off_z), nullptr, 0, nullptr, st));
+    if (o.solver == MLMC_DIRECT) {
+        PROF(4, n, S, launch_residual(n, S, ctx->cfg.f, a, at<double>(ws, L.off_x), nullptr, eps, 0, 0, 1,
+                               nullptr, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres),
+                               q, iters, nullptr, st));
+        return MLMC_OK;
+    }
+    int rc = ir_loop(ctx, L, ws, dt, factor, 0, nullptr, S, eps, q, iters, st);
+    if (rc) return rc;
+    if (L.promo_slots > 0) {
+        // samples that did not converge are re-solved with an FP64 factor
+        int *idx = at<int>(ws, L.off_idx);
+        HIPCHK(hipMemsetAsync(ctx->d_counter + 1, 0, sizeof(int), st));
+        HIPCHK(launch_collect(S, at<uint32_t>(ws, L.off_state), idx, ctx->d_counter + 1, st));
+        HIPCHK(hipMemcpyAsync(ctx->h_counter + 1, ctx->d_counter + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int np = ctx->h_counter[1];
+        void *pf = at<void>(ws, L.off_promo);
+        for (int p0 = 0; p0 < np; p0 += (int)L.promo_slots) {
+            const int nb = std::min<int>((int)L.promo_slots, np - p0);
+            const int *sub = idx + p0;
+            HIPCHK(launch_reset_subset(nb, sub, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), st));
+            PROF(2, n, nb, launch_factor(MLMC_F64, n, nb, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
+                                 pf, sub, 0, at<uint32_t>(ws, L.off_state), st));
+            PROF(3, n, nb, launch_solve(MLMC_F64, n, nb, at<double>(ws, L.off_sc), at<double>(ws, L.off_beta), pf,
+                                nullptr, (1.0 / n) * (1.0 / n) * ctx->cfg.f, at<double>(ws, L.off_x), 0,
+                                at<double>(ws, L.off_z), sub, 0, nullptr, st));
+            rc = ir_loop(ctx, L, ws, MLMC_F64, pf, 0, sub, nb, eps, q, iters, st);
+            if (rc) return rc;
+        }
+    }
+    return MLMC_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+int mlmc_create(const mlmc_config *cfg, mlmc_ctx **out)
+{
+    if (!cfg || !out) return MLMC_EINVAL;
+    *out = nullptr;
+    const mlmc_config &c = *cfg;
+    if (c.m != 2 || !is_pow2(c.n0) || c.n0 < 4 || c.L_max < 0 || (c.n0 << c.L_max) > 256 ||
+        c.K < 1 || c.K > 512 || !(c.sigma2 >= 0.0) || !(c.corr_len > 0.0) || !std::isfinite(c.f) ||
+        !(c.k_p > 0.0 && c.k_p < 1.0) || c.ir_max_iter < 0 || c.L_max > 15)
+        return MLMC_EINVAL;
+    mlmc_ctx *ctx = new mlmc_ctx();
+    ctx->cfg = c;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return MLMC_EHIP;
+    }
+    std::vector<std::vector<double>> ph;
+    int rc = build_phit(ctx, ph);
+    if (rc) {
+        delete ctx;
+        return rc;
+    }
+    ctx->phit.assign(c.L_max + 1, nullptr);
+    for (int l = 0; l <= c.L_max; ++l) {
+        if (hipMalloc(&ctx->phit[l], ph[l].size() * 8) != hipSuccess ||
+            hipMemcpy(ctx->phit[l], ph[l].data(), ph[l].size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            mlmc_destroy(ctx);
+            return MLMC_EHIP;
+        }
+    }
+    if (hipMalloc(&ctx->d_counter, 64) != hipSuccess || hipMalloc(&ctx->d_sums, 16 * 8) != hipSuccess ||
+        hipHostMalloc(&ctx->h_counter, 64, 0) != hipSuccess ||
+        hipHostMalloc(&ctx->h_sums, 16 * 8, 0) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
+        hipEventCreate(&ctx->ev1) != hipSuccess) {
+        mlmc_destroy(ctx);
+        return MLMC_EHIP;
+    }
+    *out = ctx;
+    return MLMC_OK;
+}
+
+int mlmc_destroy(mlmc_ctx *ctx)
+{
+    if (!ctx) return MLMC_EINVAL;
+    for (double *p : ctx->phit)
+        if (p) (void)hipFree(p);
+    if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    if (ctx->d_sums) (void)hipFree(ctx->d_sums);
+    if (ctx->h_counter) (void)hipHostFree(ctx->h_counter);
+    if (ctx->h_sums) (void)hipHostFree(ctx->h_sums);
+    for (auto &r : ctx->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return MLMC_OK;
+}
+
+const char *mlmc_last_error(const mlmc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t mlmc_level_cells(const mlmc_ctx *ctx, int32_t level)
+{
+    if (!ctx || level < 0 || level > ctx->cfg.L_max) return -1;
+    return ctx->cfg.n0 << level;
+}
+
+int mlmc_accuracy_targets(const mlmc_ctx *ctx, int32_t L, double *eps_out)
+{
+    if (!ctx || !eps_out || L < 0 || L > 15) return MLMC_EINVAL;
+    for (int l = 0; l <= L; ++l) {
+        const double h = 1.0 / ((double)ctx->cfg.n0 * std::pow(2.0, l));
+        eps_out[l] = (l < L ? std::sqrt(ctx->cfg.k_p) : ctx->cfg.k_p) * h * h;
+    }
+    return MLMC_OK;
+}
+
+int mlmc_get_kl_basis(const mlmc_ctx *cctx, int32_t level, double *phit_dev, void *stream)
+{
+    mlmc_ctx *ctx = const_cast<mlmc_ctx *>(cctx);
+    if (!ctx || level < 0 || level > ctx->cfg.L_max || !phit_dev)
+        return fail(ctx, MLMC_EINVAL, "get_kl_basis: bad arguments");
+    const int n = ctx->cfg.n0 << level;
+    const size_t bytes = (size_t)ctx->cfg.K * (n + 1) * (n + 1) * 8;
+    HIPCHK(hipMemcpyAsync(phit_dev, ctx->phit[level], bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return MLMC_OK;
+}
+
+size_t mlmc_workspace_bytes(const mlmc_ctx *ctx, int32_t level, int64_t n_samples,
+                            const mlmc_level_opts *opts)
+{
+    if (!ctx || !opts || level < 0 || level > ctx->cfg.L_max || n_samples < 0) return 0;
+    return make_level_layout(ctx->cfg, level, n_samples, *opts).bytes;
+}
+
+int mlmc_fill_xi(const mlmc_ctx *cctx, int32_t level, int64_t first_sample, int64_t n,
+                 double *xi_dev, void *stream)
+{
+    mlmc_ctx *ctx = const_cast<mlmc_ctx *>(cctx);
+    if (!ctx || level < 0 || level > 32767 || first_sample < 0 || n < 0 ||
+        first_sample + n > (int64_t)1 << 32 || (!xi_dev && n > 0))
+        return fail(ctx, MLMC_EINVAL, "fill_xi: bad arguments");
+    HIPCHK(launch_fill_xi(ctx->cfg.seed, level, first_sample, n, ctx->cfg.K, xi_dev, (hipStream_t)stream));
+    return MLMC_OK;
+}
+
+int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+               const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes, double *q_dev,
+               double *u_dev, uint8_t *status_dev, int32_t *iters_dev, void *stream)
+{
+    int rc = check_level(ctx, level);
+    if (rc) return rc;
+    if ((rc = check_opts(ctx, opts))) return rc;
+    if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
+    if (n == 0) return MLMC_OK;
+    if (!xi_dev || !ws_dev || !q_dev) return fail(ctx, MLMC_EINVAL, "null pointer");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
+    if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
+    hipStream_t st = (hipStream_t)stream;
+    const grid_layout &L = LL.fine;
+    void *ws = at<void>(ws_dev, LL.off_fine);
+    int32_t *it = at<int32_t>(ws, L.off_iters);
+    rc = solve_grid(ctx, L, level, xi_dev, *opts, opts->eps_fine, ws, q_dev, it, st);
+    if (rc) return rc;
+    if (u_dev) HIPCHK(launch_unpad(L.n, (int)n, at<double>(ws, L.off_x), u_dev, st));
+    if (iters_dev) HIPCHK(hipMemcpyAsync(iters_dev, it, n * 4, hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_pair_sums((int)n, q_dev, nullptr, at<uint32_t>(ws, L.off_state), nullptr, it, nullptr,
+                            status_dev, ctx->d_sums, st));
+    HIPCHK(hipMemcpyAsync(ctx->h_sums, ctx->d_sums, 7 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ctx->h_sums[5] > 0 ? MLMC_ENOCONV : MLMC_OK;
+}
+
+int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                      const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes,
+                      double *q_fine_dev, double *q_coarse_dev, double *y_dev,
+                      uint8_t *status_dev, mlmc_level_stats *stats_host, void *stream)
+{
+    int rc = check_level(ctx, level);
+    if (rc) return rc;
+    if ((rc = check_opts(ctx, opts))) return rc;
+    if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
+    if (n > 0 && (!xi_dev || !ws_dev)) return fail(ctx, MLMC_EINVAL, "null pointer");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
+    if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
+    hipStream_t st = (hipStream_t)stream;
+    if (stats_host) HIPCHK(hipEventRecord(ctx->ev0, st));
+    double *qf = q_fine_dev ? q_fine_dev : at<double>(ws_dev, LL.off_qf);
+    double *qc = q_coarse_dev ? q_coarse_dev : at<double>(ws_dev, LL.off_qc);
+    void *wf = at<void>(ws_dev, LL.off_fine);
+    if (n > 0) {
+        rc = solve_grid(ctx, LL.fine, level, xi_dev, *opts, opts->eps_fine, wf, qf,
+                        at<int32_t>(wf, LL.fine.off_iters), st);
+        if (rc) return rc;
+    }
+    const uint32_t *stc = nullptr;
+    if (level > 0 && n > 0) {
+        void *wc = at<void>(ws_dev, LL.off_coarse);
+        rc = solve_grid(ctx, LL.coarse, level - 1, xi_dev, *opts, opts->eps_coarse, wc, qc,
+                        at<int32_t>(wc, LL.coarse.off_iters), st);
+        if (rc) return rc;
+        stc = at<uint32_t>(wc, LL.coarse.off_state);
+    }
+    if (n > 0)
+        HIPCHK(launch_pair_sums((int)n, qf, level > 0 ? qc : nullptr, at<uint32_t>(wf, LL.fine.off_state),
+                                stc, at<int32_t>(wf, LL.fine.off_iters), y_dev, status_dev, ctx->d_sums, st));
+    if (stats_host) {
+        HIPCHK(hipEventRecord(ctx->ev1, st));
+        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, ctx->d_sums, 7 * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        memset(stats_host, 0, sizeof *stats_host);
+        stats_host->n = n;
+        if (n > 0) {
+            stats_host->sum_y = ctx->h_sums[0];
+            stats_host->sum_y2 = ctx->h_sums[1];
+            stats_host->sum_qf = ctx->h_sums[2];
+            stats_host->sum_qc = ctx->h_sums[3];
+            stats_host->n_promoted = (int64_t)ctx->h_sums[4];
+            stats_host->n_noconv = (int64_t)ctx->h_sums[5];
+            stats_host->mean_iters = ctx->h_sums[6] / (double)n;
+        }
+        stats_host->gpu_ms = ms;
+        return stats_host->n_noconv > 0 ? MLMC_ENOCONV : MLMC_OK;
+    }
+    return MLMC_OK;
+}
+
+int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
+                  mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream)
+{
+    if (!ctx || !out || !(tol > 0.0) || n_init < 2 || ctx->cfg.L_max < 1)
+        return fail(ctx, MLMC_EINVAL, "estimate: bad arguments");
+    if (solver != MLMC_MINRES && !dtype_per_level && solver == MLMC_DIRECT_IR)
+        return fail(ctx, MLMC_EINVAL, "estimate: dtype_per_level is NULL");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    const mlmc_config &c = ctx->cfg;
+    const int Lmax = c.L_max;
+    const int64_t chunk_max = 1 << 14;
+    // one workspace and one xi buffer sized for the largest chunk of any level
+    size_t ws_bytes = 0;
+    std::vector<int64_t> chunk(Lmax + 1);
+    for (int l = 0; l <= Lmax; ++l) {
+        mlmc_level_opts o{};
+        o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
+        o.solver = solver;
+        o.promote = 1;
+        // keep each level's workspace near 2 GiB or below
+        int64_t ch = chunk_max;
+        while (ch > 16 && make_level_layout(c, l, ch, o).bytes > ((size_t)2 << 30)) ch /= 2;
+        chunk[l] = ch;
+        ws_bytes = std::max(ws_bytes, make_level_layout(c, l, ch, o).bytes);
+    }
+    void *ws = nullptr;
+    double *xi = nullptr;
+    HIPCHK(hipMalloc(&ws, ws_bytes));
+    if (hipMalloc(&xi, (size_t)chunk_max * c.K * 8) != hipSuccess) {
+        (void)hipFree(ws);
+        return fail(ctx, MLMC_EHIP, "estimate: out of device memory");
+    }
+    auto cost = [&](int l) {
+        auto f = [](int n) { const double m = n - 1; return m * m * m * m; };
+        return f(c.n0 << l) + (l > 0 ? f(c.n0 << (l - 1)) : 0.0);
+    };
+    int L = 1;
+    std::vector<int64_t> N = {n_init, n_init}, done = {0, 0};
+    std::vector<double> s1 = {0, 0}, s2 = {0, 0};
+    std::vector<double> yhat, var;
+    const double bias_c = (std::pow((double)c.m, c.alpha) - 1.0) / std::sqrt(2.0) * tol;
+    double gpu_ms = 0.0;
+    int rc = MLMC_OK;
+    int converged = 0;
+    for (int round = 0; round < 200; ++round) {
+        double eps[16];
+        mlmc_accuracy_targets(ctx, L, eps);
+        for (int l = 0; l <= L && rc >= 0; ++l) {
+            int64_t need = N[l] - done[l];
+            while (need > 0 && rc >= 0) {
+                const int64_t cnt = std::min<int64_t>(need, chunk[l]);
+                rc = mlmc_fill_xi(ctx, l, done[l], cnt, xi, st);
+                if (rc) break;
+                mlmc_level_opts o{};
+                o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
+                o.solver = mixed ? solver : MLMC_DIRECT;
+                o.eps_fine = mixed ? eps[l] : 0.0;
+                o.eps_coarse = mixed && l > 0 ? eps[l - 1] : 0.0;
+                o.promote = 1;
+                mlmc_level_stats stt{};
+                rc = mlmc_sample_level(ctx, l, cnt, xi, &o, ws, ws_bytes, nullptr, nullptr, nullptr,
+                                       nullptr, &stt, st);
+                if (rc < 0) break;
+                if (rc == MLMC_ENOCONV) rc = MLMC_OK;
+                s1[l] += stt.sum_y;
+                s2[l] += stt.sum_y2;
+                gpu_ms += stt.gpu_ms;
+                done[l] += cnt;
+                need -= cnt;
+            }
+        }
+        if (rc < 0) break;
+        yhat.assign(L + 1, 0.0);
+        var.assign(L + 1, 0.0);
+        double tot = 0.0;
+        for (int l = 0; l <= L; ++l) {
+            yhat[l] = s1[l] / (double)done[l];
+            var[l] = std::max(s2[l] / (double)done[l] - yhat[l] * yhat[l], 0.0);
+            tot += std::sqrt(var[l] * cost(l));
+        }
+        for (int l = 0; l <= L; ++l)
+            N[l] = std::max<int64_t>(done[l], (int64_t)std::ceil(std::sqrt(var[l] / cost(l)) * 2.0 / (tol * tol) * tot));
+        if (std::fabs(yhat[L]) > bias_c && L < Lmax) {
+            ++L;
+            N.push_back(n_init);
+            done.push_back(0);
+            s1.push_back(0);
+            s2.push_back(0);
+            continue;
+        }
+        bool need_more = false;
+        for (int l = 0; l <= L; ++l) need_more |= N[l] > done[l];
+        if (!need_more) {
+            double v = 0.0;
+            for (int l = 0; l <= L; ++l) v += var[l] / (double)done[l];
+            converged = (std::fabs(yhat[L]) <= bias_c) && v <= tol * tol / 2.0 * (1 + 1e-12);
+            break;
+        }
+    }
+    (void)hipFree(ws);
+    (void)hipFree(xi);
+    if (rc < 0) return rc;
+    memset(out, 0, sizeof *out);
+    out->L = L;
+    out->converged = converged;
+    double est = 0.0, v = 0.0;
+    double eps[16];
+    mlmc_accuracy_targets(ctx, L, eps);
+    for (int l = 0; l <= L; ++l) {
+        est += yhat[l];
+        v += var[l] / (double)done[l];
+        out->N[l] = done[l];
+        out->Yhat[l] = yhat[l];
+        out->s2[l] = var[l];
+        out->C[l] = cost(l);
+        out->eps[l] = mixed ? eps[l] : 0.0;
+    }
+    out->estimate = est;
+    out->var_est = v;
+    out->gpu_ms = gpu_ms;
+    out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MLMC_OK;
+}
+
+int mlmc_profile(mlmc_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return MLMC_EINVAL;
+    for (auto &r : ctx->prof) {
+        ctx->ev_pool.push_back(r.a);
+        ctx->ev_pool.push_back(r.b);
+    }
+    ctx->prof.clear();
+    ctx->prof_on = enable != 0;
+    return MLMC_OK;
+}
+
+int mlmc_profile_read(mlmc_ctx *ctx, int32_t kind, int32_t n, double *total_ms, int64_t *launches,
+                      int64_t *samples)
+{
+    if (!ctx || !total_ms || !launches || !samples) return MLMC_EINVAL;
+    double ms = 0.0;
+    int64_t cnt = 0, smp = 0;
+    for (auto &r : ctx->prof) {
+        if (r.kind != kind || r.n != n) continue;
+        HIPCHK(hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        ++cnt;
+        smp += r.samples;
+    }
+    *total_ms = ms;
+    *launches = cnt;
+    *samples = smp;
+    return MLMC_OK;
+}
+
+int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, const double *grad_q_dev,
+              double eps_adjoint, void *ws_dev, size_t ws_bytes, double *grad_xi_dev, void *stream)
+{
+    (void)ctx; (void)level; (void)n; (void)xi_dev; (void)grad_q_dev; (void)eps_adjoint;
+    (void)ws_dev; (void)ws_bytes; (void)grad_xi_dev; (void)stream;
+    return fail(ctx, MLMC_ENOTIMPL, "grad not implemented yet");
+}
+
+}  // extern "C"
+
+namespace {
+int minres_solve(mlmc_ctx *ctx, const grid_layout &L, void *ws, double eps, hipStream_t st)
+{
+    (void)L; (void)ws; (void)eps; (void)st;
+    return fail(ctx, MLMC_ENOTIMPL, "MINRES not implemented yet");
+}
+}  // namespace

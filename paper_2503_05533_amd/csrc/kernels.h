@@ -1,0 +1,50 @@
+// Internal launch interface between the host API and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mlmc {
+
+// Internal per-sample state bits (the low nibble matches the public status bits).
+enum : uint32_t {
+    ST_CONVERGED = 1u,
+    ST_PROMOTED = 2u,
+    ST_NONFINITE = 4u,
+    ST_IMAX = 8u,
+    ST_STALL = 16u,      // residual stopped decreasing
+    ST_BREAKDOWN = 32u,  // non-positive pivot in the factorisation
+    ST_DONE = 1u << 31,  // no further refinement work for this sample
+};
+
+size_t factor_entries_per_sample(int n);
+
+hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi,
+                          hipStream_t st);
+hipError_t launch_field(int S, int K, int P, const double *xi, const double *phit, double *a,
+                        hipStream_t st);
+hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double *phit,
+                            const double *gq, double *grad, hipStream_t st);
+hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
+                         hipStream_t st);
+hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, const double *gam,
+                         void *factor, const int *idx, int64_t slot_base, uint32_t *state,
+                         hipStream_t st);
+hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const double *beta,
+                        const void *factor, const double *rhs, double rhs_const, double *x,
+                        int accumulate, double *zbuf, const int *idx, int64_t slot_base,
+                        const uint32_t *state, hipStream_t st);
+hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, const double *x,
+                           double *r, double eps, int trip, int imax, int direct, const int *idx,
+                           uint32_t *state, double *relres, double *q, int32_t *iters,
+                           int *n_active, hipStream_t st);
+hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);
+hipError_t launch_init_state(int S, uint32_t *state, double *relres, hipStream_t st);
+hipError_t launch_reset_subset(int P, const int *idx, uint32_t *state, double *relres,
+                               hipStream_t st);
+hipError_t launch_collect(int S, const uint32_t *state, int *idx, int *cnt, hipStream_t st);
+hipError_t launch_pair_sums(int S, const double *qf, const double *qc, const uint32_t *stf,
+                            const uint32_t *stc, const int32_t *itf, double *y, uint8_t *status,
+                            double *sums, hipStream_t st);
+
+}  // namespace mlmc

@@ -1,0 +1,747 @@
+// HIP kernels (gfx950) of the batched per-level sample solve.
+//
+// Per grid with n cells per side: m = n-1 unknowns per grid row, the
+// unknowns of grid row j form block j (0 <= j < m), and every block is padded
+// to M = n entries (entry m is an identity pad).  Internal vectors use that
+// padded layout: index j*M + i, i = ix-1, j = iy-1.
+//
+// The symmetric positive definite system A x = b is block tridiagonal.  With
+// the diagonal scaling S = diag(A)^(-1/2) (Ahat = S A S has unit diagonal):
+//   Ahat_jj = T_j  (tridiagonal: 1 on the diagonal, gam_j[i] between i, i+1)
+//   Ahat_j,j-1 = diag(beta_j)  (coupling to the grid row below)
+// Block elimination: Schur complements C_0 = T_0,
+//   C_j = T_j - diag(beta_j) C_{j-1}^{-1} diag(beta_j),
+// each C_j is inverted in place by the symmetric sweep (Gauss-Jordan) operator
+// and -C_j^{-1} is stored as the factor of block j.  Solves are then two
+// sweeps of symmetric block mat-vecs (forward: z_j = C_j^{-1}(s r_j -
+// beta_j z_{j-1}); back: x_j = z_j - C_j^{-1} beta_{j+1} x_{j+1}).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "dtypes.h"
+#include "kernels.h"
+
+namespace mlmc {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline double hmean(double p, double q) { return 2.0 * p * q / (p + q); }
+
+// Tile t of the lower block triangle, enumerated row by row: t = I(I+1)/2 + J.
+__device__ inline void tile_of(int t, int &I, int &J)
+{
+    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+template <int NT>
+__device__ inline double block_sum(double v, double *red)
+{
+    // fixed-order tree reduction (deterministic)
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ xi
+
+__device__ inline uint64_t splitmix_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi)
+{
+    const int npair = (K + 1) / 2;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n * npair) return;
+    const int64_t s = g / npair;
+    const int p = (int)(g % npair);
+    const uint64_t sample = (uint64_t)(first + s);
+    const uint64_t base = ((((uint64_t)level << 32) | sample) << 8 | (uint64_t)p) << 1;
+    const uint64_t o0 = splitmix_mix(seed + (base + 1ull) * 0x9E3779B97F4A7C15ull);
+    const uint64_t o1 = splitmix_mix(seed + ((base | 1ull) + 1ull) * 0x9E3779B97F4A7C15ull);
+    const double u1 = ((double)(o0 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(o1 >> 11) * 0x1.0p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(2.0 * M_PI * u2, &sn, &cs);
+    xi[s * K + 2 * p] = r * cs;
+    if (2 * p + 1 < K) xi[s * K + 2 * p + 1] = r * sn;
+}
+
+// ------------------------------------------------------------------ GEMMs
+
+// C[i][j] = epi(sum_l A[i][l] * B(l, j)), A row-major [R x L];
+// B(l,j) = B[l*ldb + j] (BT = false) or B[j*ldb + l] (BT = true).
+// 64 x 64 output tile per 256 threads, 4 x 4 per thread, L chunks of 16.
+// EPI 0: exp (coefficient field), EPI 1: scale row i by rowscale[i] (or 1).
+template <bool BT, int EPI>
+__global__ __launch_bounds__(256) void k_gemm64(int R, int Cn, int L, const double *__restrict__ A,
+                                                 int lda, const double *__restrict__ B, int ldb,
+                                                 double *__restrict__ C, int ldc,
+                                                 const double *__restrict__ rowscale)
+{
+    __shared__ double As[16][64 + 1];
+    __shared__ double Bs[16][64 + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    double acc[4][4] = {};
+    for (int l0 = 0; l0 < L; l0 += 16) {
+        for (int e = t; e < 1024; e += 256) {
+            int rr = e >> 4, ll = e & 15;
+            int gr = r0 + rr, gl = l0 + ll;
+            As[ll][rr] = (gr < R && gl < L) ? A[(size_t)gr * lda + gl] : 0.0;
+        }
+        if (BT) {
+            for (int e = t; e < 1024; e += 256) {
+                int cc = e >> 4, ll = e & 15;
+                int gc = c0 + cc, gl = l0 + ll;
+                Bs[ll][cc] = (gc < Cn && gl < L) ? B[(size_t)gc * ldb + gl] : 0.0;
+            }
+        } else {
+            for (int e = t; e < 1024; e += 256) {
+                int ll = e >> 6, cc = e & 63;
+                int gc = c0 + cc, gl = l0 + ll;
+                Bs[ll][cc] = (gc < Cn && gl < L) ? B[(size_t)gl * ldb + gc] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ll = 0; ll < 16; ++ll) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[ll][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[ll][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int gr = r0 + ty * 4 + i;
+        if (gr >= R) continue;
+        double sc = (EPI == 1 && rowscale) ? rowscale[gr] : 1.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int gc = c0 + tx + 16 * j;
+            if (gc < Cn) C[(size_t)gr * ldc + gc] = EPI == 0 ? exp(acc[i][j]) : sc * acc[i][j];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ assembly
+
+// Scaled block coefficients from the nodal coefficient a[(n+1)^2]:
+// sc = diag(A)^(-1/2), gam (to the right neighbour), beta (to the row below).
+__global__ void k_coeffs(int n, int S, const double *__restrict__ a, double *__restrict__ sc,
+                         double *__restrict__ gam, double *__restrict__ beta)
+{
+    const int m = n - 1, M = n, np = n + 1;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)S * m * M) return;
+    const int s = (int)(g / (m * M));
+    const int e = (int)(g % (m * M));
+    const int j = e / M, i = e % M;
+    const size_t o = (size_t)s * m * M + e;
+    if (i >= m) {
+        sc[o] = 0.0;
+        gam[o] = 0.0;
+        beta[o] = 0.0;
+        return;
+    }
+    const double *as = a + (size_t)s * np * np;
+    auto diag = [&](int ix, int iy) {
+        const int p = iy * np + ix;
+        const double c = as[p];
+        return hmean(c, as[p - 1]) + hmean(c, as[p + 1]) + hmean(c, as[p - np]) + hmean(c, as[p + np]);
+    };
+    const int ix = i + 1, iy = j + 1, p = iy * np + ix;
+    const double sP = 1.0 / sqrt(diag(ix, iy));
+    sc[o] = sP;
+    gam[o] = (i + 1 < m) ? -hmean(as[p], as[p + 1]) * sP / sqrt(diag(ix + 1, iy)) : 0.0;
+    beta[o] = (j > 0) ? -hmean(as[p], as[p - np]) * sP / sqrt(diag(ix, iy - 1)) : 0.0;
+}
+
+// ------------------------------------------------------------------ factor
+
+// One workgroup per sample.  The M x M working matrix lives in registers as
+// TR x TR tiles of the lower block triangle (diagonal tiles full and kept
+// symmetric), one tile per thread.  Each sweep pivot k: the owners of
+// column k publish it to LDS (double-buffered by parity), one barrier, and
+// every tile applies  X_il -= (x_ik / x_kk) x_kl  with the row/column k
+// fix-ups of the sweep operator.  After all M pivots the tiles hold -C_j^{-1}.
+template <typename Tst, int M, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_factor(int S, const double *__restrict__ beta,
+                                               const double *__restrict__ gam,
+                                               Tst *__restrict__ factor, const int *__restrict__ idx,
+                                               int64_t slot_base, uint32_t *__restrict__ state)
+{
+    using Tac = typename store_traits<Tst>::acc;
+    constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR;
+    constexpr int m = M - 1;
+    __shared__ Tac colbuf[2][M];
+    __shared__ Tac bj[M], gj[M];
+    __shared__ int bad;
+    const int b = blockIdx.x;
+    const int s = idx ? idx[b] : b;
+    const int64_t slot = slot_base + b;
+    const int t = threadIdx.x;
+    const bool active = t < T;
+    int I = 0, J = 0;
+    if (active) tile_of(t, I, J);
+    const int i0 = I * TR, j0 = J * TR;
+    const double *bs = beta + (size_t)s * m * M;
+    const double *gs = gam + (size_t)s * m * M;
+    Tst *fs = factor + (size_t)slot * m * T * E;
+    if (t == 0) bad = 0;
+    Tac tile[TR][TR];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int c = 0; c < TR; ++c) tile[r][c] = 0;
+
+    for (int j = 0; j < m; ++j) {
+        for (int i = t; i < M; i += NT) {
+            bj[i] = (Tac)bs[j * M + i];
+            gj[i] = (Tac)gs[j * M + i];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < TR; ++r)
+#pragma unroll
+                for (int c = 0; c < TR; ++c) {
+                    const int gi = i0 + r, gc = j0 + c;
+                    Tac tv = gi == gc ? (Tac)1 : (gi == gc + 1 ? gj[gc] : (gc == gi + 1 ? gj[gi] : (Tac)0));
+                    tile[r][c] = bj[gi] * tile[r][c] * bj[gc] + tv;
+                }
+        }
+        for (int K = 0; K < Tn; ++K) {
+#pragma unroll
+            for (int kk = 0; kk < TR; ++kk) {
+                const int k = K * TR + kk;
+                Tac *buf = colbuf[k & 1];
+                if (active) {
+                    if (I == K) {
+#pragma unroll
+                        for (int c = 0; c < TR; ++c) buf[j0 + c] = tile[kk][c];
+                    } else if (J == K) {
+#pragma unroll
+                        for (int r = 0; r < TR; ++r) buf[i0 + r] = tile[r][kk];
+                    }
+                }
+                __syncthreads();
+                if (active) {
+                    const Tac d = buf[k];
+                    const Tac inv = (Tac)1 / d;
+                    Tac v[TR], cc[TR];
+#pragma unroll
+                    for (int r = 0; r < TR; ++r) v[r] = buf[i0 + r] * inv;
+#pragma unroll
+                    for (int c = 0; c < TR; ++c) cc[c] = buf[j0 + c];
+#pragma unroll
+                    for (int r = 0; r < TR; ++r)
+#pragma unroll
+                        for (int c = 0; c < TR; ++c) tile[r][c] = fma(-v[r], cc[c], tile[r][c]);
+                    if (I == K) {
+#pragma unroll
+                        for (int c = 0; c < TR; ++c) tile[kk][c] = cc[c] * inv;
+                    }
+                    if (J == K) {
+#pragma unroll
+                        for (int r = 0; r < TR; ++r) tile[r][kk] = v[r];
+                        if (I == K) {
+                            tile[kk][kk] = -inv;
+                            if (!(d > (Tac)0) || !isfinite(d)) bad = 1;
+                        }
+                    }
+                }
+            }
+        }
+        if (active) {
+            Tst *fb = fs + (size_t)j * T * E;
+#pragma unroll
+            for (int r = 0; r < TR; ++r)
+#pragma unroll
+                for (int c = 0; c < TR; ++c) fb[(r * TR + c) * T + t] = store_traits<Tst>::store(tile[r][c]);
+        }
+        __syncthreads();
+    }
+    if (t == 0 && bad) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
+}
+
+// ------------------------------------------------------------------ solve
+
+// x (+)= S Ahat^{-1} S rhs with the stored factor (one workgroup per sample).
+// rhs: padded [S][m*M] FP64, or NULL for the constant rhs_const.
+// Arithmetic in Tac (FP64 for the FP64 factor, FP32 otherwise); z in zbuf.
+template <typename Tst, int M, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_solve(const double *__restrict__ sc,
+                                              const double *__restrict__ beta,
+                                              const Tst *__restrict__ factor,
+                                              const double *__restrict__ rhs, double rhs_const,
+                                              double *__restrict__ x, int accumulate,
+                                              double *__restrict__ zbuf,
+                                              const int *__restrict__ idx, int64_t slot_base,
+                                              const uint32_t *__restrict__ state)
+{
+    using Tac = typename store_traits<Tst>::acc;
+    constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR;
+    constexpr int m = M - 1;
+    __shared__ Tac g[M], acc[M], xc[M];
+    const int b = blockIdx.x;
+    const int s = idx ? idx[b] : b;
+    if (state && (state[s] & ST_DONE)) return;
+    const int64_t slot = slot_base + b;
+    const int t = threadIdx.x;
+    const bool active = t < T;
+    int I = 0, J = 0;
+    if (active) tile_of(t, I, J);
+    const int i0 = I * TR, j0 = J * TR;
+    const size_t vo = (size_t)s * m * M;
+    const double *scs = sc + vo, *bs = beta + vo;
+    const double *rs = rhs ? rhs + vo : nullptr;
+    double *xs = x + vo, *zs = zbuf + vo;
+    const Tst *fs = factor + (size_t)slot * m * T * E;
+
+    auto matvec = [&](int j) {
+        // acc[i] += sum_l F_j[i][l] g[l], F_j = stored -C_j^{-1} (symmetric)
+        if (!active) return;
+        const Tst *fb = fs + (size_t)j * T * E;
+        Tac e[TR][TR];
+#pragma unroll
+        for (int r = 0; r < TR; ++r)
+#pragma unroll
+            for (int c = 0; c < TR; ++c) e[r][c] = store_traits<Tst>::load(fb[(r * TR + c) * T + t]);
+        Tac gr[TR], gc[TR];
+#pragma unroll
+        for (int r = 0; r < TR; ++r) gr[r] = g[i0 + r];
+#pragma unroll
+        for (int c = 0; c < TR; ++c) gc[c] = g[j0 + c];
+#pragma unroll
+        for (int r = 0; r < TR; ++r) {
+            Tac sum = 0;
+#pragma unroll
+            for (int c = 0; c < TR; ++c) sum = fma(e[r][c], gc[c], sum);
+            atomicAdd(&acc[i0 + r], sum);
+        }
+        if (I != J) {
+#pragma unroll
+            for (int c = 0; c < TR; ++c) {
+                Tac sum = 0;
+#pragma unroll
+                for (int r = 0; r < TR; ++r) sum = fma(e[r][c], gr[r], sum);
+                atomicAdd(&acc[j0 + c], sum);
+            }
+        }
+    };
+
+    // forward: z_j = C_j^{-1} (s_j r_j - beta_j z_{j-1}) = -F_j g_j
+    for (int i = t; i < M; i += NT) xc[i] = 0;
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        for (int i = t; i < M; i += NT) {
+            const double rv = rs ? rs[j * M + i] : (i < m ? rhs_const : 0.0);
+            g[i] = (Tac)(scs[j * M + i] * rv) - (Tac)bs[j * M + i] * xc[i];
+            acc[i] = 0;
+        }
+        __syncthreads();
+        matvec(j);
+        __syncthreads();
+        for (int i = t; i < M; i += NT) {
+            const Tac z = -acc[i];
+            xc[i] = z;
+            zs[j * M + i] = (double)z;
+        }
+        __syncthreads();
+    }
+    // back: x_{m-1} = z_{m-1}; x_j = z_j - C_j^{-1} beta_{j+1} x_{j+1} = z_j + F_j (beta x)
+    for (int i = t; i < M; i += NT) {
+        const double d = scs[(m - 1) * M + i] * (double)xc[i];
+        xs[(m - 1) * M + i] = accumulate ? xs[(m - 1) * M + i] + d : d;
+    }
+    for (int j = m - 2; j >= 0; --j) {
+        for (int i = t; i < M; i += NT) {
+            g[i] = (Tac)bs[(j + 1) * M + i] * xc[i];
+            acc[i] = (Tac)zs[j * M + i];
+        }
+        __syncthreads();
+        matvec(j);
+        __syncthreads();
+        for (int i = t; i < M; i += NT) {
+            const Tac xv = acc[i];
+            xc[i] = xv;
+            const double d = scs[j * M + i] * (double)xv;
+            xs[j * M + i] = accumulate ? xs[j * M + i] + d : d;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ residual
+
+// r = b - A x in FP64 from the nodal coefficient (matrix-free 5-point
+// stencil), ||r||/||b||, Q = h^2 sum x, and the refinement control of
+// Algorithm 2.1: converged when relres < eps (strict), otherwise flagged at
+// the trip limit, on a non-finite value, or when the residual stopped
+// decreasing (then the sample is a candidate for promotion).
+__global__ __launch_bounds__(256) void k_residual(int n, double h, double fconst,
+                                                  const double *__restrict__ a,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ r, double eps, int trip,
+                                                  int imax, int direct,
+                                                  const int *__restrict__ idx,
+                                                  uint32_t *__restrict__ state,
+                                                  double *__restrict__ relres,
+                                                  double *__restrict__ q,
+                                                  int32_t *__restrict__ iters,
+                                                  int *__restrict__ n_active)
+{
+    __shared__ double red[256];
+    const int m = n - 1, M = n, np = n + 1;
+    const int s = idx ? idx[blockIdx.x] : blockIdx.x;
+    const uint32_t st0 = state[s];
+    if (st0 & ST_DONE) return;
+    const double *as = a + (size_t)s * np * np;
+    const double *xs = x + (size_t)s * m * M;
+    double *rsp = r ? r + (size_t)s * m * M : nullptr;
+    const double bval = h * h * fconst;
+    double rr = 0.0, bb = 0.0, sx = 0.0;
+    for (int e = threadIdx.x; e < m * M; e += 256) {
+        const int j = e / M, i = e % M;
+        if (i >= m) {
+            if (rsp) rsp[e] = 0.0;
+            continue;
+        }
+        const int p = (j + 1) * np + (i + 1);
+        const double c = as[p];
+        const double aw = hmean(c, as[p - 1]), ae = hmean(c, as[p + 1]);
+        const double asu = hmean(c, as[p - np]), an = hmean(c, as[p + np]);
+        const double xv = xs[e];
+        double ax = (aw + ae + asu + an) * xv;
+        if (i > 0) ax -= aw * xs[e - 1];
+        if (i + 1 < m) ax -= ae * xs[e + 1];
+        if (j > 0) ax -= asu * xs[e - M];
+        if (j + 1 < m) ax -= an * xs[e + M];
+        const double rv = bval - ax;
+        if (rsp) rsp[e] = rv;
+        rr += rv * rv;
+        bb += bval * bval;
+        sx += xv;
+    }
+    rr = block_sum<256>(rr, red);
+    bb = block_sum<256>(bb, red);
+    sx = block_sum<256>(sx, red);
+    if (threadIdx.x == 0) {
+        const double rel = sqrt(rr) / sqrt(bb);
+        const double prev = relres[s];
+        relres[s] = rel;
+        q[s] = h * h * sx;
+        if (iters) iters[s] = trip;
+        uint32_t st = st0;
+        if (!isfinite(rel) || !isfinite(sx)) st |= ST_NONFINITE | ST_DONE;
+        else if (direct || rel < eps) st |= ST_CONVERGED | ST_DONE;
+        else if (trip >= imax) st |= ST_IMAX | ST_DONE;
+        else if (trip > 0 && !(rel < prev)) st |= ST_STALL | ST_DONE;
+        state[s] = st;
+        if (!(st & ST_DONE) && n_active) atomicAdd(n_active, 1);
+    }
+}
+
+// Copy the padded solution to the caller's unpadded [S][(n-1)^2] layout.
+__global__ void k_unpad(int n, int S, const double *__restrict__ x, double *__restrict__ u)
+{
+    const int m = n - 1, M = n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)S * m * m) return;
+    const int s = (int)(g / (m * m));
+    const int P = (int)(g % (m * m));
+    u[(size_t)s * m * m + P] = x[(size_t)s * m * M + (P / m) * M + P % m];
+}
+
+// Scatter per-sample results of a compact subset back (promotion).
+__global__ void k_init_state(int S, uint32_t *state, double *relres)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    state[s] = 0;
+    relres[s] = INFINITY;
+}
+
+// Reset the refinement state of the samples in idx (for a promoted re-solve).
+__global__ void k_reset_subset(int P, const int *__restrict__ idx, uint32_t *state, double *relres)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int s = idx[p];
+    state[s] = ST_PROMOTED;
+    relres[s] = INFINITY;
+}
+
+// Collect samples that need promotion (not converged) into idx; count in *cnt.
+__global__ void k_collect(int S, const uint32_t *__restrict__ state, int *__restrict__ idx,
+                          int *__restrict__ cnt)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (!(state[s] & ST_CONVERGED)) {
+        const int p = atomicAdd(cnt, 1);
+        idx[p] = s;
+    }
+}
+
+// ------------------------------------------------------------------ pairing and level sums
+
+// Y = Qf - Qc (Qc may be NULL), combined status, and the FP64 level sums
+// [sum Y, sum Y^2, sum Qf, sum Qc, n_promoted, n_noconv, sum iters] in a fixed
+// order (per-thread strided partial sums, then a tree).
+__global__ __launch_bounds__(1024) void k_pair_sums(int S, const double *__restrict__ qf,
+                                                    const double *__restrict__ qc,
+                                                    const uint32_t *__restrict__ stf,
+                                                    const uint32_t *__restrict__ stc,
+                                                    const int32_t *__restrict__ itf,
+                                                    double *__restrict__ y,
+                                                    uint8_t *__restrict__ status,
+                                                    double *__restrict__ sums)
+{
+    __shared__ double red[1024];
+    double sy = 0, sy2 = 0, sf = 0, scc = 0, npro = 0, nnc = 0, sit = 0;
+    for (int s = threadIdx.x; s < S; s += 1024) {
+        const double f = qf[s], c = qc ? qc[s] : 0.0;
+        const double yv = f - c;
+        if (y) y[s] = yv;
+        sy += yv;
+        sy2 += yv * yv;
+        sf += f;
+        scc += c;
+        const uint32_t a = stf[s], bcs = stc ? stc[s] : (uint32_t)ST_CONVERGED;
+        if (status) status[s] = (uint8_t)((a & 15u) | ((bcs & 15u) << 4));
+        npro += ((a | bcs) & ST_PROMOTED) ? 1.0 : 0.0;
+        nnc += (!(a & ST_CONVERGED) || !(bcs & ST_CONVERGED)) ? 1.0 : 0.0;
+        sit += itf ? (double)itf[s] : 0.0;
+    }
+    double v[7] = {sy, sy2, sf, scc, npro, nnc, sit};
+    for (int q = 0; q < 7; ++q) {
+        double r = block_sum<1024>(v[q], red);
+        if (threadIdx.x == 0) sums[q] = r;
+    }
+}
+
+}  // namespace mlmc
+
+// ------------------------------------------------------------------ launchers
+
+using namespace mlmc;
+
+namespace {
+template <typename Tst, int M, int TR>
+constexpr int nthreads()
+{
+    constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2;
+    return ((T + 63) / 64) * 64;
+}
+
+template <int M>
+struct tile_cfg;
+template <> struct tile_cfg<16> { static constexpr int TR = 2; };
+template <> struct tile_cfg<32> { static constexpr int TR = 4; };
+template <> struct tile_cfg<64> { static constexpr int TR = 8; };
+template <> struct tile_cfg<128> { static constexpr int TR = 8; };
+template <> struct tile_cfg<256> { static constexpr int TR = 8; };
+
+template <typename Tst, int M>
+hipError_t launch_factor_t(int nblocks, const double *beta, const double *gam, void *factor,
+                           const int *idx, int64_t slot_base, uint32_t *state, hipStream_t st)
+{
+    constexpr int TR = tile_cfg<M>::TR, NT = nthreads<Tst, M, TR>();
+    hipLaunchKernelGGL((k_factor<Tst, M, TR, NT>), dim3(nblocks), dim3(NT), 0, st, nblocks, beta,
+                       gam, (Tst *)factor, idx, slot_base, state);
+    return hipGetLastError();
+}
+
+template <typename Tst, int M>
+hipError_t launch_solve_t(int nblocks, const double *sc, const double *beta, const void *factor,
+                          const double *rhs, double rhs_const, double *x, int accumulate,
+                          double *zbuf, const int *idx, int64_t slot_base, const uint32_t *state,
+                          hipStream_t st)
+{
+    constexpr int TR = tile_cfg<M>::TR, NT = nthreads<Tst, M, TR>();
+    hipLaunchKernelGGL((k_solve<Tst, M, TR, NT>), dim3(nblocks), dim3(NT), 0, st, sc, beta,
+                       (const Tst *)factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base,
+                       state);
+    return hipGetLastError();
+}
+
+template <typename Tst>
+hipError_t launch_factor_m(int M, int nb, const double *beta, const double *gam, void *factor,
+                           const int *idx, int64_t slot_base, uint32_t *state, hipStream_t st)
+{
+    switch (M) {
+    case 16: return launch_factor_t<Tst, 16>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 32: return launch_factor_t<Tst, 32>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 64: return launch_factor_t<Tst, 64>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 128: return launch_factor_t<Tst, 128>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 256: return launch_factor_t<Tst, 256>(nb, beta, gam, factor, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Tst>
+hipError_t launch_solve_m(int M, int nb, const double *sc, const double *beta, const void *factor,
+                          const double *rhs, double rc, double *x, int acc, double *zbuf,
+                          const int *idx, int64_t slot_base, const uint32_t *state, hipStream_t st)
+{
+    switch (M) {
+    case 16: return launch_solve_t<Tst, 16>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 32: return launch_solve_t<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 64: return launch_solve_t<Tst, 64>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 128: return launch_solve_t<Tst, 128>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 256: return launch_solve_t<Tst, 256>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+namespace mlmc {
+
+size_t factor_entries_per_sample(int n)
+{
+    const int M = n;
+    int TR = M <= 16 ? 2 : (M <= 32 ? 4 : 8);
+    const int Tn = M / TR, T = Tn * (Tn + 1) / 2;
+    return (size_t)(n - 1) * T * TR * TR;
+}
+
+hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi,
+                          hipStream_t st)
+{
+    const int64_t tot = n * ((K + 1) / 2);
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_xi, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, seed, level,
+                       first, n, K, xi);
+    return hipGetLastError();
+}
+
+hipError_t launch_field(int S, int K, int P, const double *xi, const double *phit, double *a,
+                        hipStream_t st)
+{
+    dim3 grid((P + 63) / 64, (S + 63) / 64);
+    hipLaunchKernelGGL((k_gemm64<false, 0>), grid, dim3(256), 0, st, S, P, K, xi, K, phit, P, a, P,
+                       (const double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double *phit,
+                            const double *gq, double *grad, hipStream_t st)
+{
+    dim3 grid((K + 63) / 64, (S + 63) / 64);
+    hipLaunchKernelGGL((k_gemm64<true, 1>), grid, dim3(256), 0, st, S, K, P, gz, P, phit, P, grad, K,
+                       gq);
+    return hipGetLastError();
+}
+
+hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
+                         hipStream_t st)
+{
+    const int64_t e = (int64_t)S * (n - 1) * n;
+    hipLaunchKernelGGL(k_coeffs, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, n, S, a, sc, gam, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, const double *gam,
+                         void *factor, const int *idx, int64_t slot_base, uint32_t *state,
+                         hipStream_t st)
+{
+    if (nblocks == 0) return hipSuccess;
+    switch (dtype) {
+    case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 2: return launch_factor_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 3: return launch_factor_m<__half>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const double *beta,
+                        const void *factor, const double *rhs, double rhs_const, double *x,
+                        int accumulate, double *zbuf, const int *idx, int64_t slot_base,
+                        const uint32_t *state, hipStream_t st)
+{
+    if (nblocks == 0) return hipSuccess;
+    switch (dtype) {
+    case 0: return launch_solve_m<double>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    case 1: return launch_solve_m<float>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    case 2: return launch_solve_m<__hip_bfloat16>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    case 3: return launch_solve_m<__half>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, const double *x,
+                           double *r, double eps, int trip, int imax, int direct, const int *idx,
+                           uint32_t *state, double *relres, double *q, int32_t *iters,
+                           int *n_active, hipStream_t st)
+{
+    if (nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual, dim3(nblocks), dim3(256), 0, st, n, 1.0 / n, fconst, a, x, r, eps,
+                       trip, imax, direct, idx, state, relres, q, iters, n_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st)
+{
+    const int64_t N = (int64_t)S * (n - 1) * (n - 1);
+    hipLaunchKernelGGL(k_unpad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, n, S, x, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(int S, uint32_t *state, double *relres, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_state, dim3((S + 255) / 256), dim3(256), 0, st, S, state, relres);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_subset(int P, const int *idx, uint32_t *state, double *relres,
+                               hipStream_t st)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_subset, dim3((P + 255) / 256), dim3(256), 0, st, P, idx, state,
+                       relres);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect(int S, const uint32_t *state, int *idx, int *cnt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_collect, dim3((S + 255) / 256), dim3(256), 0, st, S, state, idx, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_sums(int S, const double *qf, const double *qc, const uint32_t *stf,
+                            const uint32_t *stc, const int32_t *itf, double *y, uint8_t *status,
+                            double *sums, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_sums, dim3(1), dim3(1024), 0, st, S, qf, qc, stf, stc, itf, y, status,
+                       sums);
+    return hipGetLastError();
+}
+
+}  // namespace mlmc

@@ -1,0 +1,296 @@
+"""Python binding of libmlmc (argument marshalling only).
+
+Every step of the sample solve runs in the HIP library; this module only
+allocates device buffers with PyTorch, passes their pointers and the current
+HIP stream through the C ABI declared in include/mlmc.h, and converts
+results.  There is no CPU fallback: if the library is missing, or no GPU is
+visible, the calls raise.
+"""
+import ctypes
+import dataclasses
+import os
+
+import torch  # loads PyTorch's HIP runtime first; libmlmc binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlmc.so")
+
+MLMC_OK, MLMC_ENOCONV = 0, 1
+MLMC_EINVAL, MLMC_ENOMEM, MLMC_EHIP, MLMC_ENOTIMPL = -1, -2, -3, -4
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+SOLVERS = {"direct": 0, "direct_ir": 1, "minres": 2}
+ST_CONVERGED, ST_PROMOTED, ST_NONFINITE, ST_IMAX = 1, 2, 4, 8
+
+EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
+           "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
+           "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
+           "mlmc_profile_read"]
+
+
+class MLMCError(RuntimeError):
+    pass
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int32), ("m", ctypes.c_int32), ("L_max", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("sigma2", ctypes.c_double), ("corr_len", ctypes.c_double),
+                ("f", ctypes.c_double), ("k_p", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("ir_max_iter", ctypes.c_int32), ("minres_max_iter", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _LevelOpts(ctypes.Structure):
+    _fields_ = [("factor_dtype", ctypes.c_int), ("solver", ctypes.c_int),
+                ("eps_fine", ctypes.c_double), ("eps_coarse", ctypes.c_double),
+                ("promote", ctypes.c_int32)]
+
+
+class _LevelStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sum_y", ctypes.c_double), ("sum_y2", ctypes.c_double),
+                ("sum_qf", ctypes.c_double), ("sum_qc", ctypes.c_double),
+                ("n_promoted", ctypes.c_int64), ("n_noconv", ctypes.c_int64),
+                ("mean_iters", ctypes.c_double), ("gpu_ms", ctypes.c_double)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("var_est", ctypes.c_double),
+                ("L", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("N", ctypes.c_int64 * 16), ("Yhat", ctypes.c_double * 16),
+                ("s2", ctypes.c_double * 16), ("C", ctypes.c_double * 16),
+                ("eps", ctypes.c_double * 16), ("wall_s", ctypes.c_double),
+                ("gpu_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmlmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MLMCError("libmlmc.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.mlmc_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(vp)]
+    lib.mlmc_destroy.argtypes = [vp]
+    lib.mlmc_last_error.argtypes = [vp]
+    lib.mlmc_last_error.restype = ctypes.c_char_p
+    lib.mlmc_level_cells.argtypes = [vp, i32]
+    lib.mlmc_level_cells.restype = i32
+    lib.mlmc_accuracy_targets.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    lib.mlmc_get_kl_basis.argtypes = [vp, i32, vp, vp]
+    lib.mlmc_workspace_bytes.argtypes = [vp, i32, i64, ctypes.POINTER(_LevelOpts)]
+    lib.mlmc_workspace_bytes.restype = ctypes.c_size_t
+    lib.mlmc_fill_xi.argtypes = [vp, i32, i64, i64, vp, vp]
+    lib.mlmc_solve.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp, ctypes.c_size_t,
+                               vp, vp, vp, vp, vp]
+    lib.mlmc_sample_level.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp,
+                                      ctypes.c_size_t, vp, vp, vp, vp, ctypes.POINTER(_LevelStats), vp]
+    lib.mlmc_estimate.argtypes = [vp, dbl, i32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, i32,
+                                  ctypes.POINTER(_Result), vp]
+    lib.mlmc_grad.argtypes = [vp, i32, i64, vp, vp, dbl, vp, ctypes.c_size_t, vp, vp]
+    lib.mlmc_profile.argtypes = [vp, i32]
+    lib.mlmc_profile_read.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
+    _lib = lib
+    return lib
+
+
+@dataclasses.dataclass
+class Config:
+    n0: int = 16
+    m: int = 2
+    L_max: int = 4
+    K: int = 64
+    sigma2: float = 1.0
+    corr_len: float = 0.3
+    f: float = 1.0
+    k_p: float = 0.05
+    alpha: float = 2.0
+    beta: float = 4.0
+    gamma: float = 4.0
+    ir_max_iter: int = 10
+    minres_max_iter: int = 5000
+    seed: int = 1
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class MLMC:
+    """A library context: KL bases of every level live on the current device."""
+
+    def __init__(self, cfg: Config, device="cuda"):
+        if not torch.cuda.is_available():
+            raise MLMCError("no GPU visible: the MLMC library has no CPU path")
+        self.lib = load_library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        c = _Config(**dataclasses.asdict(cfg))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.mlmc_create(ctypes.byref(c), ctypes.byref(h))
+        if rc != 0:
+            raise MLMCError("mlmc_create failed (%d)" % rc)
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mlmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = self.lib.mlmc_last_error(self.h)
+            raise MLMCError("%s failed (%d): %s" % (what, rc, msg.decode() if msg else ""))
+        return rc
+
+    def _workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            torch.cuda.empty_cache()
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    @staticmethod
+    def _opts(dtype="f64", solver="direct", eps_fine=0.0, eps_coarse=0.0, promote=True):
+        return _LevelOpts(DTYPES[dtype], SOLVERS[solver], float(eps_fine), float(eps_coarse),
+                          1 if promote else 0)
+
+    def level_cells(self, level):
+        return self.lib.mlmc_level_cells(self.h, level)
+
+    def accuracy_targets(self, L):
+        out = (ctypes.c_double * (L + 1))()
+        self._check(self.lib.mlmc_accuracy_targets(self.h, L, out), "accuracy_targets")
+        return list(out)
+
+    def kl_basis(self, level):
+        """Phi_level^T as a [K, (n+1)^2] float64 device tensor (a copy)."""
+        n = self.level_cells(level)
+        out = torch.empty((self.cfg.K, (n + 1) ** 2), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mlmc_get_kl_basis(self.h, level, _ptr(out), _stream()), "get_kl_basis")
+        return out
+
+    def workspace_bytes(self, level, n, **opt):
+        o = self._opts(**opt)
+        return self.lib.mlmc_workspace_bytes(self.h, level, n, ctypes.byref(o))
+
+    KINDS = {"field": 0, "assembly": 1, "factor": 2, "solve": 3, "residual": 4}
+
+    def profile(self, enable=True):
+        self._check(self.lib.mlmc_profile(self.h, 1 if enable else 0), "profile")
+
+    def profile_read(self, kind, n):
+        ms, cnt, smp = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.mlmc_profile_read(self.h, self.KINDS[kind], n, ctypes.byref(ms),
+                                               ctypes.byref(cnt), ctypes.byref(smp)), "profile_read")
+        return dict(ms=ms.value, launches=cnt.value, samples=smp.value)
+
+    # -------------------------------------------------------------- entry points
+    def fill_xi(self, level, first, n):
+        xi = torch.empty((n, self.cfg.K), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mlmc_fill_xi(self.h, level, first, n, _ptr(xi), _stream()), "fill_xi")
+        return xi
+
+    def solve(self, level, xi, dtype="f64", solver="direct", eps=0.0, promote=True, want_u=False):
+        xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
+        S = xi.shape[0]
+        n = self.level_cells(level)
+        o = self._opts(dtype, solver, eps, 0.0, promote)
+        nb = self.lib.mlmc_workspace_bytes(self.h, level, S, ctypes.byref(o))
+        ws = self._workspace(nb)
+        q = torch.empty(S, dtype=torch.float64, device=self.device)
+        u = torch.empty((S, (n - 1) ** 2), dtype=torch.float64, device=self.device) if want_u else None
+        st = torch.empty(S, dtype=torch.uint8, device=self.device)
+        it = torch.empty(S, dtype=torch.int32, device=self.device)
+        rc = self._check(self.lib.mlmc_solve(self.h, level, S, _ptr(xi), ctypes.byref(o), _ptr(ws),
+                                             ws.numel(), _ptr(q), _ptr(u), _ptr(st), _ptr(it),
+                                             _stream()), "solve")
+        out = dict(q=q, status=st, iters=it, rc=rc)
+        if want_u:
+            out["u"] = u
+        return out
+
+    def sample_level(self, level, xi, dtype="f64", solver="direct", eps_fine=0.0, eps_coarse=0.0,
+                     promote=True, stats=True):
+        xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
+        S = xi.shape[0]
+        o = self._opts(dtype, solver, eps_fine, eps_coarse, promote)
+        nb = self.lib.mlmc_workspace_bytes(self.h, level, S, ctypes.byref(o))
+        ws = self._workspace(nb)
+        qf = torch.empty(S, dtype=torch.float64, device=self.device)
+        qc = torch.empty(S, dtype=torch.float64, device=self.device) if level > 0 else None
+        y = torch.empty(S, dtype=torch.float64, device=self.device)
+        st = torch.empty(S, dtype=torch.uint8, device=self.device)
+        sts = _LevelStats()
+        rc = self._check(self.lib.mlmc_sample_level(self.h, level, S, _ptr(xi), ctypes.byref(o),
+                                                    _ptr(ws), ws.numel(), _ptr(qf), _ptr(qc),
+                                                    _ptr(y), _ptr(st),
+                                                    ctypes.byref(sts) if stats else None,
+                                                    _stream()), "sample_level")
+        out = dict(qf=qf, qc=qc, y=y, status=st, rc=rc)
+        if stats:
+            out["stats"] = {k: getattr(sts, k) for k, _ in _LevelStats._fields_}
+        return out
+
+    def estimate(self, tol, n_init=1000, dtypes=None, solver="direct_ir", mixed=True):
+        L1 = self.cfg.L_max + 1
+        dts = (ctypes.c_int * L1)(*[DTYPES[d] for d in (dtypes or ["f32"] * L1)])
+        r = _Result()
+        self._check(self.lib.mlmc_estimate(self.h, float(tol), int(n_init), dts, SOLVERS[solver],
+                                           1 if mixed else 0, ctypes.byref(r), _stream()), "estimate")
+        L = r.L
+        return dict(estimate=r.estimate, var_est=r.var_est, L=L, converged=bool(r.converged),
+                    N=list(r.N[:L + 1]), Yhat=list(r.Yhat[:L + 1]), s2=list(r.s2[:L + 1]),
+                    C=list(r.C[:L + 1]), eps=list(r.eps[:L + 1]), wall_s=r.wall_s,
+                    gpu_ms=r.gpu_ms)
+
+    def grad(self, level, xi, grad_q=None, eps_adjoint=1e-10, dtype="f32", solver="direct_ir",
+             eps=1e-10):
+        """dQ/dxi (times grad_q) after a forward solve on the same samples."""
+        xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
+        S = xi.shape[0]
+        fw = self.solve(level, xi, dtype=dtype, solver=solver, eps=eps, promote=False)
+        ws = self._ws
+        g = torch.empty((S, self.cfg.K), dtype=torch.float64, device=self.device)
+        gq = None if grad_q is None else grad_q.to(device=self.device, dtype=torch.float64).contiguous()
+        self._check(self.lib.mlmc_grad(self.h, level, S, _ptr(xi), _ptr(gq), float(eps_adjoint),
+                                       _ptr(ws), ws.numel(), _ptr(g), _stream()), "grad")
+        return fw["q"], g
+
+
+class MLMCQoI(torch.autograd.Function):
+    """Q_l(xi) on one grid with the adjoint gradient as backward.
+
+    forward(ctx_obj, level, xi, dtype, eps) -> Q[S]; backward returns
+    grad_q[s] * dQ/dxi[s, :] from the library's adjoint kernel.
+    """
+
+    @staticmethod
+    def forward(ctx, lib_ctx, level, xi, dtype="f32", eps=1e-10):
+        q, g = lib_ctx.grad(level, xi.detach(), None, eps_adjoint=eps, dtype=dtype,
+                            solver="direct_ir" if dtype != "f64" else "direct", eps=eps)
+        ctx.save_for_backward(g)
+        return q.to(xi.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return None, None, (g * grad_out.to(g.dtype)[:, None]), None, None

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64 path: per-sample |dQ|/Q <= 1e-12.  Mixed path (low-precision factor +
+FP64 refinement to eps): the returned solution's relative residual, computed
+by the oracle, is below eps, and |dQ|/Q is within the exact bound
+(||r||/||b||) ||u|| ||b|| / (b^T u) that follows from Q - Q~ = u^T r.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _ctx(**kw):
+    from paper_2503_05533_amd import MLMC, Config
+    return MLMC(Config(**kw), device="cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_PHI = {}
+
+
+def _phi(n, K, s2, lam):
+    key = (n, K, s2, lam)
+    if key not in _PHI:
+        _PHI[key] = oracle.kl_basis(n, K, s2, lam)
+    return _PHI[key]
+
+
+# ----------------------------------------------------------------- set-up pieces
+
+def test_kl_basis_matches_oracle():
+    for (K, s2, lam) in [(16, 1.0, 0.3), (128, 2.0, 0.1)]:
+        ctx = _ctx(n0=16, L_max=2, K=K, sigma2=s2, corr_len=lam)
+        for level in range(3):
+            n = 16 << level
+            got = ctx.kl_basis(level).cpu().numpy().T
+            ref = _phi(n, K, s2, lam)
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)), (K, level)
+        ctx.close()
+
+
+def test_fill_xi_matches_generator():
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=1, K=128, seed=1003)
+    for level, first, n in [(0, 0, 1000), (1, 123456, 77), (1, (1 << 32) - 5, 5)]:
+        got = ctx.fill_xi(level, first, n).cpu().numpy()
+        ref = si.splitmix64_normals(1003, level, first, n, 128)
+        assert np.max(np.abs(got - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref)))
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+# ----------------------------------------------------------------- FP64 path
+
+def _fp64_case(n, S, K, s2, lam, seed):
+    torch = _torch()
+    level = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}[n]
+    ctx = _ctx(n0=16, L_max=level, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    xi = si.splitmix64_normals(seed, level, 0, S, K)
+    _say("fp64 case n=%d S=%d K=%d" % (n, S, K))
+    out = ctx.solve(level, torch.from_numpy(xi), dtype="f64", solver="direct", want_u=True)
+    q = out["q"].cpu().numpy()
+    u = out["u"].cpu().numpy()
+    ref, uref = oracle.solve_batch(n, _phi(n, K, s2, lam), xi, want_u=True)
+    rel = np.abs(q - ref) / ref
+    assert np.all(rel <= 1e-12), (n, rel.max())
+    assert np.max(np.abs(u - uref)) <= 1e-11 * np.max(np.abs(uref))
+    assert np.all(out["status"].cpu().numpy() & 1)
+    ctx.close()
+    return rel.max()
+
+
+def test_fp64_single_level_workload():
+    """n=32, K=16, sigma^2=1, lambda=0.3, 1000 samples: every Q within 1e-12."""
+    _fp64_case(32, 1000, 16, 1.0, 0.3, 1000)
+
+
+@pytest.mark.parametrize("n,S", [(16, 67), (64, 33), (128, 9)])
+def test_fp64_other_grids(n, S):
+    _fp64_case(n, S, 128, 2.0, 0.1, 1002)
+
+
+def test_fp64_finest_grid_sampled():
+    _fp64_case(256, 3, 128, 2.0, 0.1, 1003)
+
+
+def test_fp64_sigma0_closed_form():
+    torch = _torch()
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden",
+                                                 "laplace_sigma0.txt")) if not l.startswith("#")]
+    ctx = _ctx(n0=16, L_max=4, K=4, sigma2=0.0, corr_len=0.3)
+    for n_s, q_s in rows:
+        n = int(n_s)
+        if n < 16:
+            continue
+        level = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}[n]
+        q = ctx.solve(level, torch.zeros((2, 4), dtype=torch.float64), dtype="f64")["q"].cpu().numpy()
+        # FP64 bar 1e-12; rounding of the kappa ~ 2.6e4 system at n = 256 reaches ~1.5e-13
+        tol = 1e-13 if n <= 128 else 1e-12
+        assert np.all(np.abs(q - float(q_s)) <= tol * float(q_s)), (n, q, q_s)
+    ctx.close()
+
+
+def test_fp64_edge_batches():
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=1, K=16, seed=5)
+    xi = si.splitmix64_normals(5, 0, 0, 1, 16)
+    q1 = ctx.solve(0, torch.from_numpy(xi), dtype="f64")["q"].cpu().numpy()
+    assert abs(q1[0] - oracle.solve_batch(16, _phi(16, 16, 1.0, 0.3), xi)[0]) <= 1e-12 * q1[0]
+    out = ctx.solve(0, torch.zeros((0, 16), dtype=torch.float64), dtype="f64")
+    assert out["q"].numel() == 0
+    ctx.close()
+
+
+def test_determinism_bitwise():
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=2, K=64, seed=9)
+    xi = torch.from_numpy(si.splitmix64_normals(9, 2, 0, 40, 64))
+    a = ctx.solve(2, xi, dtype="f32", solver="direct_ir", eps=1e-9)["q"].cpu().numpy()
+    b = ctx.solve(2, xi, dtype="f32", solver="direct_ir", eps=1e-9)["q"].cpu().numpy()
+    assert np.array_equal(a, b)
+    ctx.close()
+
+
+# ----------------------------------------------------------------- mixed path
+
+def _bound(n, u, qref):
+    nb = math.sqrt(u.shape[1]) / n ** 2
+    return np.linalg.norm(u, axis=1) * nb / qref
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("n,S", [(16, 70), (32, 40), (64, 12)])
+def test_mixed_ir_reaches_eps(dtype, n, S):
+    torch = _torch()
+    level = {16: 0, 32: 1, 64: 2}[n]
+    K, s2, lam, seed = 128, 2.0, 0.1, 1002
+    ctx = _ctx(n0=16, L_max=level, K=K, sigma2=s2, corr_len=lam, seed=seed, ir_max_iter=10)
+    xi = si.splitmix64_normals(seed, level, 0, S, K)
+    phi = _phi(n, K, s2, lam)
+    qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
+    for eps in (8.7e-4, 1e-6):
+        _say("mixed case n=%d S=%d %s eps=%g" % (n, S, dtype, eps))
+        out = ctx.solve(level, torch.from_numpy(xi), dtype=dtype, solver="direct_ir", eps=eps,
+                        want_u=True)
+        st = out["status"].cpu().numpy()
+        assert np.all(st & 1), st
+        u = out["u"].cpu().numpy()
+        rr = oracle.relres_batch(n, phi, xi, u)
+        assert np.all(rr < eps * (1 + 1e-6)), rr.max()
+        q = out["q"].cpu().numpy()
+        dq = np.abs(q - qref) / qref
+        assert np.all(dq <= rr * _bound(n, uref, qref) * (1 + 1e-6) + 1e-14)
+    ctx.close()
+
+
+def test_mixed_ir_finest_grids_sampled():
+    torch = _torch()
+    K, s2, lam, seed = 128, 2.0, 0.1, 1003
+    for n, S, eps in [(128, 6, 3.052e-6), (256, 2, 7.629e-7)]:
+        level = {128: 3, 256: 4}[n]
+        ctx = _ctx(n0=16, L_max=level, K=K, sigma2=s2, corr_len=lam, seed=seed)
+        xi = si.splitmix64_normals(seed, level, 0, S, K)
+        phi = _phi(n, K, s2, lam)
+        qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
+        _say("mixed finest n=%d S=%d" % (n, S))
+        out = ctx.solve(level, torch.from_numpy(xi), dtype="f32", solver="direct_ir", eps=eps,
+                        want_u=True)
+        assert np.all(out["status"].cpu().numpy() & 1)
+        u = out["u"].cpu().numpy()
+        rr = oracle.relres_batch(n, phi, xi, u)
+        assert np.all(rr < eps * (1 + 1e-6))
+        dq = np.abs(out["q"].cpu().numpy() - qref) / qref
+        assert np.all(dq <= rr * _bound(n, uref, qref) * (1 + 1e-6) + 1e-14)
+        ctx.close()
+
+
+def test_imax_zero_flags_samples():
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=1, K=16, ir_max_iter=0)
+    xi = torch.from_numpy(si.splitmix64_normals(3, 1, 0, 10, 16))
+    out = ctx.solve(1, xi, dtype="f32", solver="direct_ir", eps=1e-14, promote=False)
+    st = out["status"].cpu().numpy()
+    assert np.all(st & 8) and not np.any(st & 1)
+    assert out["rc"] == 1
+    ctx.close()
+
+
+def test_promotion_rescues_unreachable_low_precision():
+    """eps below what a BF16 factor reaches in 2 corrections: promotion to FP64 converges."""
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=2, K=128, sigma2=2.0, corr_len=0.1, ir_max_iter=2, seed=11)
+    xi = si.splitmix64_normals(11, 2, 0, 20, 128)
+    out = ctx.solve(2, torch.from_numpy(xi), dtype="bf16", solver="direct_ir", eps=1e-11,
+                    promote=True)
+    st = out["status"].cpu().numpy()
+    assert np.all(st & 1)
+    assert np.any(st & 2)
+    q = out["q"].cpu().numpy()
+    qref = oracle.solve_batch(64, _phi(64, 128, 2.0, 0.1), xi)
+    assert np.all(np.abs(q - qref) / qref < 1e-10)
+    ctx.close()
+
+
+# ----------------------------------------------------------------- level pairing
+
+def test_sample_level_pairs_and_sums():
+    torch = _torch()
+    K, s2, lam, seed = 64, 1.0, 0.3, 1001
+    ctx = _ctx(n0=16, L_max=2, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    for level, S in [(0, 100), (1, 90), (2, 30)]:
+        xi = si.splitmix64_normals(seed, level, 0, S, K)
+        for dtype, solver, ef, ec in [("f64", "direct", 0.0, 0.0), ("f32", "direct_ir", 1e-11, 1e-11)]:
+            _say("pair level=%d %s" % (level, dtype))
+            out = ctx.sample_level(level, torch.from_numpy(xi), dtype=dtype, solver=solver,
+                                   eps_fine=ef, eps_coarse=ec)
+            nf = 16 << level
+            qf = oracle.solve_batch(nf, _phi(nf, K, s2, lam), xi)
+            qc = oracle.solve_batch(nf // 2, _phi(nf // 2, K, s2, lam), xi) if level else np.zeros(S)
+            y = out["y"].cpu().numpy()
+            assert np.allclose(out["qf"].cpu().numpy(), qf, rtol=1e-10, atol=0)
+            if level:
+                assert np.allclose(out["qc"].cpu().numpy(), qc, rtol=1e-10, atol=0)
+            assert np.all(np.abs(y - (qf - qc)) <= 1e-10 * (np.abs(qf) + np.abs(qc)))
+            stt = out["stats"]
+            assert stt["n"] == S
+            assert stt["sum_y"] == pytest.approx(y.sum(), rel=1e-13, abs=1e-18)
+            assert stt["sum_y2"] == pytest.approx((y * y).sum(), rel=1e-13)
+            assert stt["n_noconv"] == 0
+    ctx.close()
+
+
+# ----------------------------------------------------------------- errors
+
+def test_error_codes():
+    torch = _torch()
+    import ctypes
+    from paper_2503_05533_amd import MLMCError
+    ctx = _ctx(n0=16, L_max=1, K=16)
+    with pytest.raises(MLMCError):
+        ctx.solve(5, torch.zeros((2, 16), dtype=torch.float64))
+    o = ctx._opts("f64", "direct")
+    xi = torch.zeros((4, 16), dtype=torch.float64, device="cuda:0")
+    q = torch.empty(4, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda:0")
+    rc = ctx.lib.mlmc_solve(ctx.h, 0, 4, ctypes.c_void_p(xi.data_ptr()), ctypes.byref(o),
+                            ctypes.c_void_p(ws.data_ptr()), 1024, ctypes.c_void_p(q.data_ptr()),
+                            None, None, None, None)
+    assert rc == -2
+    assert b"workspace" in ctx.lib.mlmc_last_error(ctx.h)
+    ctx.close()
