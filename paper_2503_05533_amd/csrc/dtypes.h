@@ -31,4 +31,18 @@ template <> struct store_traits<__half> {
     __device__ static inline __half store(float v) { return __float2half(v); }
 };
 
+// 1/d from the hardware reciprocal refined by Newton steps (one for FP32,
+// two for FP64: relative error at the unit roundoff).
+__device__ inline float recip(float d)
+{
+    float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+__device__ inline double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
 }  // namespace mlmc

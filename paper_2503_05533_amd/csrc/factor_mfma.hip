@@ -1,0 +1,607 @@
+// Blocked symmetric-sweep factorisation on MFMA and the matching block solve
+// (grids with n >= 64 cells per side, M = n padded block size).
+//
+// Each Schur complement C_j (M x M, SPD) is inverted in place by the sweep
+// operator applied to 16-pivot panels: with V = C[:, K] (the panel columns,
+// M x 16) and P = C[K, K],
+//   C[K, K] <- -P^{-1},  C[I, K] <- V_I P^{-1},  C[R, R] <- C[R, R] - V_R P^{-1} V_R^T,
+// which equals sweeping the 16 pivots one at a time.  The lower-triangle
+// 16 x 16 blocks of C live in MFMA accumulator registers (one wave owns every
+// W-th block); the rank-16 trailing update runs on v_mfma 16x16x4 (FP32 for
+// the FP32/BF16/FP16 factors, FP64 for the FP64 factor); -P^{-1} is formed
+// inside every wave by 16 broadcast sweep steps.
+//
+// Stored factor: per Schur block j, NBL = NB(NB+1)/2 lower blocks b (row by
+// row), each in the MFMA result layout: entry (row drow(l/16, r), col l%16) of
+// block b at offset (b*4 + r)*64 + l.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dtypes.h"
+#include "kernels.h"
+
+namespace mlmc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct vec4_of;
+template <> struct vec4_of<float> { using type = f32x4; };
+template <> struct vec4_of<double> { using type = f64x4; };
+
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f64x4 mfma4(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row (within a 16 x 16 block) of result register r in lane group lr = l/16:
+// FP32 16x16x4 puts D[4 lr + r][l%16] in register r, FP64 16x16x4 puts
+// D[4 r + lr][l%16] there.
+template <typename T> __device__ constexpr int drow(int lr, int r);
+template <> __device__ constexpr int drow<float>(int lr, int r) { return 4 * lr + r; }
+template <> __device__ constexpr int drow<double>(int lr, int r) { return 4 * r + lr; }
+
+// Block ownership: the NB block rows are paired (p, NB-1-p), which together
+// hold NB+1 lower blocks; G waves share a pair, wave w = G p + h taking the
+// pair's blocks h, h+G, h+2G, ...  Returns false for an empty slot.
+template <int NB, int G>
+__device__ inline bool slot_blk(int w, int q, int &I, int &J)
+{
+    const int p = w / G, qq = w % G + G * q;
+    if (qq > NB) return false;
+    if (qq <= p) {
+        I = p;
+        J = qq;
+    } else {
+        I = NB - 1 - p;
+        J = qq - p - 1;
+    }
+    return true;
+}
+
+// Lane-`lane` value of a wave-uniform broadcast (readlane) and the DPP
+// broadcast of lane k of every 16-lane row to the whole row (row_newbcast).
+template <typename T> __device__ inline T bcast(T v, int lane);
+template <> __device__ inline float bcast<float>(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <> __device__ inline double bcast<double>(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int K> __device__ inline float rowbcast(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xF, 0xF, false));
+}
+template <int K> __device__ inline double rowbcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x150 + K, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int K>
+__device__ inline void sweep_step(T p[4], int i, int g, bool &ok)
+{
+    T rk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rk[c] = rowbcast<K>(p[c]);               // P[K][4g+c]
+    const T pik = __shfl(p[K & 3], 16 * (K >> 2) + i, 64);                 // P[i][K]
+    const T d = bcast(p[K & 3], 16 * (K >> 2) + K);                        // P[K][K]
+    ok = ok && (d > (T)0) && isfinite(d);
+    const T inv = recip(d), f = pik * inv;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        T v = fma(-f, rk[c], p[c]);
+        v = (i == K) ? rk[c] * inv : v;
+        if (4 * g + c == K) v = (i == K) ? -inv : f;
+        p[c] = v;
+    }
+}
+
+// -P^{-1} of a 16 x 16 SPD matrix by the sweep operator inside one wave.
+// Lane l = 16 g + i holds P[i][4g .. 4g+3] in p[0..3]; pivot row K reaches
+// each 16-lane row by DPP row broadcast, the pivot column entry P[i][K] by
+// one cross-lane permute.  Returns false if a pivot was not positive and finite.
+template <typename T>
+__device__ inline bool sweep16(T p[4], int l)
+{
+    const int i = l & 15, g = l >> 4;
+    bool ok = true;
+    sweep_step<T, 0>(p, i, g, ok);
+    sweep_step<T, 1>(p, i, g, ok);
+    sweep_step<T, 2>(p, i, g, ok);
+    sweep_step<T, 3>(p, i, g, ok);
+    sweep_step<T, 4>(p, i, g, ok);
+    sweep_step<T, 5>(p, i, g, ok);
+    sweep_step<T, 6>(p, i, g, ok);
+    sweep_step<T, 7>(p, i, g, ok);
+    sweep_step<T, 8>(p, i, g, ok);
+    sweep_step<T, 9>(p, i, g, ok);
+    sweep_step<T, 10>(p, i, g, ok);
+    sweep_step<T, 11>(p, i, g, ok);
+    sweep_step<T, 12>(p, i, g, ok);
+    sweep_step<T, 13>(p, i, g, ok);
+    sweep_step<T, 14>(p, i, g, ok);
+    sweep_step<T, 15>(p, i, g, ok);
+    return ok;
+}
+
+// Wave-scope ordering of LDS accesses between lanes of one wave.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename Tst, int M>
+__global__ __launch_bounds__(32 * M / 16) void k_factor_mfma(int S, const double *__restrict__ beta,
+                                                             const double *__restrict__ gam,
+                                                             Tst *__restrict__ factor,
+                                                             const int *__restrict__ idx,
+                                                             int64_t slot_base,
+                                                             uint32_t *__restrict__ state)
+{
+    using Tac = typename store_traits<Tst>::acc;
+    using V4 = typename vec4_of<Tac>::type;
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = NB / 2, SPW = NB + 1;
+    constexpr int m = M - 1, LD = 17, NT = 64 * W;
+    __shared__ Tac Vb[2][M * LD];      // panel columns C[:, K], double-buffered
+    __shared__ Tac Pw[W][16 * LD];     // per wave: -P^{-1}
+    __shared__ Tac Uw[W][2][16 * LD];  // per wave: U of its two block rows
+    __shared__ Tac bj[2][M], gj[2][M];
+    __shared__ int bad;
+    const int b = blockIdx.x;
+    const int s = idx ? idx[b] : b;
+    const int64_t slot = slot_base + b;
+    const int t = threadIdx.x, l = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lr = l >> 4, lc = l & 15;
+    const double *bs = beta + (size_t)s * m * M;
+    const double *gs = gam + (size_t)s * m * M;
+    Tst *fs = factor + (size_t)slot * m * NBL * 256;
+    if (t == 0) bad = 0;
+    V4 acc[SPW];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) acc[q] = V4{0, 0, 0, 0};
+    // coefficients of block 0 now, of block j+1 prefetched during block j
+    double pb = 0.0, pg = 0.0;
+    if (t < M) {
+        pb = bs[t];
+        pg = gs[t];
+    }
+    bool okw = true;
+
+    for (int j = 0; j < m; ++j) {
+        const int jb = j & 1;
+        if (t < M) {
+            bj[jb][t] = (Tac)pb;
+            gj[jb][t] = (Tac)pg;
+            if (j + 1 < m) {
+                pb = bs[(j + 1) * M + t];
+                pg = gs[(j + 1) * M + t];
+            }
+        }
+        __syncthreads();
+        int wj = w;
+        asm volatile("" : "+s"(wj));  // keep per-slot addresses out of registers across iterations
+        // C_j = T_j + diag(beta_j) (-C_{j-1}^{-1}) diag(beta_j)
+#pragma unroll
+        for (int q = 0; q < SPW; ++q) {
+            int I, J;
+            slot_blk<NB, 1>(wj, q, I, J);
+            const int C = 16 * J + lc;
+            const Tac bc = bj[jb][C], gc = gj[jb][C];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int R = 16 * I + drow<Tac>(lr, r);
+                const Tac gr = gj[jb][R];  // unconditional loads keep the update branch-free
+                Tac tv = (R == C + 1) ? gc : (Tac)0;
+                tv = (C == R + 1) ? gr : tv;
+                tv = (R == C) ? (Tac)1 : tv;
+                acc[q][r] = bj[jb][R] * acc[q][r] * bc + tv;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int K = 0; K < NB; ++K) {
+            int wk = w;
+            asm volatile("" : "+s"(wk));
+            Tac *V = Vb[K & 1];
+            // publish the panel columns C[:, K]
+#pragma unroll
+            for (int q = 0; q < SPW; ++q) {
+                int I, J;
+                slot_blk<NB, 1>(wk, q, I, J);
+                if (J == K) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) V[(16 * I + drow<Tac>(lr, r)) * LD + lc] = acc[q][r];
+                } else if (I == K) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) V[(16 * J + lc) * LD + drow<Tac>(lr, r)] = acc[q][r];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            asm volatile("" : "+s"(wk));
+            // every wave: -P^{-1} (redundantly), then U for its two block rows
+            Tac *P = Pw[wk];
+            {
+                Tac p[4];  // lane 16 g + i: P[i][4g .. 4g+3]
+#pragma unroll
+                for (int c = 0; c < 4; ++c) p[c] = V[(16 * K + lc) * LD + 4 * lr + c];
+                okw = sweep16(p, l) && okw;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) P[lc * LD + 4 * lr + c] = p[c];
+            }
+            wave_lds_sync();
+            // -P^{-1}[4kc+lr][lc] (= [lc][4kc+lr] by symmetry) is the B operand of U and
+            // the A operand of row K; U rows are re-read in the A layout per block below
+            // (operands are re-read from LDS rather than held, to bound registers).
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int row = x ? NB - 1 - wk : wk;
+                V4 u = V4{0, 0, 0, 0};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+                    u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Uw[wk][x][drow<Tac>(lr, r) * LD + lc] = u[r];
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int q = 0; q < SPW; ++q) {
+                int I, J;
+                slot_blk<NB, 1>(wk, q, I, J);
+                const Tac *U = Uw[wk][(q <= wk) ? 0 : 1];  // which of the wave's two rows
+                if (I != K && J != K) {
+                    // C[I,J] += U_I V_J^T
+                    Tac av[4], bv[4];
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) {
+                        av[kc] = U[lc * LD + 4 * kc + lr];
+                        bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
+                    }
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
+                } else if (I == K && J == K) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[q][r] = P[drow<Tac>(lr, r) * LD + lc];
+                } else if (J == K) {
+                    // C[I,K] = V_I P^{-1} = -U_I
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[q][r] = -U[drow<Tac>(lr, r) * LD + lc];
+                } else {
+                    // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
+                    V4 z = V4{0, 0, 0, 0};
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
+                    acc[q] = -z;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // store -C_j^{-1}
+        asm volatile("" : "+s"(wj));
+        Tst *fb = fs + (size_t)j * NBL * 256;
+#pragma unroll
+        for (int q = 0; q < SPW; ++q) {
+            int I, J;
+            slot_blk<NB, 1>(wj, q, I, J);
+            const int bb = I * (I + 1) / 2 + J;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) fb[(bb * 4 + r) * 64 + l] = store_traits<Tst>::store(acc[q][r]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (!okw) bad = 1;
+    __syncthreads();
+    if (t == 0 && bad) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
+}
+
+// ------------------------------------------------------------------ block solve
+
+// Inclusive scan over the 16 lanes of a DPP row: lane 15 of each row ends
+// with the row total.
+template <int CTRL>
+__device__ inline float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float row16_total(float v)
+{
+    v += dpp_f32<0x111>(v);
+    v += dpp_f32<0x112>(v);
+    v += dpp_f32<0x114>(v);
+    v += dpp_f32<0x118>(v);
+    return v;
+}
+__device__ inline double row16_total(double v)
+{
+    v += dpp_f64<0x111>(v);
+    v += dpp_f64<0x112>(v);
+    v += dpp_f64<0x114>(v);
+    v += dpp_f64<0x118>(v);
+    return v;
+}
+
+// x (+)= S Ahat^{-1} S rhs with the block-layout factor; one workgroup per
+// sample, wave w handles blocks w, w+W, ...; the next Schur block's factor
+// entries are loaded while the current one is applied.
+template <typename Tst, int M, int G, bool PREF>
+__global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__restrict__ sc,
+                                                      const double *__restrict__ beta,
+                                                      const Tst *__restrict__ factor,
+                                                      const double *__restrict__ rhs,
+                                                      double rhs_const, double *__restrict__ x,
+                                                      int accumulate, double *__restrict__ zbuf,
+                                                      const int *__restrict__ idx,
+                                                      int64_t slot_base,
+                                                      const uint32_t *__restrict__ state)
+{
+    using Tac = typename store_traits<Tst>::acc;
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = G * NB / 2, SPW = (NB + G) / G;
+    constexpr int m = M - 1, NT = 64 * W;
+    static_assert(NT >= M, "one vector entry per thread");
+    __shared__ Tac g[M], xc[M];
+    __shared__ Tac part[W][M];  // per-wave partial products, summed in wave order (deterministic)
+    const int b = blockIdx.x;
+    const int s = idx ? idx[b] : b;
+    if (state && (state[s] & ST_DONE)) return;
+    const int64_t slot = slot_base + b;
+    const int t = threadIdx.x, l = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lr = l >> 4, lc = l & 15;
+    const size_t vo = (size_t)s * m * M;
+    const double *scs = sc + vo, *bs = beta + vo;
+    const double *rs = rhs ? rhs + vo : nullptr;
+    double *xs = x + vo, *zs = zbuf + vo;
+    const Tst *fs = factor + (size_t)slot * m * NBL * 256;
+
+    Tst cur[SPW][4], nxt[PREF ? SPW : 1][4];
+    auto load = [&](int j, Tst (&dst)[SPW][4]) {
+        int wq = w;
+        asm volatile("" : "+s"(wq));
+        const Tst *fb = fs + (size_t)j * NBL * 256;
+#pragma unroll
+        for (int q = 0; q < SPW; ++q) {
+            int I, J;
+            if (!slot_blk<NB, G>(wq, q, I, J)) continue;
+            const int bb = I * (I + 1) / 2 + J;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[q][r] = fb[(bb * 4 + r) * 64 + l];
+        }
+    };
+    // part[w] = this wave's share of F g (symmetric block factor in `cur`):
+    // row and column contributions accumulate in part[w] slot by slot, each
+    // instruction's lanes touching distinct entries (fixed order).
+    auto apply = [&]() {
+        int wq = w;
+        asm volatile("" : "+s"(wq));
+        Tac *pw = part[wq];
+        for (int i = l; i < M; i += 64) pw[i] = 0;
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < SPW; ++q) {
+            int I, J;
+            if (!slot_blk<NB, G>(wq, q, I, J)) continue;
+            Tac f[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f[r] = store_traits<Tst>::load(cur[q][r]);
+            const Tac gj = g[16 * J + lc];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const Tac v = row16_total(f[r] * gj);
+                if (lc == 15) pw[16 * I + drow<Tac>(lr, r)] += v;
+            }
+            if (I != J) {
+                Tac c = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c = fma(f[r], g[16 * I + drow<Tac>(lr, r)], c);
+                c += __shfl_xor(c, 16, 64);
+                c += __shfl_xor(c, 32, 64);
+                if (lr == 0) pw[16 * J + lc] += c;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+    };
+    auto gather = [&](int i) {
+        Tac v = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) v += part[ww][i];
+        return v;
+    };
+    auto copy_next = [&]() {
+        if constexpr (PREF) {
+#pragma unroll
+            for (int q = 0; q < SPW; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cur[q][r] = nxt[q][r];
+        }
+    };
+
+    // Thread t < M owns vector entry t of every block (NT >= M); its inputs of
+    // the next block are loaded one block ahead.
+    const bool own = t < M;
+    // forward: z_j = -F_j (s_j r_j - beta_j z_{j-1})
+    double v_sc = 0.0, v_b = 0.0, v_r = 0.0;
+    if (own) {
+        xc[t] = 0;
+        v_sc = scs[t];
+        v_b = bs[t];
+        v_r = rs ? rs[t] : (t < m ? rhs_const : 0.0);
+    }
+    if (PREF) load(0, cur);
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        if constexpr (PREF) {
+            if (j + 1 < m) load(j + 1, nxt);
+        } else {
+            load(j, cur);
+        }
+        if (own) {
+            g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc[t];
+            if (j + 1 < m) {
+                v_sc = scs[(j + 1) * M + t];
+                v_b = bs[(j + 1) * M + t];
+                v_r = rs ? rs[(j + 1) * M + t] : (t < m ? rhs_const : 0.0);
+            }
+        }
+        __syncthreads();
+        apply();
+        __syncthreads();
+        if (own) {
+            const Tac z = -gather(t);
+            xc[t] = z;
+            zs[j * M + t] = (double)z;
+        }
+        __syncthreads();
+        if (j + 1 < m) copy_next();
+    }
+    // back: x_{m-1} = z_{m-1}; x_j = z_j + F_j (beta_{j+1} x_{j+1})
+    double v_z = 0.0, v_x = 0.0;
+    if (own) {
+        const double d = scs[(m - 1) * M + t] * (double)xc[t];
+        xs[(m - 1) * M + t] = accumulate ? xs[(m - 1) * M + t] + d : d;
+        if (m >= 2) {
+            v_b = bs[(m - 1) * M + t];
+            v_z = zs[(m - 2) * M + t];
+            v_sc = scs[(m - 2) * M + t];
+            v_x = accumulate ? xs[(m - 2) * M + t] : 0.0;
+        }
+    }
+    if (PREF && m >= 2) load(m - 2, cur);
+    for (int j = m - 2; j >= 0; --j) {
+        if constexpr (PREF) {
+            if (j > 0) load(j - 1, nxt);
+        } else {
+            load(j, cur);
+        }
+        const double c_sc = v_sc, c_x = v_x;
+        const Tac c_z = (Tac)v_z;
+        if (own) {
+            g[t] = (Tac)v_b * xc[t];
+            if (j > 0) {
+                v_b = bs[j * M + t];
+                v_z = zs[(j - 1) * M + t];
+                v_sc = scs[(j - 1) * M + t];
+                v_x = accumulate ? xs[(j - 1) * M + t] : 0.0;
+            }
+        }
+        __syncthreads();
+        apply();
+        __syncthreads();
+        if (own) {
+            const Tac xv = c_z + gather(t);
+            xc[t] = xv;
+            const double d = c_sc * (double)xv;
+            xs[j * M + t] = accumulate ? c_x + d : d;
+        }
+        __syncthreads();
+        if (j > 0) copy_next();
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+namespace {
+// Solve configuration: waves per row pair (G) and register double-buffering
+// of the next Schur block (PREF), within the register budget.
+template <typename Tst, int M> struct solve_cfg { static constexpr int G = 1; static constexpr bool PREF = true; };
+template <> struct solve_cfg<double, 64> { static constexpr int G = 2; static constexpr bool PREF = true; };
+template <> struct solve_cfg<double, 128> { static constexpr int G = 2; static constexpr bool PREF = true; };
+template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static constexpr bool PREF = false; };
+
+template <typename Tst, int M>
+hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const int *idx,
+              int64_t slot_base, uint32_t *state, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(32 * M / 16), 0, st, nb, beta, gam,
+                       (Tst *)factor, idx, slot_base, state);
+    return hipGetLastError();
+}
+
+template <typename Tst, int M>
+hipError_t ls(int nb, const double *sc, const double *beta, const void *factor, const double *rhs,
+              double rc, double *x, int acc, double *zbuf, const int *idx, int64_t slot_base,
+              const uint32_t *state, hipStream_t st)
+{
+    constexpr int G = solve_cfg<Tst, M>::G;
+    constexpr bool PREF = solve_cfg<Tst, M>::PREF;
+    hipLaunchKernelGGL((k_solve_blk<Tst, M, G, PREF>), dim3(nb), dim3(32 * G * M / 16), 0, st, sc, beta,
+                       (const Tst *)factor, rhs, rc, x, acc, zbuf, idx, slot_base, state);
+    return hipGetLastError();
+}
+
+template <typename Tst>
+hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *factor, const int *idx,
+                int64_t slot_base, uint32_t *state, hipStream_t st)
+{
+    switch (M) {
+    case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Tst>
+hipError_t ls_m(int M, int nb, const double *sc, const double *beta, const void *factor,
+                const double *rhs, double rc, double *x, int acc, double *zbuf, const int *idx,
+                int64_t slot_base, const uint32_t *state, hipStream_t st)
+{
+    switch (M) {
+    case 64: return ls<Tst, 64>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 128: return ls<Tst, 128>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 256: return ls<Tst, 256>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
+                             void *factor, const int *idx, int64_t slot_base, uint32_t *state,
+                             hipStream_t st)
+{
+    switch (dtype) {
+    case 0: return lf_m<double>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 1: return lf_m<float>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 3: return lf_m<__half>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve_blk(int dtype, int n, int nblocks, const double *sc, const double *beta,
+                            const void *factor, const double *rhs, double rhs_const, double *x,
+                            int accumulate, double *zbuf, const int *idx, int64_t slot_base,
+                            const uint32_t *state, hipStream_t st)
+{
+    switch (dtype) {
+    case 0: return ls_m<double>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    case 1: return ls_m<float>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    case 2: return ls_m<__hip_bfloat16>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    case 3: return ls_m<__half>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mlmc

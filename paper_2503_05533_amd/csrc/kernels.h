@@ -34,6 +34,13 @@ hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const d
                         const void *factor, const double *rhs, double rhs_const, double *x,
                         int accumulate, double *zbuf, const int *idx, int64_t slot_base,
                         const uint32_t *state, hipStream_t st);
+hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
+                             void *factor, const int *idx, int64_t slot_base, uint32_t *state,
+                             hipStream_t st);
+hipError_t launch_solve_blk(int dtype, int n, int nblocks, const double *sc, const double *beta,
+                            const void *factor, const double *rhs, double rhs_const, double *x,
+                            int accumulate, double *zbuf, const int *idx, int64_t slot_base,
+                            const uint32_t *state, hipStream_t st);
 hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, const double *x,
                            double *r, double eps, int trip, int imax, int direct, const int *idx,
                            uint32_t *state, double *relres, double *q, int32_t *iters,

@@ -231,7 +231,10 @@ __global__ __launch_bounds__(NT) void k_factor(int S, const double *__restrict__
 #pragma unroll
                 for (int c = 0; c < TR; ++c) {
                     const int gi = i0 + r, gc = j0 + c;
-                    Tac tv = gi == gc ? (Tac)1 : (gi == gc + 1 ? gj[gc] : (gc == gi + 1 ? gj[gi] : (Tac)0));
+                    const Tac g_i = gj[gi], g_c = gj[gc];  // unconditional loads keep this branch-free
+                    Tac tv = (gi == gc + 1) ? g_c : (Tac)0;
+                    tv = (gc == gi + 1) ? g_i : tv;
+                    tv = (gi == gc) ? (Tac)1 : tv;
                     tile[r][c] = bj[gi] * tile[r][c] * bj[gc] + tv;
                 }
         }
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(NT) void k_factor(int S, const double *__restrict__
                 __syncthreads();
                 if (active) {
                     const Tac d = buf[k];
-                    const Tac inv = (Tac)1 / d;
+                    const Tac inv = recip(d);
                     Tac v[TR], cc[TR];
 #pragma unroll
                     for (int r = 0; r < TR; ++r) v[r] = buf[i0 + r] * inv;
@@ -564,9 +567,6 @@ template <int M>
 struct tile_cfg;
 template <> struct tile_cfg<16> { static constexpr int TR = 2; };
 template <> struct tile_cfg<32> { static constexpr int TR = 4; };
-template <> struct tile_cfg<64> { static constexpr int TR = 8; };
-template <> struct tile_cfg<128> { static constexpr int TR = 8; };
-template <> struct tile_cfg<256> { static constexpr int TR = 8; };
 
 template <typename Tst, int M>
 hipError_t launch_factor_t(int nblocks, const double *beta, const double *gam, void *factor,
@@ -598,9 +598,6 @@ hipError_t launch_factor_m(int M, int nb, const double *beta, const double *gam,
     switch (M) {
     case 16: return launch_factor_t<Tst, 16>(nb, beta, gam, factor, idx, slot_base, state, st);
     case 32: return launch_factor_t<Tst, 32>(nb, beta, gam, factor, idx, slot_base, state, st);
-    case 64: return launch_factor_t<Tst, 64>(nb, beta, gam, factor, idx, slot_base, state, st);
-    case 128: return launch_factor_t<Tst, 128>(nb, beta, gam, factor, idx, slot_base, state, st);
-    case 256: return launch_factor_t<Tst, 256>(nb, beta, gam, factor, idx, slot_base, state, st);
     }
     return hipErrorInvalidValue;
 }
@@ -613,9 +610,6 @@ hipError_t launch_solve_m(int M, int nb, const double *sc, const double *beta, c
     switch (M) {
     case 16: return launch_solve_t<Tst, 16>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 32: return launch_solve_t<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 64: return launch_solve_t<Tst, 64>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 128: return launch_solve_t<Tst, 128>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 256: return launch_solve_t<Tst, 256>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     }
     return hipErrorInvalidValue;
 }
@@ -626,6 +620,10 @@ namespace mlmc {
 size_t factor_entries_per_sample(int n)
 {
     const int M = n;
+    if (M >= 64) {
+        const int NB = M / 16;
+        return (size_t)(n - 1) * (NB * (NB + 1) / 2) * 256;
+    }
     int TR = M <= 16 ? 2 : (M <= 32 ? 4 : 8);
     const int Tn = M / TR, T = Tn * (Tn + 1) / 2;
     return (size_t)(n - 1) * T * TR * TR;
@@ -672,6 +670,7 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, cons
                          hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
+    if (n >= 64) return launch_factor_blk(dtype, n, nblocks, beta, gam, factor, idx, slot_base, state, st);
     switch (dtype) {
     case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
     case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
@@ -687,6 +686,9 @@ hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const d
                         const uint32_t *state, hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
+    if (n >= 64)
+        return launch_solve_blk(dtype, n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate,
+                                zbuf, idx, slot_base, state, st);
     switch (dtype) {
     case 0: return launch_solve_m<double>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
     case 1: return launch_solve_m<float>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
