@@ -60,8 +60,10 @@ typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3 } mlmc_dt
  *                  (FP32 arithmetic), FP64 update, stop when
  *                  ||b - A x||_2 / ||b||_2 < eps (strict), at most
  *                  ir_max_iter corrections (Sec. 2.3).
- *   MLMC_MINRES    Jacobi-scaled MINRES in FP64 (Sec. 2.2) stopped on the
- *                  unscaled relative residual < eps. */
+ *   MLMC_MINRES    Jacobi-scaled MINRES in FP64 (Sec. 2.2) stopped when the
+ *                  recurrence estimate of the scaled relative residual is
+ *                  below eps and the true unscaled FP64 relative residual
+ *                  ||b - A x||/||b|| < eps, at most minres_max_iter steps. */
 typedef enum { MLMC_DIRECT = 0, MLMC_DIRECT_IR = 1, MLMC_MINRES = 2 } mlmc_solver;
 
 typedef struct {
@@ -182,22 +184,26 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
                   mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream);
 
 /* Adjoint gradient dQ/dxi on grid `level` for the n samples of the
- * preceding mlmc_solve on the same workspace (which must have used
- * MLMC_DIRECT or MLMC_DIRECT_IR): solves A lambda = h^2 1 with the stored
- * factor and FP64 refinement to eps_adjoint, forms
- * dQ/dZ_e = -sum_{edges (e,o)} (lambda_e - lambda_o)(u_e - u_o)
- *          2 a_o^2 a_e / (a_e + a_o)^2
- * and grad_xi[s,k] = grad_q[s] * sum_e dQ/dZ_e Phi[e,k].
- * grad_q_dev[n] may be NULL (taken as 1). */
+ * preceding mlmc_solve on the same workspace with the same opts (solver
+ * MLMC_DIRECT or MLMC_DIRECT_IR; the stored factor and solution are reused):
+ * solves A lambda = h^2 1 (the gradient of Q = h^2 sum u in u) with the
+ * stored factor and FP64 refinement to the relative residual eps_adjoint
+ * (non-converging samples are re-solved with an FP64 factor), forms
+ *   dQ/dZ_e = -sum_{edges (e,o)} (lambda_e - lambda_o)(u_e - u_o)
+ *             2 a_o^2 a_e / (a_e + a_o)^2      (u, lambda = 0 on the boundary)
+ * and grad_xi[s,k] = grad_q[s] * sum_e dQ/dZ_e Phi[e,k]  ([n x K] FP64).
+ * grad_q_dev[n] may be NULL (taken as 1).  xi_dev must be the forward's xi.
+ * Not part of the paper: the exact derivative of the discrete Q. */
 int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
-              const double *grad_q_dev, double eps_adjoint, void *ws_dev, size_t ws_bytes,
-              double *grad_xi_dev, void *stream);
+              const double *grad_q_dev, const mlmc_level_opts *opts, double eps_adjoint,
+              void *ws_dev, size_t ws_bytes, double *grad_xi_dev, void *stream);
 
 /* Kernel timing for measurement.  While enabled, the library brackets each
  * launch of the field, assembly, factor, solve and residual kernels with HIP
  * events on the caller's stream and records (kernel kind, grid n, samples).
  * mlmc_profile_read synchronises, and for kind (0 field, 1 assembly,
- * 2 factor, 3 solve, 4 residual) and grid n returns the summed device time,
+ * 2 factor, 3 refinement (initial solve + Algorithm 2.1 loop), 4 residual,
+ * 5 MINRES) and grid n returns the summed device time,
  * the number of launches and the summed samples over all recorded launches,
  * then keeps the records (reset with mlmc_profile(ctx, 1) again). */
 int mlmc_profile(mlmc_ctx *ctx, int32_t enable);

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmlmc.so")
-SOURCES = ["csrc/kernels.hip", "csrc/factor_mfma.hip", "csrc/api.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/factor_mfma.hip", "csrc/minres.hip", "csrc/api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -208,7 +208,8 @@ struct grid_layout {
     size_t vec;  // padded vector length per sample
     size_t off_a, off_sc, off_gam, off_beta, off_x, off_r, off_z, off_lam, off_gz;
     size_t off_factor, off_promo, off_state, off_relres, off_q, off_iters, off_idx;
-    size_t off_mr;  // MINRES vectors (5 per sample)
+    size_t off_mr;  // MINRES vectors (7 per sample)
+    size_t off_cnt; // device counters (promotion)
     int64_t promo_slots;
     size_t bytes;
 };
@@ -236,21 +237,23 @@ grid_layout make_layout(int n, int64_t S, const mlmc_level_opts &o)
     const bool direct = o.solver != MLMC_MINRES;
     const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
     L.off_factor = take(direct ? S * factor_entries_per_sample(n) * dtype_bytes(dt) : 0);
-    L.promo_slots = (direct && dt != MLMC_F64 && o.promote) ? std::max<int64_t>(1, (S + 15) / 16) : 0;
+    // every sample can be re-solved with an FP64 factor without a host round trip
+    L.promo_slots = (direct && dt != MLMC_F64 && o.promote) ? S : 0;
     L.off_promo = take(L.promo_slots * factor_entries_per_sample(n) * 8);
-    L.off_mr = take(o.solver == MLMC_MINRES ? 5 * S * L.vec * 8 : 0);
+    L.off_mr = take(o.solver == MLMC_MINRES ? 7 * S * L.vec * 8 : 0);
     L.off_state = take(S * 4);
     L.off_relres = take(S * 8);
     L.off_q = take(S * 8);
     L.off_iters = take(S * 4);
     L.off_idx = take(S * 4);
+    L.off_cnt = take(64);
     L.bytes = off;
     return L;
 }
 
 struct level_layout {
     grid_layout fine, coarse;
-    size_t off_fine, off_coarse, off_qf, off_qc, off_y, bytes;
+    size_t off_fine, off_coarse, off_qf, off_qc, off_y, off_sums, bytes;
 };
 
 level_layout make_level_layout(const mlmc_config &c, int level, int64_t S, const mlmc_level_opts &o)
@@ -272,6 +275,8 @@ level_layout make_level_layout(const mlmc_config &c, int level, int64_t S, const
     off += align256(S * 8);
     L.off_y = off;
     off += align256(S * 8);
+    L.off_sums = off;
+    off += 256;
     L.bytes = off;
     return L;
 }
@@ -295,35 +300,63 @@ int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o)
     return MLMC_OK;
 }
 
-// Refinement loop of Algorithm 2.1 for the samples in idx (or all when idx is
-// NULL): residual -> stop test -> correction solve -> update.  Stops early
-// when no sample is active.
-int ir_loop(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dtype, const void *factor,
-            int64_t slot_base, const int *idx, int nb, double eps, double *q, int32_t *iters,
-            hipStream_t st)
+// Initial solve + Algorithm 2.1 on the stored factor for all samples of a
+// grid (solution into x, rhs h^2 fconst), then, for a low-precision factor,
+// device-side compaction of the samples that did not converge and a second
+// pass with an FP64 factor for them.  Asynchronous on `st`.
+int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, double fconst,
+           double eps, double *x, double *q, int32_t *iters, hipStream_t st)
 {
-    const int imax = ctx->cfg.ir_max_iter;
-    for (int trip = 0; trip <= imax; ++trip) {
-        HIPCHK(hipMemsetAsync(ctx->d_counter, 0, sizeof(int), st));
-        PROF(4, L.n, nb, launch_residual(L.n, nb, ctx->cfg.f, at<double>(ws, L.off_a), at<double>(ws, L.off_x),
-                               at<double>(ws, L.off_r), eps, trip, imax, 0, idx,
-                               at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), q, iters,
-                               ctx->d_counter, st));
-        if (trip == imax) break;
-        HIPCHK(hipMemcpyAsync(ctx->h_counter, ctx->d_counter, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (*ctx->h_counter == 0) break;
-        PROF(3, L.n, nb, launch_solve(dtype, L.n, nb, at<double>(ws, L.off_sc), at<double>(ws, L.off_beta),
-                            factor, at<double>(ws, L.off_r), 0.0, at<double>(ws, L.off_x), 1,
-                            at<double>(ws, L.off_z), idx, slot_base, at<uint32_t>(ws, L.off_state),
-                            st));
+    const int n = L.n, S = (int)L.S;
+    uint32_t *state = at<uint32_t>(ws, L.off_state);
+    double *relres = at<double>(ws, L.off_relres);
+    ir_args g{};
+    g.n = n;
+    g.nblocks = S;
+    g.fconst = fconst;
+    g.a = at<double>(ws, L.off_a);
+    g.sc = at<double>(ws, L.off_sc);
+    g.beta = at<double>(ws, L.off_beta);
+    g.factor = at<void>(ws, L.off_factor);
+    g.x = x;
+    g.r = at<double>(ws, L.off_r);
+    g.z = at<double>(ws, L.off_z);
+    g.eps = eps;
+    g.imax = direct ? 0 : ctx->cfg.ir_max_iter;
+    g.direct = direct ? 1 : 0;
+    g.state = state;
+    g.relres = relres;
+    g.q = q;
+    g.iters = iters;
+    PROF(3, n, S, launch_ir(dt, g, st));
+    if (L.promo_slots > 0 && dt != MLMC_F64) {
+        int *idx = at<int>(ws, L.off_idx);
+        int *cnt = at<int>(ws, L.off_cnt);
+        const int np = (int)L.promo_slots;
+        void *pf = at<void>(ws, L.off_promo);
+        HIPCHK(launch_zero_int(cnt, 1, st));
+        HIPCHK(launch_collect(S, state, idx, cnt, st));
+        HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
+        PROF(2, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
+                                     pf, idx, cnt, 0, state, st));
+        ir_args p = g;
+        p.nblocks = np;
+        p.factor = pf;
+        p.idx = idx;
+        p.count = cnt;
+        p.imax = ctx->cfg.ir_max_iter;
+        p.direct = 0;
+        PROF(3, n, np, launch_ir(MLMC_F64, p, st));
     }
     return MLMC_OK;
 }
 
-int minres_solve(mlmc_ctx *ctx, const grid_layout &L, void *ws, double eps, hipStream_t st);
-
-// Solve one batch on one grid.  q (S doubles, device) receives Q.
+// Solve one batch on one grid, asynchronously on `st`: field GEMM, scaled
+// coefficients, factorisation, then one per-sample kernel running the
+// initial solve and the Algorithm 2.1 loop.  Samples that do not converge
+// (promote != 0, low-precision factor) are compacted on the device and
+// re-solved with an FP64 factor in a second pass, up to promo_slots of them.
+// q (S doubles, device) receives Q; iters the corrections per sample.
 int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
                const mlmc_level_opts &o, double eps, void *ws, double *q, int32_t *iters,
                hipStream_t st)
@@ -331,56 +364,24 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     const int n = L.n, S = (int)L.S, K = ctx->cfg.K, P = (n + 1) * (n + 1);
     if (S == 0) return MLMC_OK;
     double *a = at<double>(ws, L.off_a);
+    double *sc = at<double>(ws, L.off_sc), *gam = at<double>(ws, L.off_gam);
+    double *beta = at<double>(ws, L.off_beta);
+    uint32_t *state = at<uint32_t>(ws, L.off_state);
+    double *relres = at<double>(ws, L.off_relres);
     PROF(0, n, S, launch_field(S, K, P, xi, ctx->phit[level], a, st));
-    PROF(1, n, S, launch_coeffs(n, S, a, at<double>(ws, L.off_sc), at<double>(ws, L.off_gam),
-                         at<double>(ws, L.off_beta), st));
-    HIPCHK(launch_init_state(S, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), st));
+    PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, st));
+    HIPCHK(launch_init_state(S, state, relres, st));
     if (o.solver == MLMC_MINRES) {
-        int rc = minres_solve(ctx, L, ws, eps, st);
-        if (rc) return rc;
-        PROF(4, n, S, launch_residual(n, S, ctx->cfg.f, a, at<double>(ws, L.off_x), nullptr, eps, 0, 0, 0,
-                               nullptr, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres),
-                               q, nullptr, nullptr, st));
+        PROF(5, n, S, launch_minres(n, S, ctx->cfg.f, a, sc, gam, beta, at<double>(ws, L.off_x),
+                                    at<double>(ws, L.off_r), at<double>(ws, L.off_mr), eps,
+                                    ctx->cfg.minres_max_iter, state, relres, q, iters, st));
         return MLMC_OK;
     }
-    const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
+    const bool direct = o.solver == MLMC_DIRECT;
+    const int dt = direct ? MLMC_F64 : o.factor_dtype;
     void *factor = at<void>(ws, L.off_factor);
-    PROF(2, n, S, launch_factor(dt, n, S, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam), factor,
-                         nullptr, 0, at<uint32_t>(ws, L.off_state), st));
-    PROF(3, n, S, launch_solve(dt, n, S, at<double>(ws, L.off_sc), at<double>(ws, L.off_beta), factor,
-                        nullptr, (1.0 / n) * (1.0 / n) * ctx->cfg.f, at<double>(ws, L.off_x), 0,
-                        at<double>(ws, L.off_z), nullptr, 0, nullptr, st));
-    if (o.solver == MLMC_DIRECT) {
-        PROF(4, n, S, launch_residual(n, S, ctx->cfg.f, a, at<double>(ws, L.off_x), nullptr, eps, 0, 0, 1,
-                               nullptr, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres),
-                               q, iters, nullptr, st));
-        return MLMC_OK;
-    }
-    int rc = ir_loop(ctx, L, ws, dt, factor, 0, nullptr, S, eps, q, iters, st);
-    if (rc) return rc;
-    if (L.promo_slots > 0) {
-        // samples that did not converge are re-solved with an FP64 factor
-        int *idx = at<int>(ws, L.off_idx);
-        HIPCHK(hipMemsetAsync(ctx->d_counter + 1, 0, sizeof(int), st));
-        HIPCHK(launch_collect(S, at<uint32_t>(ws, L.off_state), idx, ctx->d_counter + 1, st));
-        HIPCHK(hipMemcpyAsync(ctx->h_counter + 1, ctx->d_counter + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        const int np = ctx->h_counter[1];
-        void *pf = at<void>(ws, L.off_promo);
-        for (int p0 = 0; p0 < np; p0 += (int)L.promo_slots) {
-            const int nb = std::min<int>((int)L.promo_slots, np - p0);
-            const int *sub = idx + p0;
-            HIPCHK(launch_reset_subset(nb, sub, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), st));
-            PROF(2, n, nb, launch_factor(MLMC_F64, n, nb, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
-                                 pf, sub, 0, at<uint32_t>(ws, L.off_state), st));
-            PROF(3, n, nb, launch_solve(MLMC_F64, n, nb, at<double>(ws, L.off_sc), at<double>(ws, L.off_beta), pf,
-                                nullptr, (1.0 / n) * (1.0 / n) * ctx->cfg.f, at<double>(ws, L.off_x), 0,
-                                at<double>(ws, L.off_z), sub, 0, nullptr, st));
-            rc = ir_loop(ctx, L, ws, MLMC_F64, pf, 0, sub, nb, eps, q, iters, st);
-            if (rc) return rc;
-        }
-    }
-    return MLMC_OK;
+    PROF(2, n, S, launch_factor(dt, n, S, beta, gam, factor, nullptr, nullptr, 0, state, st));
+    return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, at<double>(ws, L.off_x), q, iters, st);
 }
 
 }  // namespace
@@ -517,9 +518,10 @@ int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
     if (rc) return rc;
     if (u_dev) HIPCHK(launch_unpad(L.n, (int)n, at<double>(ws, L.off_x), u_dev, st));
     if (iters_dev) HIPCHK(hipMemcpyAsync(iters_dev, it, n * 4, hipMemcpyDeviceToDevice, st));
+    double *sums = at<double>(ws_dev, LL.off_sums);
     HIPCHK(launch_pair_sums((int)n, q_dev, nullptr, at<uint32_t>(ws, L.off_state), nullptr, it, nullptr,
-                            status_dev, ctx->d_sums, st));
-    HIPCHK(hipMemcpyAsync(ctx->h_sums, ctx->d_sums, 7 * 8, hipMemcpyDeviceToHost, st));
+                            status_dev, sums, st));
+    HIPCHK(hipMemcpyAsync(ctx->h_sums, sums, 7 * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return ctx->h_sums[5] > 0 ? MLMC_ENOCONV : MLMC_OK;
 }
@@ -555,12 +557,13 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
         if (rc) return rc;
         stc = at<uint32_t>(wc, LL.coarse.off_state);
     }
+    double *sums = at<double>(ws_dev, LL.off_sums);
     if (n > 0)
         HIPCHK(launch_pair_sums((int)n, qf, level > 0 ? qc : nullptr, at<uint32_t>(wf, LL.fine.off_state),
-                                stc, at<int32_t>(wf, LL.fine.off_iters), y_dev, status_dev, ctx->d_sums, st));
+                                stc, at<int32_t>(wf, LL.fine.off_iters), y_dev, status_dev, sums, st));
     if (stats_host) {
         HIPCHK(hipEventRecord(ctx->ev1, st));
-        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, ctx->d_sums, 7 * 8, hipMemcpyDeviceToHost, st));
+        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, sums, 7 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -740,19 +743,36 @@ int mlmc_profile_read(mlmc_ctx *ctx, int32_t kind, int32_t n, double *total_ms, 
 }
 
 int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, const double *grad_q_dev,
-              double eps_adjoint, void *ws_dev, size_t ws_bytes, double *grad_xi_dev, void *stream)
+              const mlmc_level_opts *opts, double eps_adjoint, void *ws_dev, size_t ws_bytes,
+              double *grad_xi_dev, void *stream)
 {
-    (void)ctx; (void)level; (void)n; (void)xi_dev; (void)grad_q_dev; (void)eps_adjoint;
-    (void)ws_dev; (void)ws_bytes; (void)grad_xi_dev; (void)stream;
-    return fail(ctx, MLMC_ENOTIMPL, "grad not implemented yet");
+    int rc = check_level(ctx, level);
+    if (rc) return rc;
+    if ((rc = check_opts(ctx, opts))) return rc;
+    if (opts->solver == MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not MINRES)");
+    if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
+    if (n == 0) return MLMC_OK;
+    if (!xi_dev || !ws_dev || !grad_xi_dev || !(eps_adjoint > 0.0))
+        return fail(ctx, MLMC_EINVAL, "grad: bad arguments");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
+    if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
+    hipStream_t st = (hipStream_t)stream;
+    const grid_layout &L = LL.fine;
+    void *ws = at<void>(ws_dev, LL.off_fine);
+    const int S = (int)n, nn = L.n, K = ctx->cfg.K, P = (nn + 1) * (nn + 1);
+    const bool direct = opts->solver == MLMC_DIRECT;
+    const int dt = direct ? MLMC_F64 : opts->factor_dtype;
+    // adjoint state: A lambda = dQ/du = h^2 1 (rhs with fconst = 1), refined in FP64
+    HIPCHK(launch_init_state(S, at<uint32_t>(ws, L.off_state), at<double>(ws, L.off_relres), st));
+    double *lam = at<double>(ws, L.off_lam);
+    rc = refine(ctx, L, ws, dt, false, 1.0, eps_adjoint, lam, at<double>(ws, L.off_q), nullptr, st);
+    if (rc) return rc;
+    double *gz = at<double>(ws, L.off_gz);
+    HIPCHK(launch_adjoint_gz(nn, S, at<double>(ws, L.off_a), at<double>(ws, L.off_x), lam, gz, st));
+    HIPCHK(launch_grad_gemm(S, K, P, gz, ctx->phit[level], grad_q_dev, grad_xi_dev, st));
+    return MLMC_OK;
 }
 
 }  // extern "C"
 
-namespace {
-int minres_solve(mlmc_ctx *ctx, const grid_layout &L, void *ws, double eps, hipStream_t st)
-{
-    (void)L; (void)ws; (void)eps; (void)st;
-    return fail(ctx, MLMC_ENOTIMPL, "MINRES not implemented yet");
-}
-}  // namespace

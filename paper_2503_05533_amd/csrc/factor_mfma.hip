@@ -19,6 +19,7 @@
 
 #include "dtypes.h"
 #include "kernels.h"
+#include "ir_common.h"
 
 namespace mlmc {
 
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(32 * M / 16) void k_factor_mfma(int S, const double
                                                              const double *__restrict__ gam,
                                                              Tst *__restrict__ factor,
                                                              const int *__restrict__ idx,
+                                                             const int *__restrict__ count,
                                                              int64_t slot_base,
                                                              uint32_t *__restrict__ state)
 {
@@ -161,6 +163,7 @@ __global__ __launch_bounds__(32 * M / 16) void k_factor_mfma(int S, const double
     __shared__ Tac bj[2][M], gj[2][M];
     __shared__ int bad;
     const int b = blockIdx.x;
+    if (count && b >= *count) return;
     const int s = idx ? idx[b] : b;
     const int64_t slot = slot_base + b;
     const int t = threadIdx.x, l = t & 63;
@@ -342,19 +345,15 @@ __device__ inline double row16_total(double v)
     return v;
 }
 
-// x (+)= S Ahat^{-1} S rhs with the block-layout factor; one workgroup per
-// sample, wave w handles blocks w, w+W, ...; the next Schur block's factor
-// entries are loaded while the current one is applied.
+// x (+)= S Ahat^{-1} S rhs for one sample with the block-layout factor fs
+// (all threads of the workgroup call it); wave w handles the blocks of its
+// row pair, the next Schur block's factor entries are loaded while the
+// current one is applied.  rs == NULL means the constant rhs_const.
 template <typename Tst, int M, int G, bool PREF>
-__global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__restrict__ sc,
-                                                      const double *__restrict__ beta,
-                                                      const Tst *__restrict__ factor,
-                                                      const double *__restrict__ rhs,
-                                                      double rhs_const, double *__restrict__ x,
-                                                      int accumulate, double *__restrict__ zbuf,
-                                                      const int *__restrict__ idx,
-                                                      int64_t slot_base,
-                                                      const uint32_t *__restrict__ state)
+__device__ inline void solve_blk_pass(const double *__restrict__ scs, const double *__restrict__ bs,
+                                      const Tst *__restrict__ fs, const double *__restrict__ rs,
+                                      double rhs_const, double *__restrict__ xs, int accumulate,
+                                      double *__restrict__ zs)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = G * NB / 2, SPW = (NB + G) / G;
@@ -362,18 +361,9 @@ __global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__r
     static_assert(NT >= M, "one vector entry per thread");
     __shared__ Tac g[M], xc[M];
     __shared__ Tac part[W][M];  // per-wave partial products, summed in wave order (deterministic)
-    const int b = blockIdx.x;
-    const int s = idx ? idx[b] : b;
-    if (state && (state[s] & ST_DONE)) return;
-    const int64_t slot = slot_base + b;
     const int t = threadIdx.x, l = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lr = l >> 4, lc = l & 15;
-    const size_t vo = (size_t)s * m * M;
-    const double *scs = sc + vo, *bs = beta + vo;
-    const double *rs = rhs ? rhs + vo : nullptr;
-    double *xs = x + vo, *zs = zbuf + vo;
-    const Tst *fs = factor + (size_t)slot * m * NBL * 256;
 
     Tst cur[SPW][4], nxt[PREF ? SPW : 1][4];
     auto load = [&](int j, Tst (&dst)[SPW][4]) {
@@ -520,6 +510,75 @@ __global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__r
     }
 }
 
+template <typename Tst, int M, int G, bool PREF>
+__global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__restrict__ sc,
+                                                      const double *__restrict__ beta,
+                                                      const Tst *__restrict__ factor,
+                                                      const double *__restrict__ rhs,
+                                                      double rhs_const, double *__restrict__ x,
+                                                      int accumulate, double *__restrict__ zbuf,
+                                                      const int *__restrict__ idx,
+                                                      int64_t slot_base,
+                                                      const uint32_t *__restrict__ state)
+{
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1;
+    const int b = blockIdx.x;
+    const int s = idx ? idx[b] : b;
+    if (state && (state[s] & ST_DONE)) return;
+    const size_t vo = (size_t)s * m * M;
+    solve_blk_pass<Tst, M, G, PREF>(sc + vo, beta + vo, factor + (size_t)(slot_base + b) * m * NBL * 256,
+                                    rhs ? rhs + vo : nullptr, rhs_const, x + vo, accumulate, zbuf + vo);
+}
+
+// Algorithm 2.1 for one sample per workgroup, after the factorisation:
+// x0 = S Ahat^{-1} S b, then {r = b - A x (FP64); stop test; x += solve(r)}.
+// With `direct` the first residual only yields Q and the relative residual.
+// Workgroups b >= *count (when count is given) exit at once.
+template <typename Tst, int M, int G, bool PREF>
+__global__ __launch_bounds__(32 * G * M / 16) void k_ir_blk(
+    int n, double fconst, const double *__restrict__ a, const double *__restrict__ sc,
+    const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
+    double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
+    const int *__restrict__ idx, const int *__restrict__ count, int64_t slot_base,
+    uint32_t *__restrict__ state, double *__restrict__ relres, double *__restrict__ q,
+    int32_t *__restrict__ iters)
+{
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1, NT = 32 * G * M / 16;
+    __shared__ double red[NT];
+    const int b = blockIdx.x;
+    if (count && b >= *count) return;
+    const int s = idx ? idx[b] : b;
+    const size_t vo = (size_t)s * m * M;
+    const double *scs = sc + vo, *bs = beta + vo;
+    const Tst *fs = factor + (size_t)(slot_base + b) * m * NBL * 256;
+    double *xs = x + vo, *rsb = r + vo, *zs = zbuf + vo;
+    const double *as = a + (size_t)s * (n + 1) * (n + 1);
+    const double h = 1.0 / n;
+    solve_blk_pass<Tst, M, G, PREF>(scs, bs, fs, nullptr, h * h * fconst, xs, 0, zs);
+    uint32_t st = state[s] & ~(uint32_t)ST_DONE;
+    double prev = INFINITY, rel = INFINITY, sx = 0.0;
+    int trip = 0;
+    for (;;) {
+        __syncthreads();
+        const resid_out o = residual_pass<NT>(n, fconst, as, xs, rsb, red);
+        rel = sqrt(o.rr) / sqrt(o.bb);
+        sx = o.sx;
+        st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
+        if (st & ST_DONE) break;
+        prev = rel;
+        __syncthreads();
+        solve_blk_pass<Tst, M, G, PREF>(scs, bs, fs, rsb, 0.0, xs, 1, zs);
+        ++trip;
+    }
+    if (threadIdx.x == 0) {
+        state[s] = st;
+        relres[s] = rel;
+        q[s] = h * h * sx;
+        if (iters) iters[s] = trip;
+    }
+}
+
+
 // ------------------------------------------------------------------ launchers
 
 namespace {
@@ -532,10 +591,10 @@ template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static c
 
 template <typename Tst, int M>
 hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const int *idx,
-              int64_t slot_base, uint32_t *state, hipStream_t st)
+              const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
 {
     hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(32 * M / 16), 0, st, nb, beta, gam,
-                       (Tst *)factor, idx, slot_base, state);
+                       (Tst *)factor, idx, count, slot_base, state);
     return hipGetLastError();
 }
 
@@ -551,14 +610,36 @@ hipError_t ls(int nb, const double *sc, const double *beta, const void *factor, 
     return hipGetLastError();
 }
 
+template <typename Tst, int M>
+hipError_t li(const ir_args &g, hipStream_t st)
+{
+    constexpr int G = solve_cfg<Tst, M>::G;
+    constexpr bool PREF = solve_cfg<Tst, M>::PREF;
+    hipLaunchKernelGGL((k_ir_blk<Tst, M, G, PREF>), dim3(g.nblocks), dim3(32 * G * M / 16), 0, st, g.n,
+                       g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps,
+                       g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters);
+    return hipGetLastError();
+}
+
+template <typename Tst>
+hipError_t li_m(const ir_args &g, hipStream_t st)
+{
+    switch (g.n) {
+    case 64: return li<Tst, 64>(g, st);
+    case 128: return li<Tst, 128>(g, st);
+    case 256: return li<Tst, 256>(g, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename Tst>
 hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *factor, const int *idx,
-                int64_t slot_base, uint32_t *state, hipStream_t st)
+                const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
 {
     switch (M) {
-    case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, slot_base, state, st);
-    case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, slot_base, state, st);
-    case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     }
     return hipErrorInvalidValue;
 }
@@ -578,14 +659,25 @@ hipError_t ls_m(int M, int nb, const double *sc, const double *beta, const void 
 }  // namespace
 
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                             void *factor, const int *idx, int64_t slot_base, uint32_t *state,
-                             hipStream_t st)
+                             void *factor, const int *idx, const int *count, int64_t slot_base,
+                             uint32_t *state, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return lf_m<double>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
-    case 1: return lf_m<float>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
-    case 2: return lf_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
-    case 3: return lf_m<__half>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 0: return lf_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 1: return lf_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 3: return lf_m<__half>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st)
+{
+    switch (dtype) {
+    case 0: return li_m<double>(g, st);
+    case 1: return li_m<float>(g, st);
+    case 2: return li_m<__hip_bfloat16>(g, st);
+    case 3: return li_m<__half>(g, st);
     }
     return hipErrorInvalidValue;
 }

@@ -19,6 +19,23 @@ enum : uint32_t {
 
 size_t factor_entries_per_sample(int n);
 
+// Arguments of the per-sample refinement kernel (one workgroup per sample b:
+// sample idx[b] (or b), factor slot slot_base + b; b >= *count exits).
+struct ir_args {
+    int n, nblocks;
+    double fconst;
+    const double *a, *sc, *beta;
+    const void *factor;
+    double *x, *r, *z;
+    double eps;
+    int imax, direct;
+    const int *idx, *count;
+    int64_t slot_base;
+    uint32_t *state;
+    double *relres, *q;
+    int32_t *iters;
+};
+
 hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi,
                           hipStream_t st);
 hipError_t launch_field(int S, int K, int P, const double *xi, const double *phit, double *a,
@@ -28,15 +45,18 @@ hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double 
 hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
                          hipStream_t st);
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                         void *factor, const int *idx, int64_t slot_base, uint32_t *state,
-                         hipStream_t st);
+                         void *factor, const int *idx, const int *count, int64_t slot_base,
+                         uint32_t *state, hipStream_t st);
+// Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample.
+hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const double *beta,
                         const void *factor, const double *rhs, double rhs_const, double *x,
                         int accumulate, double *zbuf, const int *idx, int64_t slot_base,
                         const uint32_t *state, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                             void *factor, const int *idx, int64_t slot_base, uint32_t *state,
-                             hipStream_t st);
+                             void *factor, const int *idx, const int *count, int64_t slot_base,
+                             uint32_t *state, hipStream_t st);
+hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_solve_blk(int dtype, int n, int nblocks, const double *sc, const double *beta,
                             const void *factor, const double *rhs, double rhs_const, double *x,
                             int accumulate, double *zbuf, const int *idx, int64_t slot_base,
@@ -45,10 +65,17 @@ hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, c
                            double *r, double eps, int trip, int imax, int direct, const int *idx,
                            uint32_t *state, double *relres, double *q, int32_t *iters,
                            int *n_active, hipStream_t st);
+hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
+                         const double *gam, const double *beta, double *x, double *r, double *vecs,
+                         double eps, int maxit, uint32_t *state, double *relres, double *q,
+                         int32_t *iters, hipStream_t st);
+hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
+                             double *gz, hipStream_t st);
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);
 hipError_t launch_init_state(int S, uint32_t *state, double *relres, hipStream_t st);
-hipError_t launch_reset_subset(int P, const int *idx, uint32_t *state, double *relres,
-                               hipStream_t st);
+hipError_t launch_reset_subset(int P, const int *idx, const int *count, uint32_t *state,
+                               double *relres, hipStream_t st);
+hipError_t launch_zero_int(int *p, int n, hipStream_t st);
 hipError_t launch_collect(int S, const uint32_t *state, int *idx, int *cnt, hipStream_t st);
 hipError_t launch_pair_sums(int S, const double *qf, const double *qc, const uint32_t *stf,
                             const uint32_t *stc, const int32_t *itf, double *y, uint8_t *status,

@@ -21,6 +21,7 @@
 
 #include "dtypes.h"
 #include "kernels.h"
+#include "ir_common.h"
 
 namespace mlmc {
 
@@ -193,7 +194,8 @@ template <typename Tst, int M, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_factor(int S, const double *__restrict__ beta,
                                                const double *__restrict__ gam,
                                                Tst *__restrict__ factor, const int *__restrict__ idx,
-                                               int64_t slot_base, uint32_t *__restrict__ state)
+                                               const int *__restrict__ count, int64_t slot_base,
+                                               uint32_t *__restrict__ state)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR;
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(NT) void k_factor(int S, const double *__restrict__
     __shared__ Tac bj[M], gj[M];
     __shared__ int bad;
     const int b = blockIdx.x;
+    if (count && b >= *count) return;
     const int s = idx ? idx[b] : b;
     const int64_t slot = slot_base + b;
     const int t = threadIdx.x;
@@ -294,37 +297,25 @@ __global__ __launch_bounds__(NT) void k_factor(int S, const double *__restrict__
 
 // ------------------------------------------------------------------ solve
 
-// x (+)= S Ahat^{-1} S rhs with the stored factor (one workgroup per sample).
-// rhs: padded [S][m*M] FP64, or NULL for the constant rhs_const.
-// Arithmetic in Tac (FP64 for the FP64 factor, FP32 otherwise); z in zbuf.
+// x (+)= S Ahat^{-1} S rhs for one sample with the tile-layout factor fs
+// (all threads of the workgroup call it).  rs == NULL means the constant
+// rhs_const.  Arithmetic in Tac (FP64 for the FP64 factor, FP32 otherwise).
+// With a single-wave workgroup the LDS atomics below execute in a fixed order.
 template <typename Tst, int M, int TR, int NT>
-__global__ __launch_bounds__(NT) void k_solve(const double *__restrict__ sc,
-                                              const double *__restrict__ beta,
-                                              const Tst *__restrict__ factor,
-                                              const double *__restrict__ rhs, double rhs_const,
-                                              double *__restrict__ x, int accumulate,
-                                              double *__restrict__ zbuf,
-                                              const int *__restrict__ idx, int64_t slot_base,
-                                              const uint32_t *__restrict__ state)
+__device__ inline void solve_tile_pass(const double *__restrict__ scs, const double *__restrict__ bs,
+                                       const Tst *__restrict__ fs, const double *__restrict__ rs,
+                                       double rhs_const, double *__restrict__ xs, int accumulate,
+                                       double *__restrict__ zs)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR;
     constexpr int m = M - 1;
     __shared__ Tac g[M], acc[M], xc[M];
-    const int b = blockIdx.x;
-    const int s = idx ? idx[b] : b;
-    if (state && (state[s] & ST_DONE)) return;
-    const int64_t slot = slot_base + b;
     const int t = threadIdx.x;
     const bool active = t < T;
     int I = 0, J = 0;
     if (active) tile_of(t, I, J);
     const int i0 = I * TR, j0 = J * TR;
-    const size_t vo = (size_t)s * m * M;
-    const double *scs = sc + vo, *bs = beta + vo;
-    const double *rs = rhs ? rhs + vo : nullptr;
-    double *xs = x + vo, *zs = zbuf + vo;
-    const Tst *fs = factor + (size_t)slot * m * T * E;
 
     auto matvec = [&](int j) {
         // acc[i] += sum_l F_j[i][l] g[l], F_j = stored -C_j^{-1} (symmetric)
@@ -400,6 +391,71 @@ __global__ __launch_bounds__(NT) void k_solve(const double *__restrict__ sc,
     }
 }
 
+template <typename Tst, int M, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_solve(const double *__restrict__ sc,
+                                              const double *__restrict__ beta,
+                                              const Tst *__restrict__ factor,
+                                              const double *__restrict__ rhs, double rhs_const,
+                                              double *__restrict__ x, int accumulate,
+                                              double *__restrict__ zbuf,
+                                              const int *__restrict__ idx, int64_t slot_base,
+                                              const uint32_t *__restrict__ state)
+{
+    constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR, m = M - 1;
+    const int b = blockIdx.x;
+    const int s = idx ? idx[b] : b;
+    if (state && (state[s] & ST_DONE)) return;
+    const size_t vo = (size_t)s * m * M;
+    solve_tile_pass<Tst, M, TR, NT>(sc + vo, beta + vo, factor + (size_t)(slot_base + b) * m * T * E,
+                                    rhs ? rhs + vo : nullptr, rhs_const, x + vo, accumulate, zbuf + vo);
+}
+
+// Algorithm 2.1 for one sample per workgroup (tile-layout factor): x0, then
+// {r = b - A x (FP64); stop test; x += solve(r)}; `direct`: residual only.
+template <typename Tst, int M, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_ir_tile(
+    int n, double fconst, const double *__restrict__ a, const double *__restrict__ sc,
+    const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
+    double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
+    const int *__restrict__ idx, const int *__restrict__ count, int64_t slot_base,
+    uint32_t *__restrict__ state, double *__restrict__ relres, double *__restrict__ q,
+    int32_t *__restrict__ iters)
+{
+    constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR, m = M - 1;
+    __shared__ double red[NT];
+    const int b = blockIdx.x;
+    if (count && b >= *count) return;
+    const int s = idx ? idx[b] : b;
+    const size_t vo = (size_t)s * m * M;
+    const double *scs = sc + vo, *bs = beta + vo;
+    const Tst *fs = factor + (size_t)(slot_base + b) * m * T * E;
+    double *xs = x + vo, *rsb = r + vo, *zs = zbuf + vo;
+    const double *as = a + (size_t)s * (n + 1) * (n + 1);
+    const double h = 1.0 / n;
+    solve_tile_pass<Tst, M, TR, NT>(scs, bs, fs, nullptr, h * h * fconst, xs, 0, zs);
+    uint32_t st = state[s] & ~(uint32_t)ST_DONE;
+    double prev = INFINITY, rel = INFINITY, sx = 0.0;
+    int trip = 0;
+    for (;;) {
+        __syncthreads();
+        const resid_out o = residual_pass<NT>(n, fconst, as, xs, rsb, red);
+        rel = sqrt(o.rr) / sqrt(o.bb);
+        sx = o.sx;
+        st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
+        if (st & ST_DONE) break;
+        prev = rel;
+        __syncthreads();
+        solve_tile_pass<Tst, M, TR, NT>(scs, bs, fs, rsb, 0.0, xs, 1, zs);
+        ++trip;
+    }
+    if (threadIdx.x == 0) {
+        state[s] = st;
+        relres[s] = rel;
+        q[s] = h * h * sx;
+        if (iters) iters[s] = trip;
+    }
+}
+
 // ------------------------------------------------------------------ residual
 
 // r = b - A x in FP64 from the nodal coefficient (matrix-free 5-point
@@ -470,6 +526,40 @@ __global__ __launch_bounds__(256) void k_residual(int n, double h, double fconst
     }
 }
 
+// dQ/dZ at every node for the adjoint gradient: with u and lambda the
+// (padded) primal and adjoint solutions (0 on the boundary),
+//   gz_e = -sum_{edges (e,o)} (lambda_e - lambda_o)(u_e - u_o) 2 a_o^2 a_e / (a_e + a_o)^2,
+// the derivative of the harmonic-mean edge coefficient with respect to
+// Z_e = log a_e.  One thread per node.
+__global__ void k_adjoint_gz(int n, int S, const double *__restrict__ a, const double *__restrict__ u,
+                             const double *__restrict__ lam, double *__restrict__ gz)
+{
+    const int m = n - 1, M = n, np = n + 1;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)S * np * np) return;
+    const int s = (int)(g / (np * np));
+    const int p = (int)(g % (np * np));
+    const int ix = p % np, iy = p / np;
+    const double *as = a + (size_t)s * np * np;
+    const double *us = u + (size_t)s * m * M, *ls = lam + (size_t)s * m * M;
+    auto val = [&](const double *v, int jx, int jy) {
+        return (jx >= 1 && jx <= m && jy >= 1 && jy <= m) ? v[(jy - 1) * M + (jx - 1)] : 0.0;
+    };
+    const double ae = as[p], ue = val(us, ix, iy), le = val(ls, ix, iy);
+    double acc = 0.0;
+    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int jx = ix + dx[k], jy = iy + dy[k];
+        if (jx < 0 || jx > n || jy < 0 || jy > n) continue;
+        const double ao = as[jy * np + jx];
+        const double du = ue - val(us, jx, jy), dl = le - val(ls, jx, jy);
+        const double den = ae + ao;
+        acc -= dl * du * 2.0 * ao * ao * ae / (den * den);
+    }
+    gz[g] = acc;
+}
+
 // Copy the padded solution to the caller's unpadded [S][(n-1)^2] layout.
 __global__ void k_unpad(int n, int S, const double *__restrict__ x, double *__restrict__ u)
 {
@@ -491,13 +581,21 @@ __global__ void k_init_state(int S, uint32_t *state, double *relres)
 }
 
 // Reset the refinement state of the samples in idx (for a promoted re-solve).
-__global__ void k_reset_subset(int P, const int *__restrict__ idx, uint32_t *state, double *relres)
+__global__ void k_reset_subset(int P, const int *__restrict__ idx, const int *__restrict__ count,
+                               uint32_t *state, double *relres)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    if (p >= P || (count && p >= *count)) return;
     const int s = idx[p];
     state[s] = ST_PROMOTED;
     relres[s] = INFINITY;
+}
+
+// Zero n ints (a kernel rather than a memset node, so captured graphs replay it).
+__global__ void k_zero_int(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // Collect samples that need promotion (not converged) into idx; count in *cnt.
@@ -565,17 +663,42 @@ constexpr int nthreads()
 
 template <int M>
 struct tile_cfg;
+template <> struct tile_cfg<4> { static constexpr int TR = 2; };
+template <> struct tile_cfg<8> { static constexpr int TR = 2; };
 template <> struct tile_cfg<16> { static constexpr int TR = 2; };
 template <> struct tile_cfg<32> { static constexpr int TR = 4; };
 
 template <typename Tst, int M>
 hipError_t launch_factor_t(int nblocks, const double *beta, const double *gam, void *factor,
-                           const int *idx, int64_t slot_base, uint32_t *state, hipStream_t st)
+                           const int *idx, const int *count, int64_t slot_base, uint32_t *state,
+                           hipStream_t st)
 {
     constexpr int TR = tile_cfg<M>::TR, NT = nthreads<Tst, M, TR>();
     hipLaunchKernelGGL((k_factor<Tst, M, TR, NT>), dim3(nblocks), dim3(NT), 0, st, nblocks, beta,
-                       gam, (Tst *)factor, idx, slot_base, state);
+                       gam, (Tst *)factor, idx, count, slot_base, state);
     return hipGetLastError();
+}
+
+template <typename Tst, int M>
+hipError_t launch_ir_t(const ir_args &g, hipStream_t st)
+{
+    constexpr int TR = tile_cfg<M>::TR, NT = nthreads<Tst, M, TR>();
+    hipLaunchKernelGGL((k_ir_tile<Tst, M, TR, NT>), dim3(g.nblocks), dim3(NT), 0, st, g.n, g.fconst,
+                       g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps, g.imax,
+                       g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters);
+    return hipGetLastError();
+}
+
+template <typename Tst>
+hipError_t launch_ir_m(const ir_args &g, hipStream_t st)
+{
+    switch (g.n) {
+    case 4: return launch_ir_t<Tst, 4>(g, st);
+    case 8: return launch_ir_t<Tst, 8>(g, st);
+    case 16: return launch_ir_t<Tst, 16>(g, st);
+    case 32: return launch_ir_t<Tst, 32>(g, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename Tst, int M>
@@ -593,11 +716,14 @@ hipError_t launch_solve_t(int nblocks, const double *sc, const double *beta, con
 
 template <typename Tst>
 hipError_t launch_factor_m(int M, int nb, const double *beta, const double *gam, void *factor,
-                           const int *idx, int64_t slot_base, uint32_t *state, hipStream_t st)
+                           const int *idx, const int *count, int64_t slot_base, uint32_t *state,
+                           hipStream_t st)
 {
     switch (M) {
-    case 16: return launch_factor_t<Tst, 16>(nb, beta, gam, factor, idx, slot_base, state, st);
-    case 32: return launch_factor_t<Tst, 32>(nb, beta, gam, factor, idx, slot_base, state, st);
+    case 4: return launch_factor_t<Tst, 4>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 8: return launch_factor_t<Tst, 8>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 16: return launch_factor_t<Tst, 16>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 32: return launch_factor_t<Tst, 32>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     }
     return hipErrorInvalidValue;
 }
@@ -608,6 +734,8 @@ hipError_t launch_solve_m(int M, int nb, const double *sc, const double *beta, c
                           const int *idx, int64_t slot_base, const uint32_t *state, hipStream_t st)
 {
     switch (M) {
+    case 4: return launch_solve_t<Tst, 4>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
+    case 8: return launch_solve_t<Tst, 8>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 16: return launch_solve_t<Tst, 16>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 32: return launch_solve_t<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     }
@@ -666,16 +794,30 @@ hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam,
 }
 
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                         void *factor, const int *idx, int64_t slot_base, uint32_t *state,
-                         hipStream_t st)
+                         void *factor, const int *idx, const int *count, int64_t slot_base,
+                         uint32_t *state, hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
-    if (n >= 64) return launch_factor_blk(dtype, n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    if (n >= 64)
+        return launch_factor_blk(dtype, n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     switch (dtype) {
-    case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
-    case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
-    case 2: return launch_factor_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
-    case 3: return launch_factor_m<__half>(n, nblocks, beta, gam, factor, idx, slot_base, state, st);
+    case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 2: return launch_factor_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 3: return launch_factor_m<__half>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st)
+{
+    if (g.nblocks == 0) return hipSuccess;
+    if (g.n >= 64) return launch_ir_blk(dtype, g, st);
+    switch (dtype) {
+    case 0: return launch_ir_m<double>(g, st);
+    case 1: return launch_ir_m<float>(g, st);
+    case 2: return launch_ir_m<__hip_bfloat16>(g, st);
+    case 3: return launch_ir_m<__half>(g, st);
     }
     return hipErrorInvalidValue;
 }
@@ -709,6 +851,15 @@ hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, c
     return hipGetLastError();
 }
 
+hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
+                             double *gz, hipStream_t st)
+{
+    const int64_t tot = (int64_t)S * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_adjoint_gz, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, S, a, u,
+                       lam, gz);
+    return hipGetLastError();
+}
+
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st)
 {
     const int64_t N = (int64_t)S * (n - 1) * (n - 1);
@@ -722,12 +873,18 @@ hipError_t launch_init_state(int S, uint32_t *state, double *relres, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_reset_subset(int P, const int *idx, uint32_t *state, double *relres,
-                               hipStream_t st)
+hipError_t launch_reset_subset(int P, const int *idx, const int *count, uint32_t *state,
+                               double *relres, hipStream_t st)
 {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reset_subset, dim3((P + 255) / 256), dim3(256), 0, st, P, idx, state,
+    hipLaunchKernelGGL(k_reset_subset, dim3((P + 255) / 256), dim3(256), 0, st, P, idx, count, state,
                        relres);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int *p, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

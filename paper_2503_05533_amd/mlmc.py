@@ -91,7 +91,8 @@ def load_library():
                                       ctypes.c_size_t, vp, vp, vp, vp, ctypes.POINTER(_LevelStats), vp]
     lib.mlmc_estimate.argtypes = [vp, dbl, i32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, i32,
                                   ctypes.POINTER(_Result), vp]
-    lib.mlmc_grad.argtypes = [vp, i32, i64, vp, vp, dbl, vp, ctypes.c_size_t, vp, vp]
+    lib.mlmc_grad.argtypes = [vp, i32, i64, vp, vp, ctypes.POINTER(_LevelOpts), dbl, vp,
+                              ctypes.c_size_t, vp, vp]
     lib.mlmc_profile.argtypes = [vp, i32]
     lib.mlmc_profile_read.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
@@ -192,7 +193,7 @@ class MLMC:
         o = self._opts(**opt)
         return self.lib.mlmc_workspace_bytes(self.h, level, n, ctypes.byref(o))
 
-    KINDS = {"field": 0, "assembly": 1, "factor": 2, "solve": 3, "residual": 4}
+    KINDS = {"field": 0, "assembly": 1, "factor": 2, "solve": 3, "residual": 4, "minres": 5}
 
     def profile(self, enable=True):
         self._check(self.lib.mlmc_profile(self.h, 1 if enable else 0), "profile")
@@ -264,15 +265,17 @@ class MLMC:
 
     def grad(self, level, xi, grad_q=None, eps_adjoint=1e-10, dtype="f32", solver="direct_ir",
              eps=1e-10):
-        """dQ/dxi (times grad_q) after a forward solve on the same samples."""
+        """(Q, dQ/dxi * grad_q): forward solve, then the adjoint on the same workspace."""
         xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
         S = xi.shape[0]
-        fw = self.solve(level, xi, dtype=dtype, solver=solver, eps=eps, promote=False)
+        fw = self.solve(level, xi, dtype=dtype, solver=solver, eps=eps, promote=True)
+        o = self._opts(dtype, solver, eps, 0.0, True)
         ws = self._ws
         g = torch.empty((S, self.cfg.K), dtype=torch.float64, device=self.device)
         gq = None if grad_q is None else grad_q.to(device=self.device, dtype=torch.float64).contiguous()
-        self._check(self.lib.mlmc_grad(self.h, level, S, _ptr(xi), _ptr(gq), float(eps_adjoint),
-                                       _ptr(ws), ws.numel(), _ptr(g), _stream()), "grad")
+        self._check(self.lib.mlmc_grad(self.h, level, S, _ptr(xi), _ptr(gq), ctypes.byref(o),
+                                       float(eps_adjoint), _ptr(ws), ws.numel(), _ptr(g), _stream()),
+                    "grad")
         return fw["q"], g
 
 

@@ -1,0 +1,194 @@
+"""GPU parity of the MINRES path, the adjoint gradient and the Algorithm 4.1 driver."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def _ctx(**kw):
+    from paper_2503_05533_amd import MLMC, Config
+    return MLMC(Config(**kw), device="cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ----------------------------------------------------------------- MINRES
+
+@pytest.mark.parametrize("n,S", [(16, 40), (32, 20), (64, 6)])
+def test_minres_reaches_eps(n, S):
+    torch = _torch()
+    level = {16: 0, 32: 1, 64: 2}[n]
+    K, s2, lam, seed = 64, 1.0, 0.3, 1001
+    ctx = _ctx(n0=16, L_max=level, K=K, sigma2=s2, corr_len=lam, seed=seed, minres_max_iter=4000)
+    xi = si.splitmix64_normals(seed, level, 0, S, K)
+    phi = oracle.kl_basis(n, K, s2, lam)
+    qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
+    for eps in (8.7e-4, 1e-8):
+        _say("minres n=%d S=%d eps=%g" % (n, S, eps))
+        out = ctx.solve(level, torch.from_numpy(xi), solver="minres", eps=eps, want_u=True)
+        st = out["status"].cpu().numpy()
+        assert np.all(st & 1), st
+        rr = oracle.relres_batch(n, phi, xi, out["u"].cpu().numpy())
+        assert np.all(rr < eps * (1 + 1e-6)), rr.max()
+        nb = math.sqrt(uref.shape[1]) / n ** 2
+        bound = np.linalg.norm(uref, axis=1) * nb / qref
+        dq = np.abs(out["q"].cpu().numpy() - qref) / qref
+        assert np.all(dq <= rr * bound * (1 + 1e-6) + 1e-14)
+        it = out["iters"].cpu().numpy()
+        assert np.all(it >= 1)
+    ctx.close()
+
+
+def test_minres_iterations_grow_with_accuracy():
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=1, K=16, minres_max_iter=4000)
+    xi = torch.from_numpy(si.splitmix64_normals(3, 1, 0, 8, 16))
+    loose = ctx.solve(1, xi, solver="minres", eps=1e-3)["iters"].cpu().numpy()
+    tight = ctx.solve(1, xi, solver="minres", eps=1e-9)["iters"].cpu().numpy()
+    assert np.all(tight > loose)
+    ctx.close()
+
+
+def test_minres_iteration_cap_flags():
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=1, K=16, minres_max_iter=3)
+    xi = torch.from_numpy(si.splitmix64_normals(3, 1, 0, 4, 16))
+    out = ctx.solve(1, xi, solver="minres", eps=1e-12)
+    st = out["status"].cpu().numpy()
+    assert np.all(st & 8) and not np.any(st & 1)
+    ctx.close()
+
+
+# ----------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("dtype,solver,tol", [("f64", "direct", 1e-9), ("f32", "direct_ir", 1e-7)])
+def test_adjoint_matches_oracle_gradient(dtype, solver, tol):
+    torch = _torch()
+    for n, K, s2, lam, S in [(16, 16, 1.0, 0.3, 12), (64, 128, 2.0, 0.1, 4)]:
+        level = {16: 0, 64: 2}[n]
+        ctx = _ctx(n0=16, L_max=level, K=K, sigma2=s2, corr_len=lam, seed=21)
+        xi = si.splitmix64_normals(21, level, 0, S, K)
+        gq = np.linspace(0.5, 2.0, S)
+        _say("adjoint n=%d %s" % (n, dtype))
+        q, g = ctx.grad(level, torch.from_numpy(xi), torch.from_numpy(gq), eps_adjoint=1e-11,
+                        dtype=dtype, solver=solver, eps=1e-11)
+        g = g.cpu().numpy()
+        ref = oracle.grad_batch(n, oracle.kl_basis(n, K, s2, lam), xi) * gq[:, None]
+        for s in range(S):
+            assert np.linalg.norm(g[s] - ref[s]) <= tol * np.linalg.norm(ref[s]), s
+        ctx.close()
+
+
+def test_adjoint_central_differences_n128():
+    """dQ/dxi at n=128, K=128 against central differences (h=1e-6) of the GPU FP64 Q."""
+    torch = _torch()
+    K, s2, lam, seed = 128, 2.0, 0.1, 1004
+    ctx = _ctx(n0=16, L_max=3, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    xi = si.splitmix64_normals(seed, 0, 0, 2, K)
+    _, g = ctx.grad(3, torch.from_numpy(xi), None, eps_adjoint=1e-10, dtype="f32",
+                    solver="direct_ir", eps=1e-10)
+    g = g.cpu().numpy()
+    hfd = 1e-6
+    ks = [0, 1, 5, 17, 63, 127]
+    for s in range(2):
+        pert = []
+        for k in ks:
+            for sign in (1, -1):
+                x = xi[s].copy()
+                x[k] += sign * hfd
+                pert.append(x)
+        qp = ctx.solve(3, torch.from_numpy(np.array(pert)), dtype="f64", solver="direct")["q"].cpu().numpy()
+        fd = (qp[0::2] - qp[1::2]) / (2 * hfd)
+        assert np.linalg.norm(g[s, ks] - fd) <= 1e-4 * np.linalg.norm(fd), (g[s, ks], fd)
+    ctx.close()
+
+
+def test_autograd_function():
+    torch = _torch()
+    from paper_2503_05533_amd import MLMCQoI
+    K = 16
+    ctx = _ctx(n0=16, L_max=1, K=K, seed=4)
+    xi = torch.from_numpy(si.splitmix64_normals(4, 1, 0, 6, K)).cuda().requires_grad_(True)
+    q = MLMCQoI.apply(ctx, 1, xi, "f32", 1e-11)
+    w = torch.linspace(1, 2, 6, dtype=torch.float64, device="cuda")
+    (q * w).sum().backward()
+    ref = oracle.grad_batch(32, oracle.kl_basis(32, K, 1.0, 0.3), xi.detach().cpu().numpy())
+    ref = ref * w.cpu().numpy()[:, None]
+    got = xi.grad.cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
+    qref = oracle.solve_batch(32, oracle.kl_basis(32, K, 1.0, 0.3), xi.detach().cpu().numpy())
+    assert np.allclose(q.detach().cpu().numpy(), qref, rtol=1e-10, atol=0)
+    ctx.close()
+
+
+# ----------------------------------------------------------------- Algorithm 4.1
+
+def _oracle_estimate(n0, L_max, K, s2, lam, seed, tol, n_init, mixed):
+    phis = {}
+
+    def phi(n):
+        if n not in phis:
+            phis[n] = oracle.kl_basis(n, K, s2, lam)
+        return phis[n]
+
+    def sample_fn(l, first, count, dfine, dcoarse):
+        xi = si.splitmix64_normals(seed, l, first, count, K)
+        nf = n0 * 2 ** l
+        qf = oracle.solve_batch(nf, phi(nf), xi)
+        if l == 0:
+            return qf
+        return qf - oracle.solve_batch(nf // 2, phi(nf // 2), xi)
+
+    return oracle.adaptive_mpml(sample_fn, n0, tol, L_max, n_init=n_init, mixed=mixed)
+
+
+def test_estimate_fp64_follows_oracle_decisions():
+    torch = _torch()
+    n0, L_max, K, s2, lam, seed = 4, 3, 16, 1.0, 0.3, 77
+    tol, n_init = 4e-4, 200
+    ctx = _ctx(n0=n0, L_max=L_max, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    res = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * (L_max + 1), solver="direct", mixed=False)
+    ref = _oracle_estimate(n0, L_max, K, s2, lam, seed, tol, n_init, mixed=False)
+    _say("gpu", res["L"], res["N"], res["estimate"], "oracle", ref["L"], ref["N"], ref["estimate"])
+    assert res["L"] == ref["L"]
+    for a, b in zip(res["N"], ref["N"]):
+        assert abs(a - b) <= max(1, 1e-6 * b)
+    if res["N"] == ref["N"]:
+        assert res["estimate"] == pytest.approx(ref["estimate"], rel=1e-10)
+    assert res["converged"]
+    ctx.close()
+
+
+def test_estimate_mixed_matches_fp64():
+    torch = _torch()
+    n0, L_max, K, s2, lam, seed = 4, 3, 16, 1.0, 0.3, 78
+    tol, n_init = 4e-4, 200
+    ctx = _ctx(n0=n0, L_max=L_max, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    mix = ctx.estimate(tol, n_init=n_init, dtypes=["f16", "f32", "f32", "f32"], solver="direct_ir",
+                       mixed=True)
+    ref = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * 4, solver="direct", mixed=False)
+    _say("mixed", mix["L"], mix["N"], mix["estimate"], "fp64", ref["L"], ref["N"], ref["estimate"])
+    # the accuracy rule keeps the computational error far below the statistical
+    # error: with equal sample counts the estimates differ by solver error only
+    if mix["N"] == ref["N"]:
+        assert abs(mix["estimate"] - ref["estimate"]) < 1e-3 * tol
+    else:
+        assert abs(mix["estimate"] - ref["estimate"]) < tol
+    assert mix["converged"]
+    assert all(e > 0 for e in mix["eps"])
+    ctx.close()
