@@ -169,6 +169,33 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
                       double *q_fine_dev, double *q_coarse_dev, double *y_dev,
                       uint8_t *status_dev, mlmc_level_stats *stats_host, void *stream);
 
+/* Several MLMC levels in one call: level levels[i] with n[i] samples and
+ * xi_dev[i] ([n[i] x K]) under opts[i].  Every level's fine and coarse grids
+ * run concurrently on streams forked from `stream` and joined back to it,
+ * so uneven work (many small coarse samples, few large fine ones) shares the
+ * GPU.  With use_graph != 0 the whole fork/join is captured once into a HIP
+ * graph and replayed while the arguments (pointers, sizes, options) stay the
+ * same.  The workspace is mlmc_levels_workspace_bytes() bytes; y_dev (may be
+ * NULL, or an array of n_levels device pointers, entries may be NULL) gets
+ * Y_l; stats_host (may be NULL, else n_levels entries) makes the call
+ * synchronise and report the level sums (gpu_ms: the whole call). */
+size_t mlmc_levels_workspace_bytes(const mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels,
+                                   const int64_t *n, const mlmc_level_opts *opts);
+int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, const int64_t *n,
+                       const double *const *xi_dev, const mlmc_level_opts *opts, void *ws_dev,
+                       size_t ws_bytes, double *const *y_dev, mlmc_level_stats *stats_host,
+                       int32_t use_graph, void *stream);
+
+/* Autotuner: times the candidate refinement-kernel configurations (waves
+ * per block-row pair, grids with n >= 64) on the given level and samples
+ * (xi_dev [n x K], the workspace of mlmc_sample_level) and keeps the fastest
+ * for the factor dtype of opts in the context; chosen[0] (fine grid) and
+ * chosen[1] (coarse grid) receive the choice (0 = single configuration).
+ * Synchronises the stream. */
+int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                  const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes, int32_t *chosen,
+                  void *stream);
+
 /* Algorithm 4.1 (adaptive MPML, Sec. 4.3) driven on the GPU: L starts at 1,
  * N_0 = N_1 = n_init; each round recomputes delta_l (Sec. 4.5), tops every
  * level up to N_l with fresh counter-based xi, updates

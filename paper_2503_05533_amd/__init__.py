@@ -3,5 +3,5 @@
 The compute path is the HIP library libmlmc.so (C ABI in include/mlmc.h);
 ``mlmc`` is its thin Python binding.
 """
-from .mlmc import (Config, MLMC, MLMCError, MLMCQoI, DTYPES, SOLVERS, EXPORTS,  # noqa: F401
-                   LIB_PATH, load_library)
+from .mlmc import (Config, MLMC, MLMCError, MLMCQoI, LevelPlan, DTYPES, SOLVERS,  # noqa: F401
+                   EXPORTS, LIB_PATH, load_library)

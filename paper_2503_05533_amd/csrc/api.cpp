@@ -32,6 +32,16 @@ struct mlmc_ctx {
     bool prof_on = false;
     std::vector<prof_rec> prof;
     std::vector<hipEvent_t> ev_pool;
+    // refinement-kernel variant per (factor dtype, log2 n), 0 = built-in default
+    int ir_variant[4][9] = {};
+    // concurrent multi-level launches: two streams per level, events, cached graph
+    std::vector<hipStream_t> lstreams;
+    std::vector<hipEvent_t> levents;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uintptr_t> graph_key;
+    bool capturing = false;
 };
 
 namespace {
@@ -66,6 +76,7 @@ int fail(mlmc_ctx *c, int code, const char *fmt, ...)
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : 2); }
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+inline int ilog2(int v) { int l = 0; while ((1 << (l + 1)) <= v) ++l; return l; }
 
 // ---------------------------------------------------------------- kernel timing
 
@@ -91,7 +102,7 @@ struct prof_scope {
     prof_scope(mlmc_ctx *c_, int kind_, int n_, int64_t s_, hipStream_t st_)
         : c(c_), st(st_), kind(kind_), n(n_), samples(s_)
     {
-        if (c->prof_on && (a = pool_event(c))) (void)hipEventRecord(a, st);
+        if (c->prof_on && !c->capturing && (a = pool_event(c))) (void)hipEventRecord(a, st);
     }
     ~prof_scope()
     {
@@ -328,6 +339,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
     g.relres = relres;
     g.q = q;
     g.iters = iters;
+    g.variant = ctx->ir_variant[dt][ilog2(n)];
     PROF(3, n, S, launch_ir(dt, g, st));
     if (L.promo_slots > 0 && dt != MLMC_F64) {
         int *idx = at<int>(ws, L.off_idx);
@@ -346,6 +358,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         p.count = cnt;
         p.imax = ctx->cfg.ir_max_iter;
         p.direct = 0;
+        p.variant = ctx->ir_variant[MLMC_F64][ilog2(n)];
         PROF(3, n, np, launch_ir(MLMC_F64, p, st));
     }
     return MLMC_OK;
@@ -382,6 +395,53 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     void *factor = at<void>(ws, L.off_factor);
     PROF(2, n, S, launch_factor(dt, n, S, beta, gam, factor, nullptr, nullptr, 0, state, st));
     return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, at<double>(ws, L.off_x), q, iters, st);
+}
+
+
+// Enqueue one MLMC level: the fine grid on `sf`, the coarse grid on `sc`
+// (which may equal sf), then the pairing and level sums on `sf` after the
+// coarse grid (event `ev`).  Outputs default to workspace buffers.
+int level_enqueue(mlmc_ctx *ctx, int level, int64_t n, const double *xi, const mlmc_level_opts &o,
+                  void *ws_dev, const level_layout &LL, double *q_fine, double *q_coarse, double *y,
+                  uint8_t *status, hipStream_t sf, hipStream_t scs, hipEvent_t ev)
+{
+    if (n == 0) return MLMC_OK;
+    double *qf = q_fine ? q_fine : at<double>(ws_dev, LL.off_qf);
+    double *qc = q_coarse ? q_coarse : at<double>(ws_dev, LL.off_qc);
+    void *wf = at<void>(ws_dev, LL.off_fine);
+    int rc = solve_grid(ctx, LL.fine, level, xi, o, o.eps_fine, wf, qf, at<int32_t>(wf, LL.fine.off_iters), sf);
+    if (rc) return rc;
+    const uint32_t *stc = nullptr;
+    if (level > 0) {
+        void *wc = at<void>(ws_dev, LL.off_coarse);
+        rc = solve_grid(ctx, LL.coarse, level - 1, xi, o, o.eps_coarse, wc, qc,
+                        at<int32_t>(wc, LL.coarse.off_iters), scs);
+        if (rc) return rc;
+        stc = at<uint32_t>(wc, LL.coarse.off_state);
+        if (scs != sf) {
+            HIPCHK(hipEventRecord(ev, scs));
+            HIPCHK(hipStreamWaitEvent(sf, ev, 0));
+        }
+    }
+    HIPCHK(launch_pair_sums((int)n, qf, level > 0 ? qc : nullptr, at<uint32_t>(wf, LL.fine.off_state), stc,
+                            at<int32_t>(wf, LL.fine.off_iters), y, status, at<double>(ws_dev, LL.off_sums), sf));
+    return MLMC_OK;
+}
+
+void fill_stats(mlmc_level_stats *out, int64_t n, const double *h, double ms)
+{
+    memset(out, 0, sizeof *out);
+    out->n = n;
+    if (n > 0) {
+        out->sum_y = h[0];
+        out->sum_y2 = h[1];
+        out->sum_qf = h[2];
+        out->sum_qc = h[3];
+        out->n_promoted = (int64_t)h[4];
+        out->n_noconv = (int64_t)h[5];
+        out->mean_iters = h[6] / (double)n;
+    }
+    out->gpu_ms = ms;
 }
 
 }  // namespace
@@ -444,6 +504,11 @@ int mlmc_destroy(mlmc_ctx *ctx)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->levents) (void)hipEventDestroy(e);
+    for (hipStream_t s2 : ctx->lstreams) (void)hipStreamDestroy(s2);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -541,46 +606,196 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
     if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
     hipStream_t st = (hipStream_t)stream;
     if (stats_host) HIPCHK(hipEventRecord(ctx->ev0, st));
-    double *qf = q_fine_dev ? q_fine_dev : at<double>(ws_dev, LL.off_qf);
-    double *qc = q_coarse_dev ? q_coarse_dev : at<double>(ws_dev, LL.off_qc);
-    void *wf = at<void>(ws_dev, LL.off_fine);
-    if (n > 0) {
-        rc = solve_grid(ctx, LL.fine, level, xi_dev, *opts, opts->eps_fine, wf, qf,
-                        at<int32_t>(wf, LL.fine.off_iters), st);
-        if (rc) return rc;
-    }
-    const uint32_t *stc = nullptr;
-    if (level > 0 && n > 0) {
-        void *wc = at<void>(ws_dev, LL.off_coarse);
-        rc = solve_grid(ctx, LL.coarse, level - 1, xi_dev, *opts, opts->eps_coarse, wc, qc,
-                        at<int32_t>(wc, LL.coarse.off_iters), st);
-        if (rc) return rc;
-        stc = at<uint32_t>(wc, LL.coarse.off_state);
-    }
-    double *sums = at<double>(ws_dev, LL.off_sums);
-    if (n > 0)
-        HIPCHK(launch_pair_sums((int)n, qf, level > 0 ? qc : nullptr, at<uint32_t>(wf, LL.fine.off_state),
-                                stc, at<int32_t>(wf, LL.fine.off_iters), y_dev, status_dev, sums, st));
+    rc = level_enqueue(ctx, level, n, xi_dev, *opts, ws_dev, LL, q_fine_dev, q_coarse_dev, y_dev, status_dev,
+                       st, st, nullptr);
+    if (rc) return rc;
     if (stats_host) {
         HIPCHK(hipEventRecord(ctx->ev1, st));
-        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, sums, 7 * 8, hipMemcpyDeviceToHost, st));
+        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, at<double>(ws_dev, LL.off_sums), 7 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        memset(stats_host, 0, sizeof *stats_host);
-        stats_host->n = n;
-        if (n > 0) {
-            stats_host->sum_y = ctx->h_sums[0];
-            stats_host->sum_y2 = ctx->h_sums[1];
-            stats_host->sum_qf = ctx->h_sums[2];
-            stats_host->sum_qc = ctx->h_sums[3];
-            stats_host->n_promoted = (int64_t)ctx->h_sums[4];
-            stats_host->n_noconv = (int64_t)ctx->h_sums[5];
-            stats_host->mean_iters = ctx->h_sums[6] / (double)n;
-        }
-        stats_host->gpu_ms = ms;
+        fill_stats(stats_host, n, ctx->h_sums, ms);
         return stats_host->n_noconv > 0 ? MLMC_ENOCONV : MLMC_OK;
     }
+    return MLMC_OK;
+}
+
+size_t mlmc_levels_workspace_bytes(const mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels,
+                                   const int64_t *n, const mlmc_level_opts *opts)
+{
+    if (!ctx || n_levels < 1 || n_levels > 16 || !levels || !n || !opts) return 0;
+    size_t tot = 0;
+    for (int i = 0; i < n_levels; ++i) {
+        if (levels[i] < 0 || levels[i] > ctx->cfg.L_max || n[i] < 0) return 0;
+        tot += align256(make_level_layout(ctx->cfg, levels[i], n[i], opts[i]).bytes);
+    }
+    return tot;
+}
+
+int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, const int64_t *n,
+                       const double *const *xi_dev, const mlmc_level_opts *opts, void *ws_dev,
+                       size_t ws_bytes, double *const *y_dev, mlmc_level_stats *stats_host,
+                       int32_t use_graph, void *stream)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (n_levels < 1 || n_levels > 16 || !levels || !n || !xi_dev || !opts || !ws_dev)
+        return fail(ctx, MLMC_EINVAL, "sample_levels: bad arguments");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    std::vector<level_layout> LL(n_levels);
+    std::vector<size_t> off(n_levels);
+    size_t tot = 0;
+    for (int i = 0; i < n_levels; ++i) {
+        int rc = check_level(ctx, levels[i]);
+        if (rc) return rc;
+        if ((rc = check_opts(ctx, &opts[i]))) return rc;
+        if (n[i] < 0 || n[i] > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
+        if (n[i] > 0 && !xi_dev[i]) return fail(ctx, MLMC_EINVAL, "null xi");
+        LL[i] = make_level_layout(ctx->cfg, levels[i], n[i], opts[i]);
+        off[i] = tot;
+        tot += align256(LL[i].bytes);
+    }
+    if (ws_bytes < tot) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, tot);
+    hipStream_t st = (hipStream_t)stream;
+    // streams and events for the fork/join (created once, default priority)
+    const size_t need = 2 * (size_t)n_levels;
+    while (ctx->lstreams.size() < need) {
+        hipStream_t s2;
+        HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        ctx->lstreams.push_back(s2);
+    }
+    while (ctx->levents.size() < 2 * need + 1) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->levents.push_back(e);
+    }
+    // os: the stream the fork starts from and the join ends on
+    auto enqueue_all = [&](hipStream_t os) -> int {
+        hipEvent_t fork = ctx->levents[0];
+        HIPCHK(hipEventRecord(fork, os));
+        for (int i = 0; i < n_levels; ++i) {
+            hipStream_t sf = ctx->lstreams[2 * i], scs = ctx->lstreams[2 * i + 1];
+            HIPCHK(hipStreamWaitEvent(sf, fork, 0));
+            // the coarse stream joins only when it has work (every fork is joined back)
+            if (levels[i] > 0 && n[i] > 0) HIPCHK(hipStreamWaitEvent(scs, fork, 0));
+            void *w = (char *)ws_dev + off[i];
+            int rc = level_enqueue(ctx, levels[i], n[i], xi_dev[i], opts[i], w, LL[i], nullptr, nullptr,
+                                   y_dev ? y_dev[i] : nullptr, nullptr, sf, scs, ctx->levents[1 + 2 * i]);
+            if (rc) return rc;
+            HIPCHK(hipEventRecord(ctx->levents[2 + 2 * i], sf));
+            HIPCHK(hipStreamWaitEvent(os, ctx->levents[2 + 2 * i], 0));
+
+        }
+        return MLMC_OK;
+    };
+    if (stats_host) HIPCHK(hipEventRecord(ctx->ev0, st));
+    if (use_graph) {
+        std::vector<uintptr_t> key = {(uintptr_t)n_levels, (uintptr_t)ws_dev};
+        for (int i = 0; i < n_levels; ++i) {
+            key.push_back((uintptr_t)levels[i]);
+            key.push_back((uintptr_t)n[i]);
+            key.push_back((uintptr_t)xi_dev[i]);
+            key.push_back(y_dev ? (uintptr_t)y_dev[i] : 0);
+            const unsigned char *ob = (const unsigned char *)&opts[i];
+            for (size_t b = 0; b < sizeof(mlmc_level_opts); b += sizeof(uintptr_t)) {
+                uintptr_t v = 0;
+                memcpy(&v, ob + b, std::min(sizeof(uintptr_t), sizeof(mlmc_level_opts) - b));
+                key.push_back(v);
+            }
+        }
+        for (auto &row : ctx->ir_variant)
+            for (int v : row) key.push_back((uintptr_t)v);
+        if (!ctx->graph_exec || key != ctx->graph_key) {
+            if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+            if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+            ctx->graph_exec = nullptr;
+            ctx->graph = nullptr;
+            // captured on a stream of the context (the caller's stream may be
+            // the legacy null stream, which cannot be captured); the graph is
+            // then launched on the caller's stream
+            if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            ctx->capturing = true;
+            HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_all(ctx->cap_stream);
+            hipGraph_t gr = nullptr;
+            const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &gr);
+            ctx->capturing = false;
+            if (rc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(ctx, MLMC_EHIP, "graph capture: %s", hipGetErrorString(ec));
+            ctx->graph = gr;
+            HIPCHK(hipGraphInstantiate(&ctx->graph_exec, gr, nullptr, nullptr, 0));
+            ctx->graph_key = key;
+        }
+        HIPCHK(hipGraphLaunch(ctx->graph_exec, st));
+    } else {
+        int rc = enqueue_all(st);
+        if (rc) return rc;
+    }
+    if (stats_host) {
+        HIPCHK(hipEventRecord(ctx->ev1, st));
+        HIPCHK(hipStreamSynchronize(st));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        int any_noconv = 0;
+        for (int i = 0; i < n_levels; ++i) {
+            double h[8] = {};
+            if (n[i] > 0)
+                HIPCHK(hipMemcpy(h, at<double>((char *)ws_dev + off[i], LL[i].off_sums), 7 * 8, hipMemcpyDeviceToHost));
+            fill_stats(&stats_host[i], n[i], h, ms);
+            any_noconv |= stats_host[i].n_noconv > 0;
+        }
+        return any_noconv ? MLMC_ENOCONV : MLMC_OK;
+    }
+    return MLMC_OK;
+}
+
+int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                  const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes, int32_t *chosen,
+                  void *stream)
+{
+    int rc = check_level(ctx, level);
+    if (rc) return rc;
+    if ((rc = check_opts(ctx, opts))) return rc;
+    if (n < 1 || !xi_dev || !ws_dev) return fail(ctx, MLMC_EINVAL, "autotune: bad arguments");
+    const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
+    if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
+    if (opts->solver == MLMC_MINRES) return MLMC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int dt = opts->solver == MLMC_DIRECT ? MLMC_F64 : opts->factor_dtype;
+    const bool was = ctx->prof_on;
+    ctx->prof_on = false;
+    for (int g = 0; g < (level > 0 ? 2 : 1); ++g) {
+        const int lv = level - g, nn = ctx->cfg.n0 << lv;
+        const grid_layout &L = g ? LL.coarse : LL.fine;
+        void *w = at<void>(ws_dev, g ? LL.off_coarse : LL.off_fine);
+        int best = 0;
+        if (nn >= 64) {
+            float best_ms = 1e30f;
+            for (int var = 1; var <= 2; ++var) {
+                ctx->ir_variant[dt][ilog2(nn)] = var;
+                for (int rep = 0; rep < 3; ++rep) {
+                    if (rep == 1) HIPCHK(hipEventRecord(ctx->ev0, st));
+                    rc = solve_grid(ctx, L, lv, xi_dev, *opts, g ? opts->eps_coarse : opts->eps_fine, w,
+                                    at<double>(ws_dev, g ? LL.off_qc : LL.off_qf), nullptr, st);
+                    if (rc) return rc;
+                }
+                HIPCHK(hipEventRecord(ctx->ev1, st));
+                HIPCHK(hipEventSynchronize(ctx->ev1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = var;
+                }
+            }
+            ctx->ir_variant[dt][ilog2(nn)] = best;
+        }
+        if (chosen) chosen[g] = best;
+    }
+    ctx->prof_on = was;
     return MLMC_OK;
 }
 

@@ -610,15 +610,26 @@ hipError_t ls(int nb, const double *sc, const double *beta, const void *factor, 
     return hipGetLastError();
 }
 
-template <typename Tst, int M>
-hipError_t li(const ir_args &g, hipStream_t st)
+// Refinement kernel variants: G waves per block-row pair (1 or 2); the FP64
+// n = 256 variant keeps no register double-buffer (register budget).
+template <typename Tst, int M, int G> struct ir_pref { static constexpr bool v = true; };
+template <int G> struct ir_pref<double, 256, G> { static constexpr bool v = false; };
+
+template <typename Tst, int M, int G>
+hipError_t li_g(const ir_args &g, hipStream_t st)
 {
-    constexpr int G = solve_cfg<Tst, M>::G;
-    constexpr bool PREF = solve_cfg<Tst, M>::PREF;
+    constexpr bool PREF = ir_pref<Tst, M, G>::v;
     hipLaunchKernelGGL((k_ir_blk<Tst, M, G, PREF>), dim3(g.nblocks), dim3(32 * G * M / 16), 0, st, g.n,
                        g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps,
                        g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters);
     return hipGetLastError();
+}
+
+template <typename Tst, int M>
+hipError_t li(const ir_args &g, hipStream_t st)
+{
+    int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
+    return G == 2 ? li_g<Tst, M, 2>(g, st) : li_g<Tst, M, 1>(g, st);
 }
 
 template <typename Tst>

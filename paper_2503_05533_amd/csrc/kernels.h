@@ -34,6 +34,7 @@ struct ir_args {
     uint32_t *state;
     double *relres, *q;
     int32_t *iters;
+    int variant;  // refinement-kernel variant (0: built-in default; n >= 64: waves per row pair)
 };
 
 hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi,

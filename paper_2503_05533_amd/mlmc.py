@@ -24,7 +24,7 @@ ST_CONVERGED, ST_PROMOTED, ST_NONFINITE, ST_IMAX = 1, 2, 4, 8
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
            "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
            "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
-           "mlmc_profile_read"]
+           "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune"]
 
 
 class MLMCError(RuntimeError):
@@ -93,6 +93,15 @@ def load_library():
                                   ctypes.POINTER(_Result), vp]
     lib.mlmc_grad.argtypes = [vp, i32, i64, vp, vp, ctypes.POINTER(_LevelOpts), dbl, vp,
                               ctypes.c_size_t, vp, vp]
+    lib.mlmc_levels_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                                ctypes.POINTER(_LevelOpts)]
+    lib.mlmc_levels_workspace_bytes.restype = ctypes.c_size_t
+    lib.mlmc_sample_levels.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                       ctypes.POINTER(vp), ctypes.POINTER(_LevelOpts), vp,
+                                       ctypes.c_size_t, ctypes.POINTER(vp), ctypes.POINTER(_LevelStats),
+                                       i32, vp]
+    lib.mlmc_autotune.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp, ctypes.c_size_t,
+                                  ctypes.POINTER(i32), vp]
     lib.mlmc_profile.argtypes = [vp, i32]
     lib.mlmc_profile_read.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
@@ -251,6 +260,20 @@ class MLMC:
             out["stats"] = {k: getattr(sts, k) for k, _ in _LevelStats._fields_}
         return out
 
+    def plan_levels(self, levels, xis, opts, use_graph=True):
+        """A LevelPlan: opts is a list of dicts (dtype, solver, eps_fine, eps_coarse, promote)."""
+        return LevelPlan(self, levels, xis, opts, use_graph)
+
+    def autotune(self, level, xi, dtype="f32", solver="direct_ir", eps_fine=1e-6, eps_coarse=1e-6):
+        xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
+        o = self._opts(dtype, solver, eps_fine, eps_coarse, True)
+        nb = self.lib.mlmc_workspace_bytes(self.h, level, xi.shape[0], ctypes.byref(o))
+        ws = self._workspace(nb)
+        ch = (ctypes.c_int32 * 2)()
+        self._check(self.lib.mlmc_autotune(self.h, level, xi.shape[0], _ptr(xi), ctypes.byref(o),
+                                           _ptr(ws), ws.numel(), ch, _stream()), "autotune")
+        return list(ch)
+
     def estimate(self, tol, n_init=1000, dtypes=None, solver="direct_ir", mixed=True):
         L1 = self.cfg.L_max + 1
         dts = (ctypes.c_int * L1)(*[DTYPES[d] for d in (dtypes or ["f32"] * L1)])
@@ -277,6 +300,42 @@ class MLMC:
                                        float(eps_adjoint), _ptr(ws), ws.numel(), _ptr(g), _stream()),
                     "grad")
         return fw["q"], g
+
+
+class LevelPlan:
+    """Persistent buffers for repeated mlmc_sample_levels calls on fixed inputs.
+
+    levels, xis (device tensors [N_l, K]) and per-level options are fixed at
+    construction; run() launches every level concurrently (optionally as one
+    replayed HIP graph) and returns the Y tensors.
+    """
+
+    def __init__(self, ctx, levels, xis, opts, use_graph=True):
+        self.ctx, self.use_graph = ctx, use_graph
+        self.levels = list(levels)
+        self.xis = [x.to(device=ctx.device, dtype=torch.float64).contiguous() for x in xis]
+        L = len(self.levels)
+        self.c_levels = (ctypes.c_int32 * L)(*self.levels)
+        self.c_n = (ctypes.c_int64 * L)(*[x.shape[0] for x in self.xis])
+        self.c_xi = (ctypes.c_void_p * L)(*[x.data_ptr() for x in self.xis])
+        self.c_opts = (_LevelOpts * L)(*[MLMC._opts(**o) for o in opts])
+        nb = ctx.lib.mlmc_levels_workspace_bytes(ctx.h, L, self.c_levels, self.c_n, self.c_opts)
+        if nb == 0:
+            raise MLMCError("bad level plan")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=ctx.device)
+        self.y = [torch.empty(x.shape[0], dtype=torch.float64, device=ctx.device) for x in self.xis]
+        self.c_y = (ctypes.c_void_p * L)(*[y.data_ptr() for y in self.y])
+
+    def run(self, stats=False):
+        L = len(self.levels)
+        st = (_LevelStats * L)() if stats else None
+        rc = self.ctx._check(self.ctx.lib.mlmc_sample_levels(
+            self.ctx.h, L, self.c_levels, self.c_n, self.c_xi, self.c_opts, _ptr(self.ws),
+            self.ws.numel(), self.c_y, st, 1 if self.use_graph else 0, _stream()), "sample_levels")
+        out = dict(y=self.y, rc=rc)
+        if stats:
+            out["stats"] = [{k: getattr(x, k) for k, _ in _LevelStats._fields_} for x in st]
+        return out
 
 
 class MLMCQoI(torch.autograd.Function):
