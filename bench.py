@@ -3,16 +3,28 @@
 A step is one pass of the whole hot path over one batch: for every level l
 of the workload, N_l samples, each a fine solve on grid l and (l >= 1) a
 coarse solve on grid l-1 from the same xi row, paired into Y_l, with the
-level sums.  The mixed path factorises in FP32 and refines in FP64 to the
-level accuracy delta_l of the adaptive rule; the FP64 path factorises and
-solves in FP64.  Inputs (xi) are resident in HBM before the timed region.
+level sums.  All levels run concurrently (fine and coarse grids on their own
+streams) as one replayed HIP graph.  The mixed path factorises in FP32 and
+refines in FP64 to the level accuracy delta_l of the adaptive rule; the FP64
+path factorises and solves in FP64.  Inputs (xi) are resident in HBM before
+the timed region.
 
-Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
-one GPU.
+Legs:
+  * timed: W warm-up steps, then K steps between two device synchronisations
+    (the value);
+  * profiled: the same K steps launched eagerly with HIP events around each
+    kernel launch on its own stream (per-kernel device time; the roofline of
+    the dominant kernel);
+  * per level: each level alone, event-timed (samples/s per level);
+  * FP64: the same timed leg with the FP64 direct path;
+  * time to RMSE: Algorithm 4.1 (adaptive MLMC) to an absolute tolerance,
+    mixed and FP64, wall time on the host;
+  * CPU: the FP64 oracle on a bounded sample of the workload, host cores.
+
+Prints one JSON line.  --gpus N > 1 is refused: the path runs on one GPU.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -21,7 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "PDE samples/s per level + MLMC time-to-RMSE, mixed+IR vs FP64 on same GPU"
-PEAK = {"f64_alu": 78.6, "f32_alu": 157.3, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s
+PEAK = {"f64": 78.6, "f32": 157.3, "hbm": 8000.0}  # TFLOP/s (FP64, FP32 MFMA), GB/s
+DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 
 
 def factor_flops(n):
@@ -29,23 +42,55 @@ def factor_flops(n):
     return float((n - 1) ** 4)
 
 
+def factor_entries(n):
+    """Entries of the stored factor per sample: m diagonal blocks of the
+    block-tridiagonal LDL^T, each the symmetric inverse Schur complement of
+    size n (padded), stored as its upper tr x tr tiles."""
+    m = n - 1
+    tr = 16 if n >= 64 else (2 if n <= 16 else 4)
+    tn = n // tr
+    return m * tn * (tn + 1) // 2 * tr * tr
+
+
+def refine_bytes(n, trips, fbytes):
+    """Algorithmic HBM bytes per sample of the refinement kernel: the initial
+    solve and `trips` corrections each read the factor twice (forward and
+    backward block sweeps) and the row couplings and scaling; every residual
+    (1 + trips) reads the nodal coefficient and the iterate; x is written."""
+    m = n - 1
+    N = m * n
+    per_solve = 2 * factor_entries(n) * fbytes + 3 * N * 8
+    per_resid = (n + 1) ** 2 * 8 + N * 8
+    return (1 + trips) * (per_solve + per_resid) + N * 8
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=5)
-    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="mlmc4_n16-128_K64")
     p.add_argument("--dtype", default="f32")
+    p.add_argument("--no-graph", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-per-level", action="store_true")
+    p.add_argument("--autotune", action="store_true")
+    p.add_argument("--ttr-tol", type=float, default=2e-5,
+                   help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     return p.parse_args()
+
+
+def log(*a):
+    print("bench:", *a, flush=True)
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus,
+        print("bench.py: the path runs on one GPU; --gpus %d is not supported "
+              "(samples are independent: see the sharding notes in the design document)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -63,92 +108,136 @@ def main():
     ctx = MLMC(cfg, device="cuda:0")
     eps = ctx.accuracy_targets(L)
     cells = [ctx.level_cells(l) for l in levels]
-    print("bench: workload %s levels %s N %s eps %s" % (a.workload, cells, Ns, eps), flush=True)
+    log("workload %s cells %s N %s eps %s" % (a.workload, cells, Ns, ["%.3e" % e for e in eps]))
     xis = [ctx.fill_xi(l, 0, N) for l, N in zip(levels, Ns)]
     torch.cuda.synchronize()
 
-    def step(dtype, solver):
-        out = []
-        for l, N, xi in zip(levels, Ns, xis):
-            r = ctx.sample_level(l, xi, dtype=dtype, solver=solver, eps_fine=eps[l],
-                                 eps_coarse=eps[l - 1] if l > 0 else 0.0, stats=False)
-            out.append(r)
-        return out
+    def opts(dtype, solver):
+        return [dict(dtype=dtype, solver=solver, eps_fine=eps[l],
+                     eps_coarse=eps[l - 1] if l > 0 else 0.0) for l in levels]
 
-    def timed(dtype, solver, steps, warmup, per_level=False, profile=False):
+    om, o64 = opts(a.dtype, "direct_ir"), opts("f64", "direct")
+    tuned = None
+    if a.autotune:
+        tuned = {cells[i]: ctx.autotune(l, xis[i], **{k: v for k, v in om[i].items() if k != "promote"})
+                 for i, l in enumerate(levels)}
+        log("autotuned refinement variants", tuned)
+    total = float(sum(Ns))
+
+    def timed(plan, steps, warmup):
         for _ in range(warmup):
-            step(dtype, solver)
+            plan.run()
         torch.cuda.synchronize()
-        if profile:
-            ctx.profile(True)  # kernel events over the timed steps only
-        lvl_ms = [0.0] * len(levels)
         t0 = time.perf_counter()
         for _ in range(steps):
-            if per_level:
-                for i, (l, xi) in enumerate(zip(levels, xis)):
-                    ev0 = torch.cuda.Event(enable_timing=True)
-                    ev1 = torch.cuda.Event(enable_timing=True)
-                    ev0.record()
-                    ctx.sample_level(l, xi, dtype=dtype, solver=solver, eps_fine=eps[l],
-                                     eps_coarse=eps[l - 1] if l > 0 else 0.0, stats=False)
-                    ev1.record()
-                    ev1.synchronize()
-                    lvl_ms[i] += ev0.elapsed_time(ev1)
-            else:
-                step(dtype, solver)
+            plan.run()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        return ms, [v / steps for v in lvl_ms]
+        return (time.perf_counter() - t0) * 1e3 / steps
 
-    # ---- mixed path (timed region with per-kernel events)
-    ms_mixed, _ = timed(a.dtype, "direct_ir", a.steps, a.warmup, profile=True)
+    # ---- mixed path: the timed leg (graph replays of the concurrent step)
+    plan_m = ctx.plan_levels(levels, xis, om, use_graph=not a.no_graph)
+    ms_mixed = timed(plan_m, a.steps, a.warmup)
+    value = total / (ms_mixed / 1e3)
+    log("mixed %.3f ms/step, %.4g samples/s" % (ms_mixed, value))
+    st_m = ctx.plan_levels(levels, xis, om, use_graph=False).run(stats=True)["stats"]
+
+    # ---- profiled leg: the same concurrent step launched eagerly
+    eager = ctx.plan_levels(levels, xis, om, use_graph=False)
+    eager.run()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        eager.run()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / a.steps
     prof = {}
-    for kind in ("field", "assembly", "factor", "solve", "residual"):
-        for n in sorted(set(cells + [c // 2 for c in cells if c > w["n0"]])):
+    grids = sorted(set(cells + [c // 2 for c in cells if c > w["n0"]]))
+    for kind in ctx.KINDS:
+        for n in grids:
             r = ctx.profile_read(kind, n)
             if r["launches"]:
                 prof[(kind, n)] = r
     ctx.profile(False)
-    _, lvl_mixed = timed(a.dtype, "direct_ir", 1, 0, per_level=True)
-    st = ctx.sample_level(levels[-1], xis[-1], dtype=a.dtype, solver="direct_ir",
-                          eps_fine=eps[levels[-1]], eps_coarse=eps[levels[-1] - 1], stats=True)
-    total = float(sum(Ns))
-    value = total / (ms_mixed / 1e3)
+
+    # mean corrections per grid (fine and coarse uses weighted by samples)
+    trips = {}
+    for i, l in enumerate(levels):
+        for n, t in [(cells[i], st_m[i]["mean_iters"])] + \
+                    ([(cells[i] // 2, st_m[i]["mean_iters_coarse"])] if l > 0 else []):
+            s0, t0_ = trips.get(n, (0, 0.0))
+            trips[n] = (s0 + Ns[i], t0_ + Ns[i] * t)
+    trips = {n: v[1] / v[0] for n, v in trips.items()}
+
+    # ---- roofline of the dominant kernel of the mixed step
+    (kind, n), r = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = r["ms"] / r["launches"]
+    per_launch = r["samples"] / r["launches"]
+    if kind == "factor":
+        work = factor_flops(n) * per_launch
+        achieved = work / (avg_ms * 1e-3) / 1e12
+        peak = PEAK["f64"] if a.dtype == "f64" else PEAK["f32"]
+        roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    traffic=None)
+        per_unit = "%.4g flops per sample ((n-1)^4)" % factor_flops(n)
+    else:
+        per = refine_bytes(n, trips.get(n, 1.0), DT_BYTES[a.dtype])
+        work = per * per_launch
+        achieved = work / (avg_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
+                    frac=achieved / PEAK["hbm"], traffic=None)
+        per_unit = "%.4g bytes per sample at %.3f mean corrections" % (per, trips.get(n, 1.0))
+    roof.update(kernel="%s n=%d" % (kind, n), avg_launch_ms=avg_ms, launches=r["launches"],
+                samples_per_launch=per_launch, per_unit=per_unit)
+    log("dominant kernel", roof)
+
+    # ---- per-level throughput (each level alone)
+    def per_level(o):
+        out = []
+        for i, l in enumerate(levels):
+            p = ctx.plan_levels([l], [xis[i]], [o[i]], use_graph=False)
+            p.run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            p.run()
+            e1.record()
+            e1.synchronize()
+            out.append(Ns[i] / (e0.elapsed_time(e1) / 1e3))
+        return out
+
+    lvl_m = None if a.no_per_level else per_level(om)
 
     # ---- FP64 path on the same workload
     fp64 = None
     if not a.no_fp64:
-        ms64, lvl64 = timed("f64", "direct", max(1, a.steps // 2), 1)
-        _, lvl64 = timed("f64", "direct", 1, 0, per_level=True)
+        plan_d = ctx.plan_levels(levels, xis, o64, use_graph=not a.no_graph)
+        ms64 = timed(plan_d, a.steps, a.warmup)
+        log("fp64 %.3f ms/step" % ms64)
         fp64 = dict(ms_per_step=ms64, samples_per_s=total / (ms64 / 1e3),
-                    per_level_samples_per_s=[N / (t / 1e3) for N, t in zip(Ns, lvl64)])
+                    per_level_samples_per_s=None if a.no_per_level else per_level(o64))
+        del plan_d
 
-    # ---- roofline of the dominant kernel of the mixed step
-    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
-    (kind, n), r = dom
-    avg_ms = r["ms"] / r["launches"]
-    if kind == "factor":
-        work = factor_flops(n) * r["samples"] / r["launches"]
-        achieved = work / (avg_ms * 1e-3) / 1e12
-        peak = PEAK["f32_alu"] if a.dtype != "f64" else PEAK["f64_alu"]
-        roof = dict(bound="alu", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                    traffic=None)
-    else:
-        m = n - 1
-        nbytes = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[a.dtype]
-        T = (n // 8) * (n // 8 + 1) // 2 * 64 if n >= 64 else (m + 1) * m
-        work = 2.0 * m * T * nbytes * r["samples"] / r["launches"]
-        achieved = work / (avg_ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",
-                    frac=achieved / PEAK["hbm"], traffic=None)
-    roof["kernel"] = "%s n=%d" % (kind, n)
-    roof["avg_launch_ms"] = avg_ms
-    roof["launches"] = r["launches"]
+    # ---- time to RMSE: Algorithm 4.1 at an absolute tolerance
+    ttr = None
+    if a.ttr_tol > 0:
+        dts = [a.dtype] * (L + 1)
+        ttr = dict(tol=a.ttr_tol)
+        runs = [("mixed", dts, "direct_ir", True)]
+        if not a.no_fp64:
+            runs.append(("fp64", ["f64"] * (L + 1), "direct", False))
+        for name, d, solver, mixed in runs:
+            res = ctx.estimate(a.ttr_tol, n_init=1000, dtypes=d, solver=solver, mixed=mixed)
+            ttr[name] = dict(wall_s=res["wall_s"], gpu_ms=res["gpu_ms"], estimate=res["estimate"],
+                             rmse_est=res["var_est"] ** 0.5, L=res["L"], N=res["N"],
+                             converged=res["converged"])
+            log("time to RMSE %s" % name, ttr[name])
+        if "fp64" in ttr:
+            ttr["speedup"] = ttr["fp64"]["wall_s"] / ttr["mixed"]["wall_s"]
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not a.no_cpu:
-        import numpy as np
         import oracle
         phis = {}
         t_per = []
@@ -177,8 +266,9 @@ def main():
             samples_desc.append("%d/%d" % (s, N))
         cpu_time = sum(t * N for t, N in zip(t_per, Ns))
         cpu = dict(value=total / cpu_time, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
-                   sample="FP64 banded Cholesky on %s samples per level (fine+coarse), scaled to "
-                          "the full workload" % ",".join(samples_desc))
+                   sample="FP64 banded Cholesky on the first %s samples of each level (fine+coarse), "
+                          "per-sample time scaled to the full workload" % ",".join(samples_desc))
+        log("cpu oracle", cpu)
 
     line = {
         "metric": METRIC,
@@ -191,17 +281,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": a.dtype,
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "cells": cells, "N_l": Ns, "K": K,
                    "sigma2": w["sigma2"], "corr_len": w["corr_len"], "eps_l": eps,
-                   "path": "%s factor + FP64 refinement; residual, update, sums FP64" % a.dtype},
-        "per_level_samples_per_s": [N / (t / 1e3) for N, t in zip(Ns, lvl_mixed)],
+                   "path": "%s factor + FP64 residual/refinement/sums, all levels concurrent, "
+                           "%s" % (a.dtype, "eager" if a.no_graph else "one HIP graph per step")},
+        "per_level_samples_per_s": lvl_m,
         "fp64": fp64,
         "speedup_vs_fp64": (value / fp64["samples_per_s"]) if fp64 else None,
-        "mean_ir_trips_finest": st["stats"]["mean_iters"],
+        "mean_corrections": {str(k): v for k, v in sorted(trips.items())},
+        "promoted": [s["n_promoted"] for s in st_m],
+        "time_to_rmse": ttr,
         "roofline": roof,
-        "kernel_ms_per_step": {"%s_n%d" % k: v["ms"] / a.steps for k, v in prof.items()},
+        "eager_ms_per_step": ms_eager,
+        "kernel_ms_per_step": {"%s_n%d" % k: v["ms"] / a.steps for k, v in sorted(prof.items())},
+        "autotuned": tuned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

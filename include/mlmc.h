@@ -96,6 +96,7 @@ typedef struct {
     int64_t n_promoted, n_noconv;    /* samples re-solved / not converged */
     double mean_iters;               /* mean corrections (IR) or iterations (MINRES), fine grid */
     double gpu_ms;                   /* device time of the call (event-timed) */
+    double mean_iters_coarse;        /* the same for the coarse partner (0 at level 0) */
 } mlmc_level_stats;
 
 typedef struct {
@@ -230,7 +231,10 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * events on the caller's stream and records (kernel kind, grid n, samples).
  * mlmc_profile_read synchronises, and for kind (0 field, 1 assembly,
  * 2 factor, 3 refinement (initial solve + Algorithm 2.1 loop), 4 residual,
- * 5 MINRES) and grid n returns the summed device time,
+ * 5 MINRES, 6 FP64 re-factorisation of promoted samples, 7 FP64 refinement
+ * of promoted samples; 6 and 7 launch over the promotion slots and exit at
+ * once for slots beyond the device-side count) and grid n returns the
+ * summed device time,
  * the number of launches and the summed samples over all recorded launches,
  * then keeps the records (reset with mlmc_profile(ctx, 1) again). */
 int mlmc_profile(mlmc_ctx *ctx, int32_t enable);

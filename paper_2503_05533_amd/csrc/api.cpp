@@ -349,7 +349,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         HIPCHK(launch_zero_int(cnt, 1, st));
         HIPCHK(launch_collect(S, state, idx, cnt, st));
         HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
-        PROF(2, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
+        PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
                                      pf, idx, cnt, 0, state, st));
         ir_args p = g;
         p.nblocks = np;
@@ -359,7 +359,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         p.imax = ctx->cfg.ir_max_iter;
         p.direct = 0;
         p.variant = ctx->ir_variant[MLMC_F64][ilog2(n)];
-        PROF(3, n, np, launch_ir(MLMC_F64, p, st));
+        PROF(7, n, np, launch_ir(MLMC_F64, p, st));
     }
     return MLMC_OK;
 }
@@ -412,19 +412,22 @@ int level_enqueue(mlmc_ctx *ctx, int level, int64_t n, const double *xi, const m
     int rc = solve_grid(ctx, LL.fine, level, xi, o, o.eps_fine, wf, qf, at<int32_t>(wf, LL.fine.off_iters), sf);
     if (rc) return rc;
     const uint32_t *stc = nullptr;
+    const int32_t *itc = nullptr;
     if (level > 0) {
         void *wc = at<void>(ws_dev, LL.off_coarse);
         rc = solve_grid(ctx, LL.coarse, level - 1, xi, o, o.eps_coarse, wc, qc,
                         at<int32_t>(wc, LL.coarse.off_iters), scs);
         if (rc) return rc;
         stc = at<uint32_t>(wc, LL.coarse.off_state);
+        itc = at<int32_t>(wc, LL.coarse.off_iters);
         if (scs != sf) {
             HIPCHK(hipEventRecord(ev, scs));
             HIPCHK(hipStreamWaitEvent(sf, ev, 0));
         }
     }
     HIPCHK(launch_pair_sums((int)n, qf, level > 0 ? qc : nullptr, at<uint32_t>(wf, LL.fine.off_state), stc,
-                            at<int32_t>(wf, LL.fine.off_iters), y, status, at<double>(ws_dev, LL.off_sums), sf));
+                            at<int32_t>(wf, LL.fine.off_iters), itc, y, status, at<double>(ws_dev, LL.off_sums),
+                            sf));
     return MLMC_OK;
 }
 
@@ -440,6 +443,7 @@ void fill_stats(mlmc_level_stats *out, int64_t n, const double *h, double ms)
         out->n_promoted = (int64_t)h[4];
         out->n_noconv = (int64_t)h[5];
         out->mean_iters = h[6] / (double)n;
+        out->mean_iters_coarse = h[7] / (double)n;
     }
     out->gpu_ms = ms;
 }
@@ -585,8 +589,8 @@ int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
     if (iters_dev) HIPCHK(hipMemcpyAsync(iters_dev, it, n * 4, hipMemcpyDeviceToDevice, st));
     double *sums = at<double>(ws_dev, LL.off_sums);
     HIPCHK(launch_pair_sums((int)n, q_dev, nullptr, at<uint32_t>(ws, L.off_state), nullptr, it, nullptr,
-                            status_dev, sums, st));
-    HIPCHK(hipMemcpyAsync(ctx->h_sums, sums, 7 * 8, hipMemcpyDeviceToHost, st));
+                            nullptr, status_dev, sums, st));
+    HIPCHK(hipMemcpyAsync(ctx->h_sums, sums, 8 * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return ctx->h_sums[5] > 0 ? MLMC_ENOCONV : MLMC_OK;
 }
@@ -611,7 +615,7 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
     if (rc) return rc;
     if (stats_host) {
         HIPCHK(hipEventRecord(ctx->ev1, st));
-        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, at<double>(ws_dev, LL.off_sums), 7 * 8, hipMemcpyDeviceToHost, st));
+        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, at<double>(ws_dev, LL.off_sums), 8 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -743,7 +747,7 @@ int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, c
         for (int i = 0; i < n_levels; ++i) {
             double h[8] = {};
             if (n[i] > 0)
-                HIPCHK(hipMemcpy(h, at<double>((char *)ws_dev + off[i], LL[i].off_sums), 7 * 8, hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(h, at<double>((char *)ws_dev + off[i], LL[i].off_sums), 8 * 8, hipMemcpyDeviceToHost));
             fill_stats(&stats_host[i], n[i], h, ms);
             any_noconv |= stats_host[i].n_noconv > 0;
         }

@@ -79,7 +79,7 @@ hipError_t launch_reset_subset(int P, const int *idx, const int *count, uint32_t
 hipError_t launch_zero_int(int *p, int n, hipStream_t st);
 hipError_t launch_collect(int S, const uint32_t *state, int *idx, int *cnt, hipStream_t st);
 hipError_t launch_pair_sums(int S, const double *qf, const double *qc, const uint32_t *stf,
-                            const uint32_t *stc, const int32_t *itf, double *y, uint8_t *status,
-                            double *sums, hipStream_t st);
+                            const uint32_t *stc, const int32_t *itf, const int32_t *itc, double *y,
+                            uint8_t *status, double *sums, hipStream_t st);
 
 }  // namespace mlmc

@@ -620,12 +620,13 @@ __global__ __launch_bounds__(1024) void k_pair_sums(int S, const double *__restr
                                                     const uint32_t *__restrict__ stf,
                                                     const uint32_t *__restrict__ stc,
                                                     const int32_t *__restrict__ itf,
+                                                    const int32_t *__restrict__ itc,
                                                     double *__restrict__ y,
                                                     uint8_t *__restrict__ status,
                                                     double *__restrict__ sums)
 {
     __shared__ double red[1024];
-    double sy = 0, sy2 = 0, sf = 0, scc = 0, npro = 0, nnc = 0, sit = 0;
+    double sy = 0, sy2 = 0, sf = 0, scc = 0, npro = 0, nnc = 0, sit = 0, sitc = 0;
     for (int s = threadIdx.x; s < S; s += 1024) {
         const double f = qf[s], c = qc ? qc[s] : 0.0;
         const double yv = f - c;
@@ -639,9 +640,10 @@ __global__ __launch_bounds__(1024) void k_pair_sums(int S, const double *__restr
         npro += ((a | bcs) & ST_PROMOTED) ? 1.0 : 0.0;
         nnc += (!(a & ST_CONVERGED) || !(bcs & ST_CONVERGED)) ? 1.0 : 0.0;
         sit += itf ? (double)itf[s] : 0.0;
+        sitc += itc ? (double)itc[s] : 0.0;
     }
-    double v[7] = {sy, sy2, sf, scc, npro, nnc, sit};
-    for (int q = 0; q < 7; ++q) {
+    double v[8] = {sy, sy2, sf, scc, npro, nnc, sit, sitc};
+    for (int q = 0; q < 8; ++q) {
         double r = block_sum<1024>(v[q], red);
         if (threadIdx.x == 0) sums[q] = r;
     }
@@ -895,11 +897,11 @@ hipError_t launch_collect(int S, const uint32_t *state, int *idx, int *cnt, hipS
 }
 
 hipError_t launch_pair_sums(int S, const double *qf, const double *qc, const uint32_t *stf,
-                            const uint32_t *stc, const int32_t *itf, double *y, uint8_t *status,
-                            double *sums, hipStream_t st)
+                            const uint32_t *stc, const int32_t *itf, const int32_t *itc, double *y,
+                            uint8_t *status, double *sums, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pair_sums, dim3(1), dim3(1024), 0, st, S, qf, qc, stf, stc, itf, y, status,
-                       sums);
+    hipLaunchKernelGGL(k_pair_sums, dim3(1), dim3(1024), 0, st, S, qf, qc, stf, stc, itf, itc, y,
+                       status, sums);
     return hipGetLastError();
 }
 

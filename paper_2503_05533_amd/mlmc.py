@@ -50,7 +50,8 @@ class _LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sum_y", ctypes.c_double), ("sum_y2", ctypes.c_double),
                 ("sum_qf", ctypes.c_double), ("sum_qc", ctypes.c_double),
                 ("n_promoted", ctypes.c_int64), ("n_noconv", ctypes.c_int64),
-                ("mean_iters", ctypes.c_double), ("gpu_ms", ctypes.c_double)]
+                ("mean_iters", ctypes.c_double), ("gpu_ms", ctypes.c_double),
+                ("mean_iters_coarse", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -202,7 +203,8 @@ class MLMC:
         o = self._opts(**opt)
         return self.lib.mlmc_workspace_bytes(self.h, level, n, ctypes.byref(o))
 
-    KINDS = {"field": 0, "assembly": 1, "factor": 2, "solve": 3, "residual": 4, "minres": 5}
+    KINDS = {"field": 0, "assembly": 1, "factor": 2, "solve": 3, "residual": 4, "minres": 5,
+             "promote_factor": 6, "promote_solve": 7}
 
     def profile(self, enable=True):
         self._check(self.lib.mlmc_profile(self.h, 1 if enable else 0), "profile")
