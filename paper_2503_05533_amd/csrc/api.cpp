@@ -814,25 +814,32 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     hipStream_t st = (hipStream_t)stream;
     const mlmc_config &c = ctx->cfg;
     const int Lmax = c.L_max;
-    const int64_t chunk_max = 1 << 14;
-    // one workspace and one xi buffer sized for the largest chunk of any level
-    size_t ws_bytes = 0;
+    // Per-level chunk: as many samples as fit a per-level workspace budget, so
+    // that the fine levels fill the GPU; one workspace holds every level's
+    // chunk and the levels of a round run concurrently (mlmc_sample_levels).
+    const int64_t chunk_max = 1 << 18;
+    const size_t level_budget = (size_t)8 << 30;
     std::vector<int64_t> chunk(Lmax + 1);
+    std::vector<mlmc_level_opts> lopt(Lmax + 1);
+    size_t ws_bytes = 0, xi_bytes = 0;
+    std::vector<size_t> xi_off(Lmax + 1);
     for (int l = 0; l <= Lmax; ++l) {
         mlmc_level_opts o{};
         o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
-        o.solver = solver;
+        o.solver = mixed ? solver : MLMC_DIRECT;
         o.promote = 1;
-        // keep each level's workspace near 2 GiB or below
         int64_t ch = chunk_max;
-        while (ch > 16 && make_level_layout(c, l, ch, o).bytes > ((size_t)2 << 30)) ch /= 2;
+        while (ch > 16 && make_level_layout(c, l, ch, o).bytes > level_budget) ch /= 2;
         chunk[l] = ch;
-        ws_bytes = std::max(ws_bytes, make_level_layout(c, l, ch, o).bytes);
+        lopt[l] = o;
+        ws_bytes += align256(make_level_layout(c, l, ch, o).bytes);
+        xi_off[l] = xi_bytes;
+        xi_bytes += align256((size_t)ch * c.K * 8);
     }
     void *ws = nullptr;
-    double *xi = nullptr;
+    char *xi = nullptr;
     HIPCHK(hipMalloc(&ws, ws_bytes));
-    if (hipMalloc(&xi, (size_t)chunk_max * c.K * 8) != hipSuccess) {
+    if (hipMalloc(&xi, xi_bytes) != hipSuccess) {
         (void)hipFree(ws);
         return fail(ctx, MLMC_EHIP, "estimate: out of device memory");
     }
@@ -851,29 +858,37 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     for (int round = 0; round < 200; ++round) {
         double eps[16];
         mlmc_accuracy_targets(ctx, L, eps);
-        for (int l = 0; l <= L && rc >= 0; ++l) {
-            int64_t need = N[l] - done[l];
-            while (need > 0 && rc >= 0) {
-                const int64_t cnt = std::min<int64_t>(need, chunk[l]);
-                rc = mlmc_fill_xi(ctx, l, done[l], cnt, xi, st);
-                if (rc) break;
-                mlmc_level_opts o{};
-                o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
-                o.solver = mixed ? solver : MLMC_DIRECT;
-                o.eps_fine = mixed ? eps[l] : 0.0;
-                o.eps_coarse = mixed && l > 0 ? eps[l - 1] : 0.0;
-                o.promote = 1;
-                mlmc_level_stats stt{};
-                rc = mlmc_sample_level(ctx, l, cnt, xi, &o, ws, ws_bytes, nullptr, nullptr, nullptr,
-                                       nullptr, &stt, st);
-                if (rc < 0) break;
-                if (rc == MLMC_ENOCONV) rc = MLMC_OK;
-                s1[l] += stt.sum_y;
-                s2[l] += stt.sum_y2;
-                gpu_ms += stt.gpu_ms;
-                done[l] += cnt;
-                need -= cnt;
+        // top every level up to N_l: one concurrent multi-level call per chunk
+        while (rc >= 0) {
+            int32_t lv[16];
+            int64_t cnt[16];
+            const double *xp[16];
+            mlmc_level_opts op[16];
+            int nl = 0;
+            for (int l = 0; l <= L; ++l) {
+                const int64_t need = N[l] - done[l];
+                if (need <= 0) continue;
+                cnt[nl] = std::min<int64_t>(need, chunk[l]);
+                double *xl = (double *)(xi + xi_off[l]);
+                if ((rc = mlmc_fill_xi(ctx, l, done[l], cnt[nl], xl, st))) break;
+                lv[nl] = l;
+                xp[nl] = xl;
+                op[nl] = lopt[l];
+                op[nl].eps_fine = mixed ? eps[l] : 0.0;
+                op[nl].eps_coarse = mixed && l > 0 ? eps[l - 1] : 0.0;
+                ++nl;
             }
+            if (rc < 0 || nl == 0) break;
+            mlmc_level_stats stt[16];
+            rc = mlmc_sample_levels(ctx, nl, lv, cnt, xp, op, ws, ws_bytes, nullptr, stt, 0, st);
+            if (rc < 0) break;
+            rc = MLMC_OK;  // non-converged samples are counted in the stats, not fatal
+            for (int i = 0; i < nl; ++i) {
+                s1[lv[i]] += stt[i].sum_y;
+                s2[lv[i]] += stt[i].sum_y2;
+                done[lv[i]] += cnt[i];
+            }
+            gpu_ms += stt[0].gpu_ms;
         }
         if (rc < 0) break;
         yhat.assign(L + 1, 0.0);
