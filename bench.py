@@ -58,24 +58,26 @@ def factor_flops(n):
     return float((n - 1) ** 4)
 
 
-def factor_entries(n):
+def factor_entries(n, dtype):
     """Entries of the stored factor per sample: m diagonal blocks of the
     block-tridiagonal LDL^T, each the symmetric inverse Schur complement of
-    size n (padded), stored as its upper tr x tr tiles."""
+    size n (padded), stored as its lower tr x tr tiles (16 x 16 MFMA tiles
+    from n = 32 for the low-precision factors and from n = 64 for FP64)."""
     m = n - 1
-    tr = 16 if n >= 64 else (2 if n <= 16 else 4)
+    blk = n >= (64 if dtype == "f64" else 32)
+    tr = 16 if blk else (2 if n <= 16 else 4)
     tn = n // tr
     return m * tn * (tn + 1) // 2 * tr * tr
 
 
-def refine_bytes(n, trips, fbytes):
+def refine_bytes(n, trips, dtype):
     """Algorithmic HBM bytes per sample of the refinement kernel: the initial
     solve and `trips` corrections each read the factor twice (forward and
     backward block sweeps) and the row couplings and scaling; every residual
     (1 + trips) reads the nodal coefficient and the iterate; x is written."""
     m = n - 1
     N = m * n
-    per_solve = 2 * factor_entries(n) * fbytes + 3 * N * 8
+    per_solve = 2 * factor_entries(n, dtype) * DT_BYTES[dtype] + 3 * N * 8
     per_resid = (n + 1) ** 2 * 8 + N * 8
     return (1 + trips) * (per_solve + per_resid) + N * 8
 
@@ -207,7 +209,7 @@ def main():
                     traffic=None)
         per_unit = "%.4g flops per sample ((n-1)^4)" % factor_flops(n)
     else:
-        per = refine_bytes(n, trips.get(n, 1.0), DT_BYTES[a.dtype])
+        per = refine_bytes(n, trips.get(n, 1.0), a.dtype)
         work = per * per_launch
         achieved = work / (avg_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK["hbm"], unit="GB/s",

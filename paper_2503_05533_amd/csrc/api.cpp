@@ -247,10 +247,10 @@ grid_layout make_layout(int n, int64_t S, const mlmc_level_opts &o)
     L.off_lam = take(vb);
     const bool direct = o.solver != MLMC_MINRES;
     const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
-    L.off_factor = take(direct ? S * factor_entries_per_sample(n) * dtype_bytes(dt) : 0);
+    L.off_factor = take(direct ? S * factor_entries_per_sample(dt, n) * dtype_bytes(dt) : 0);
     // every sample can be re-solved with an FP64 factor without a host round trip
     L.promo_slots = (direct && dt != MLMC_F64 && o.promote) ? S : 0;
-    L.off_promo = take(L.promo_slots * factor_entries_per_sample(n) * 8);
+    L.off_promo = take(L.promo_slots * factor_entries_per_sample(MLMC_F64, n) * 8);
     L.off_mr = take(o.solver == MLMC_MINRES ? 7 * S * L.vec * 8 : 0);
     L.off_state = take(S * 4);
     L.off_relres = take(S * 8);
@@ -776,7 +776,7 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
         const grid_layout &L = g ? LL.coarse : LL.fine;
         void *w = at<void>(ws_dev, g ? LL.off_coarse : LL.off_fine);
         int best = 0;
-        if (nn >= 64) {
+        if (use_blk(dt, nn) && nn >= 64) {
             float best_ms = 1e30f;
             for (int var = 1; var <= 2; ++var) {
                 ctx->ir_variant[dt][ilog2(nn)] = var;

@@ -89,6 +89,42 @@ template <int K> __device__ inline double rowbcast(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Lane swaps across the four 16-lane rows of a wave (gfx950):
+// permlane32_swap(x, y) yields ([x0 x1 y0 y1], [x2 x3 y2 y3]) and
+// permlane16_swap(x, y) yields ([x0 y0 x2 y2], [x1 y1 x3 y3]) (rows of 16).
+// Sum over the four rows of the lanes with the same l % 16, ((r0 + r2) + (r1 + r3)),
+// returned in every lane.
+__device__ inline float rows4_total(float v)
+{
+    const unsigned u = __float_as_uint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const unsigned us = __float_as_uint(s);
+    const auto b = __builtin_amdgcn_permlane16_swap(us, us, false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+__device__ inline double swap32_lo_hi(double v, int which)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return __longlong_as_double(
+        (long long)(((unsigned long long)(which ? hi[1] : hi[0]) << 32) | (which ? lo[1] : lo[0])));
+}
+__device__ inline double swap16_lo_hi(double v, int which)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return __longlong_as_double(
+        (long long)(((unsigned long long)(which ? hi[1] : hi[0]) << 32) | (which ? lo[1] : lo[0])));
+}
+__device__ inline double rows4_total(double v)
+{
+    const double s = swap32_lo_hi(v, 0) + swap32_lo_hi(v, 1);
+    return swap16_lo_hi(s, 0) + swap16_lo_hi(s, 1);
+}
+
 template <typename T, int K>
 __device__ inline void sweep_step(T p[4], int i, int g, bool &ok)
 {
@@ -346,9 +382,15 @@ __device__ inline double row16_total(double v)
 }
 
 // x (+)= S Ahat^{-1} S rhs for one sample with the block-layout factor fs
-// (all threads of the workgroup call it); wave w handles the blocks of its
-// row pair, the next Schur block's factor entries are loaded while the
-// current one is applied.  rs == NULL means the constant rhs_const.
+// (all threads of the workgroup call it).  Wave w holds the blocks of its
+// row pair; per Schur block it forms its share of F g: row sums of its
+// blocks accumulate in registers and are reduced across each 16-lane row by
+// DPP, the transposed (column) contributions of off-diagonal blocks are
+// reduced across the four lane rows and stored once per block.  Every
+// partial has its own LDS slot, so the sum over waves (one thread per vector
+// entry) is in a fixed order.  Two barriers per Schur block; the next block's
+// factor entries are loaded while the current one is applied.  rs == NULL
+// means the constant rhs_const.
 template <typename Tst, int M, int G, bool PREF>
 __device__ inline void solve_blk_pass(const double *__restrict__ scs, const double *__restrict__ bs,
                                       const Tst *__restrict__ fs, const double *__restrict__ rs,
@@ -359,11 +401,19 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = G * NB / 2, SPW = (NB + G) / G;
     constexpr int m = M - 1, NT = 64 * W;
     static_assert(NT >= M, "one vector entry per thread");
-    __shared__ Tac g[M], xc[M];
-    __shared__ Tac part[W][M];  // per-wave partial products, summed in wave order (deterministic)
+    __shared__ Tac g[M];
+    __shared__ Tac partR[W][M];     // row sums of the wave's two block rows (other entries 0)
+    __shared__ Tac partC[W][2][M];  // column sums of the off-diagonal blocks of each row (others 0)
     const int t = threadIdx.x, l = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int pr = w / G;  // the wave's row pair (pr, NB-1-pr)
     const int lr = l >> 4, lc = l & 15;
+
+    for (int i = l; i < M; i += 64) {
+        partR[w][i] = 0;
+        partC[w][0][i] = 0;
+        partC[w][1][i] = 0;
+    }
 
     Tst cur[SPW][4], nxt[PREF ? SPW : 1][4];
     auto load = [&](int j, Tst (&dst)[SPW][4]) {
@@ -379,15 +429,11 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
             for (int r = 0; r < 4; ++r) dst[q][r] = fb[(bb * 4 + r) * 64 + l];
         }
     };
-    // part[w] = this wave's share of F g (symmetric block factor in `cur`):
-    // row and column contributions accumulate in part[w] slot by slot, each
-    // instruction's lanes touching distinct entries (fixed order).
+    // this wave's partials of F g for the block in `cur`
     auto apply = [&]() {
         int wq = w;
         asm volatile("" : "+s"(wq));
-        Tac *pw = part[wq];
-        for (int i = l; i < M; i += 64) pw[i] = 0;
-        wave_lds_sync();
+        Tac ra0[4] = {0, 0, 0, 0}, ra1[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < SPW; ++q) {
             int I, J;
@@ -396,27 +442,36 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
 #pragma unroll
             for (int r = 0; r < 4; ++r) f[r] = store_traits<Tst>::load(cur[q][r]);
             const Tac gj = g[16 * J + lc];
+            const bool first = (I == pr);  // wave-uniform: which of the two block rows
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const Tac v = row16_total(f[r] * gj);
-                if (lc == 15) pw[16 * I + drow<Tac>(lr, r)] += v;
+                if (first)
+                    ra0[r] = fma(f[r], gj, ra0[r]);
+                else
+                    ra1[r] = fma(f[r], gj, ra1[r]);
             }
             if (I != J) {
                 Tac c = 0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) c = fma(f[r], g[16 * I + drow<Tac>(lr, r)], c);
-                c += __shfl_xor(c, 16, 64);
-                c += __shfl_xor(c, 32, 64);
-                if (lr == 0) pw[16 * J + lc] += c;
+                c = rows4_total(c);
+                if (lr == 0) partC[wq][first ? 0 : 1][16 * J + lc] = c;
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
-
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const Tac v0 = row16_total(ra0[r]);
+            const Tac v1 = row16_total(ra1[r]);
+            if (lc == 15) {
+                partR[wq][16 * pr + drow<Tac>(lr, r)] = v0;
+                partR[wq][16 * (NB - 1 - pr) + drow<Tac>(lr, r)] = v1;
+            }
+        }
     };
     auto gather = [&](int i) {
         Tac v = 0;
 #pragma unroll
-        for (int ww = 0; ww < W; ++ww) v += part[ww][i];
+        for (int ww = 0; ww < W; ++ww) v += partR[ww][i] + partC[ww][0][i] + partC[ww][1][i];
         return v;
     };
     auto copy_next = [&]() {
@@ -428,16 +483,20 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
         }
     };
 
-    // Thread t < M owns vector entry t of every block (NT >= M); its inputs of
-    // the next block are loaded one block ahead.
+    // Thread t < M owns vector entry t of every block; its inputs of the next
+    // block are loaded one block ahead.
     const bool own = t < M;
     // forward: z_j = -F_j (s_j r_j - beta_j z_{j-1})
+    Tac xc = 0;
     double v_sc = 0.0, v_b = 0.0, v_r = 0.0;
     if (own) {
-        xc[t] = 0;
-        v_sc = scs[t];
-        v_b = bs[t];
-        v_r = rs ? rs[t] : (t < m ? rhs_const : 0.0);
+        const double r0 = rs ? rs[t] : (t < m ? rhs_const : 0.0);
+        g[t] = (Tac)(scs[t] * r0);
+        if (m > 1) {
+            v_sc = scs[M + t];
+            v_b = bs[M + t];
+            v_r = rs ? rs[M + t] : (t < m ? rhs_const : 0.0);
+        }
     }
     if (PREF) load(0, cur);
     __syncthreads();
@@ -447,66 +506,60 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
         } else {
             load(j, cur);
         }
-        if (own) {
-            g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc[t];
-            if (j + 1 < m) {
-                v_sc = scs[(j + 1) * M + t];
-                v_b = bs[(j + 1) * M + t];
-                v_r = rs ? rs[(j + 1) * M + t] : (t < m ? rhs_const : 0.0);
-            }
-        }
-        __syncthreads();
         apply();
         __syncthreads();
         if (own) {
-            const Tac z = -gather(t);
-            xc[t] = z;
-            zs[j * M + t] = (double)z;
+            xc = -gather(t);
+            zs[j * M + t] = (double)xc;
+            if (j + 1 < m) {
+                g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc;
+                if (j + 2 < m) {
+                    v_sc = scs[(j + 2) * M + t];
+                    v_b = bs[(j + 2) * M + t];
+                    v_r = rs ? rs[(j + 2) * M + t] : (t < m ? rhs_const : 0.0);
+                }
+            }
         }
-        __syncthreads();
         if (j + 1 < m) copy_next();
+        __syncthreads();
     }
     // back: x_{m-1} = z_{m-1}; x_j = z_j + F_j (beta_{j+1} x_{j+1})
     double v_z = 0.0, v_x = 0.0;
     if (own) {
-        const double d = scs[(m - 1) * M + t] * (double)xc[t];
+        const double d = scs[(m - 1) * M + t] * (double)xc;
         xs[(m - 1) * M + t] = accumulate ? xs[(m - 1) * M + t] + d : d;
         if (m >= 2) {
-            v_b = bs[(m - 1) * M + t];
+            g[t] = (Tac)bs[(m - 1) * M + t] * xc;
             v_z = zs[(m - 2) * M + t];
             v_sc = scs[(m - 2) * M + t];
             v_x = accumulate ? xs[(m - 2) * M + t] : 0.0;
+            v_b = (m >= 3) ? bs[(m - 2) * M + t] : 0.0;
         }
     }
     if (PREF && m >= 2) load(m - 2, cur);
+    __syncthreads();
     for (int j = m - 2; j >= 0; --j) {
         if constexpr (PREF) {
             if (j > 0) load(j - 1, nxt);
         } else {
             load(j, cur);
         }
-        const double c_sc = v_sc, c_x = v_x;
-        const Tac c_z = (Tac)v_z;
-        if (own) {
-            g[t] = (Tac)v_b * xc[t];
-            if (j > 0) {
-                v_b = bs[j * M + t];
-                v_z = zs[(j - 1) * M + t];
-                v_sc = scs[(j - 1) * M + t];
-                v_x = accumulate ? xs[(j - 1) * M + t] : 0.0;
-            }
-        }
-        __syncthreads();
         apply();
         __syncthreads();
         if (own) {
-            const Tac xv = c_z + gather(t);
-            xc[t] = xv;
-            const double d = c_sc * (double)xv;
-            xs[j * M + t] = accumulate ? c_x + d : d;
+            xc = (Tac)v_z + gather(t);
+            const double d = v_sc * (double)xc;
+            xs[j * M + t] = accumulate ? v_x + d : d;
+            if (j > 0) {
+                g[t] = (Tac)v_b * xc;
+                v_z = zs[(j - 1) * M + t];
+                v_sc = scs[(j - 1) * M + t];
+                v_x = accumulate ? xs[(j - 1) * M + t] : 0.0;
+                v_b = (j > 1) ? bs[(j - 1) * M + t] : 0.0;
+            }
         }
-        __syncthreads();
         if (j > 0) copy_next();
+        __syncthreads();
     }
 }
 
@@ -636,6 +689,7 @@ template <typename Tst>
 hipError_t li_m(const ir_args &g, hipStream_t st)
 {
     switch (g.n) {
+    case 32: return li<Tst, 32>(g, st);
     case 64: return li<Tst, 64>(g, st);
     case 128: return li<Tst, 128>(g, st);
     case 256: return li<Tst, 256>(g, st);
@@ -648,6 +702,7 @@ hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *fact
                 const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
 {
     switch (M) {
+    case 32: return lf<Tst, 32>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, count, slot_base, state, st);
@@ -661,6 +716,7 @@ hipError_t ls_m(int M, int nb, const double *sc, const double *beta, const void 
                 int64_t slot_base, const uint32_t *state, hipStream_t st)
 {
     switch (M) {
+    case 32: return ls<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 64: return ls<Tst, 64>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 128: return ls<Tst, 128>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 256: return ls<Tst, 256>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);

@@ -17,7 +17,13 @@ enum : uint32_t {
     ST_DONE = 1u << 31,  // no further refinement work for this sample
 };
 
-size_t factor_entries_per_sample(int n);
+// Whether grid n with factor dtype (mlmc_dtype code) uses the MFMA
+// block-layout factor and solves (else the register-tile kernels): from 32
+// cells per side for the low-precision factors, from 64 for FP64 (where the
+// tile kernels are faster at 32).
+inline bool use_blk(int dtype, int n) { return n >= (dtype == 0 ? 64 : 32); }
+
+size_t factor_entries_per_sample(int dtype, int n);
 
 // Arguments of the per-sample refinement kernel (one workgroup per sample b:
 // sample idx[b] (or b), factor slot slot_base + b; b >= *count exits).

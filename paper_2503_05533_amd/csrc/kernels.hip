@@ -747,10 +747,10 @@ hipError_t launch_solve_m(int M, int nb, const double *sc, const double *beta, c
 
 namespace mlmc {
 
-size_t factor_entries_per_sample(int n)
+size_t factor_entries_per_sample(int dtype, int n)
 {
     const int M = n;
-    if (M >= 64) {
+    if (use_blk(dtype, n)) {
         const int NB = M / 16;
         return (size_t)(n - 1) * (NB * (NB + 1) / 2) * 256;
     }
@@ -800,7 +800,7 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, cons
                          uint32_t *state, hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
-    if (n >= 64)
+    if (use_blk(dtype, n))
         return launch_factor_blk(dtype, n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     switch (dtype) {
     case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
@@ -814,7 +814,7 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, cons
 hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st)
 {
     if (g.nblocks == 0) return hipSuccess;
-    if (g.n >= 64) return launch_ir_blk(dtype, g, st);
+    if (use_blk(dtype, g.n)) return launch_ir_blk(dtype, g, st);
     switch (dtype) {
     case 0: return launch_ir_m<double>(g, st);
     case 1: return launch_ir_m<float>(g, st);
@@ -830,7 +830,7 @@ hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const d
                         const uint32_t *state, hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
-    if (n >= 64)
+    if (use_blk(dtype, n))
         return launch_solve_blk(dtype, n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate,
                                 zbuf, idx, slot_base, state, st);
     switch (dtype) {
