@@ -45,6 +45,11 @@ template <typename T> __device__ constexpr int drow(int lr, int r);
 template <> __device__ constexpr int drow<float>(int lr, int r) { return 4 * lr + r; }
 template <> __device__ constexpr int drow<double>(int lr, int r) { return 4 * r + lr; }
 
+// Waves per sample and block slots per wave for block size M with G waves
+// per row pair; a single block row (M = 16) is one wave with one block.
+template <int M, int G> constexpr int blk_waves() { return M >= 32 ? G * (M / 16) / 2 : 1; }
+template <int M, int G> constexpr int blk_slots() { return M >= 32 ? (M / 16 + G) / G : 1; }
+
 // Block ownership: the NB block rows are paired (p, NB-1-p), which together
 // hold NB+1 lower blocks; G waves share a pair, wave w = G p + h taking the
 // pair's blocks h, h+G, h+2G, ...  Returns false for an empty slot.
@@ -79,13 +84,13 @@ template <> __device__ inline double bcast<double>(double v, int lane)
 }
 template <int K> __device__ inline float rowbcast(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + K, 0xF, 0xF, false));
 }
 template <int K> __device__ inline double rowbcast(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x150 + K, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x150 + K, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -135,13 +140,17 @@ __device__ inline void sweep_step(T p[4], int i, int g, bool &ok)
     const T d = bcast(p[K & 3], 16 * (K >> 2) + K);                        // P[K][K]
     ok = ok && (d > (T)0) && isfinite(d);
     const T inv = recip(d), f = pik * inv;
+    const bool piv = (i == K);
+    // rows i != K: P[i][c] - f P[K][c]; row K (whose lanes hold p == rk):
+    // P[K][c] / d, written P[K][c] - (1 - 1/d) P[K][c] so one FMA serves both.
+    // The pivots of the scaled SPD blocks are at most 1, so 1 - 1/d <= 0 up to
+    // rounding and the form is accurate to rounding.
+    const T fe = piv ? (T)1 - inv : f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        T v = fma(-f, rk[c], p[c]);
-        v = (i == K) ? rk[c] * inv : v;
-        if (4 * g + c == K) v = (i == K) ? -inv : f;
-        p[c] = v;
-    }
+    for (int c = 0; c < 4; ++c) p[c] = fma(-fe, rk[c], p[c]);
+    // column K sits in register K & 3 of lane row K >> 2: f there, -1/d at (K, K)
+    constexpr int cK = K & 3;
+    p[cK] = (g == (K >> 2)) ? (piv ? -inv : f) : p[cK];
 }
 
 // -P^{-1} of a 16 x 16 SPD matrix by the sweep operator inside one wave.
@@ -181,7 +190,7 @@ __device__ inline void wave_lds_sync()
 }
 
 template <typename Tst, int M>
-__global__ __launch_bounds__(32 * M / 16) void k_factor_mfma(int S, const double *__restrict__ beta,
+__global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S, const double *__restrict__ beta,
                                                              const double *__restrict__ gam,
                                                              Tst *__restrict__ factor,
                                                              const int *__restrict__ idx,
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(32 * M / 16) void k_factor_mfma(int S, const double
 {
     using Tac = typename store_traits<Tst>::acc;
     using V4 = typename vec4_of<Tac>::type;
-    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = NB / 2, SPW = NB + 1;
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = blk_waves<M, 1>(), SPW = blk_slots<M, 1>();
     constexpr int m = M - 1, LD = 17, NT = 64 * W;
     __shared__ Tac Vb[2][M * LD];      // panel columns C[:, K], double-buffered
     __shared__ Tac Pw[W][16 * LD];     // per wave: -P^{-1}
@@ -251,82 +260,93 @@ __global__ __launch_bounds__(32 * M / 16) void k_factor_mfma(int S, const double
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        for (int K = 0; K < NB; ++K) {
-            int wk = w;
-            asm volatile("" : "+s"(wk));
-            Tac *V = Vb[K & 1];
-            // publish the panel columns C[:, K]
+        if constexpr (NB == 1 && drow<Tac>(1, 0) == 4) {
+            // a single 16 x 16 block in FP32: its result layout (register r of lane
+            // row lr holds C[4 lr + r][lc]) is, by symmetry, the sweep layout
+            Tac p[4];
 #pragma unroll
-            for (int q = 0; q < SPW; ++q) {
-                int I, J;
-                slot_blk<NB, 1>(wk, q, I, J);
-                if (J == K) {
+            for (int r = 0; r < 4; ++r) p[r] = acc[0][r];
+            okw = sweep16(p, l) && okw;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) V[(16 * I + drow<Tac>(lr, r)) * LD + lc] = acc[q][r];
-                } else if (I == K) {
+            for (int r = 0; r < 4; ++r) acc[0][r] = p[r];
+        } else {
+            for (int K = 0; K < NB; ++K) {
+                int wk = w;
+                asm volatile("" : "+s"(wk));
+                Tac *V = Vb[K & 1];
+                // publish the panel columns C[:, K]
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) V[(16 * J + lc) * LD + drow<Tac>(lr, r)] = acc[q][r];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            __syncthreads();
-            asm volatile("" : "+s"(wk));
-            // every wave: -P^{-1} (redundantly), then U for its two block rows
-            Tac *P = Pw[wk];
-            {
-                Tac p[4];  // lane 16 g + i: P[i][4g .. 4g+3]
+                for (int q = 0; q < SPW; ++q) {
+                    int I, J;
+                    slot_blk<NB, 1>(wk, q, I, J);
+                    if (J == K) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) p[c] = V[(16 * K + lc) * LD + 4 * lr + c];
-                okw = sweep16(p, l) && okw;
+                        for (int r = 0; r < 4; ++r) V[(16 * I + drow<Tac>(lr, r)) * LD + lc] = acc[q][r];
+                    } else if (I == K) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) P[lc * LD + 4 * lr + c] = p[c];
-            }
-            wave_lds_sync();
-            // -P^{-1}[4kc+lr][lc] (= [lc][4kc+lr] by symmetry) is the B operand of U and
-            // the A operand of row K; U rows are re-read in the A layout per block below
-            // (operands are re-read from LDS rather than held, to bound registers).
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                const int row = x ? NB - 1 - wk : wk;
-                V4 u = V4{0, 0, 0, 0};
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc)
-                    u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Uw[wk][x][drow<Tac>(lr, r) * LD + lc] = u[r];
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int q = 0; q < SPW; ++q) {
-                int I, J;
-                slot_blk<NB, 1>(wk, q, I, J);
-                const Tac *U = Uw[wk][(q <= wk) ? 0 : 1];  // which of the wave's two rows
-                if (I != K && J != K) {
-                    // C[I,J] += U_I V_J^T
-                    Tac av[4], bv[4];
-#pragma unroll
-                    for (int kc = 0; kc < 4; ++kc) {
-                        av[kc] = U[lc * LD + 4 * kc + lr];
-                        bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
+                        for (int r = 0; r < 4; ++r) V[(16 * J + lc) * LD + drow<Tac>(lr, r)] = acc[q][r];
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+                asm volatile("" : "+s"(wk));
+                // every wave: -P^{-1} (redundantly), then U for its two block rows
+                Tac *P = Pw[wk];
+                {
+                    Tac p[4];  // lane 16 g + i: P[i][4g .. 4g+3]
 #pragma unroll
-                    for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
-                } else if (I == K && J == K) {
+                    for (int c = 0; c < 4; ++c) p[c] = V[(16 * K + lc) * LD + 4 * lr + c];
+                    okw = sweep16(p, l) && okw;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[q][r] = P[drow<Tac>(lr, r) * LD + lc];
-                } else if (J == K) {
-                    // C[I,K] = V_I P^{-1} = -U_I
+                    for (int c = 0; c < 4; ++c) P[lc * LD + 4 * lr + c] = p[c];
+                }
+                wave_lds_sync();
+                // -P^{-1}[4kc+lr][lc] (= [lc][4kc+lr] by symmetry) is the B operand of U and
+                // the A operand of row K; U rows are re-read in the A layout per block below
+                // (operands are re-read from LDS rather than held, to bound registers).
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[q][r] = -U[drow<Tac>(lr, r) * LD + lc];
-                } else {
-                    // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
-                    V4 z = V4{0, 0, 0, 0};
+                for (int x = 0; x < 2; ++x) {
+                    const int row = x ? NB - 1 - wk : wk;
+                    V4 u = V4{0, 0, 0, 0};
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc)
-                        z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
-                    acc[q] = -z;
+                        u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Uw[wk][x][drow<Tac>(lr, r) * LD + lc] = u[r];
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                wave_lds_sync();
+#pragma unroll
+                for (int q = 0; q < SPW; ++q) {
+                    int I, J;
+                    slot_blk<NB, 1>(wk, q, I, J);
+                    const Tac *U = Uw[wk][(q <= wk) ? 0 : 1];  // which of the wave's two rows
+                    if (I != K && J != K) {
+                        // C[I,J] += U_I V_J^T
+                        Tac av[4], bv[4];
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) {
+                            av[kc] = U[lc * LD + 4 * kc + lr];
+                            bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
+                        }
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
+                    } else if (I == K && J == K) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[q][r] = P[drow<Tac>(lr, r) * LD + lc];
+                    } else if (J == K) {
+                        // C[I,K] = V_I P^{-1} = -U_I
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[q][r] = -U[drow<Tac>(lr, r) * LD + lc];
+                    } else {
+                        // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
+                        V4 z = V4{0, 0, 0, 0};
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc)
+                            z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
+                        acc[q] = -z;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
         // store -C_j^{-1}
@@ -398,7 +418,7 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
                                       double *__restrict__ zs)
 {
     using Tac = typename store_traits<Tst>::acc;
-    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = G * NB / 2, SPW = (NB + G) / G;
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = blk_waves<M, G>(), SPW = blk_slots<M, G>();
     constexpr int m = M - 1, NT = 64 * W;
     static_assert(NT >= M, "one vector entry per thread");
     __shared__ Tac g[M];
@@ -464,7 +484,7 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
             const Tac v1 = row16_total(ra1[r]);
             if (lc == 15) {
                 partR[wq][16 * pr + drow<Tac>(lr, r)] = v0;
-                partR[wq][16 * (NB - 1 - pr) + drow<Tac>(lr, r)] = v1;
+                if (NB > 1) partR[wq][16 * (NB - 1 - pr) + drow<Tac>(lr, r)] = v1;
             }
         }
     };
@@ -564,7 +584,7 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
 }
 
 template <typename Tst, int M, int G, bool PREF>
-__global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__restrict__ sc,
+__global__ __launch_bounds__((64 * blk_waves<M, G>())) void k_solve_blk(const double *__restrict__ sc,
                                                       const double *__restrict__ beta,
                                                       const Tst *__restrict__ factor,
                                                       const double *__restrict__ rhs,
@@ -588,7 +608,7 @@ __global__ __launch_bounds__(32 * G * M / 16) void k_solve_blk(const double *__r
 // With `direct` the first residual only yields Q and the relative residual.
 // Workgroups b >= *count (when count is given) exit at once.
 template <typename Tst, int M, int G, bool PREF>
-__global__ __launch_bounds__(32 * G * M / 16) void k_ir_blk(
+__global__ __launch_bounds__((64 * blk_waves<M, G>())) void k_ir_blk(
     int n, double fconst, const double *__restrict__ a, const double *__restrict__ sc,
     const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
     double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
@@ -596,7 +616,7 @@ __global__ __launch_bounds__(32 * G * M / 16) void k_ir_blk(
     uint32_t *__restrict__ state, double *__restrict__ relres, double *__restrict__ q,
     int32_t *__restrict__ iters)
 {
-    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1, NT = 32 * G * M / 16;
+    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1, NT = 64 * blk_waves<M, G>();
     __shared__ double red[NT];
     const int b = blockIdx.x;
     if (count && b >= *count) return;
@@ -646,7 +666,7 @@ template <typename Tst, int M>
 hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const int *idx,
               const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(32 * M / 16), 0, st, nb, beta, gam,
+    hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
                        (Tst *)factor, idx, count, slot_base, state);
     return hipGetLastError();
 }
@@ -658,7 +678,7 @@ hipError_t ls(int nb, const double *sc, const double *beta, const void *factor, 
 {
     constexpr int G = solve_cfg<Tst, M>::G;
     constexpr bool PREF = solve_cfg<Tst, M>::PREF;
-    hipLaunchKernelGGL((k_solve_blk<Tst, M, G, PREF>), dim3(nb), dim3(32 * G * M / 16), 0, st, sc, beta,
+    hipLaunchKernelGGL((k_solve_blk<Tst, M, G, PREF>), dim3(nb), dim3(64 * blk_waves<M, G>()), 0, st, sc, beta,
                        (const Tst *)factor, rhs, rc, x, acc, zbuf, idx, slot_base, state);
     return hipGetLastError();
 }
@@ -672,7 +692,7 @@ template <typename Tst, int M, int G>
 hipError_t li_g(const ir_args &g, hipStream_t st)
 {
     constexpr bool PREF = ir_pref<Tst, M, G>::v;
-    hipLaunchKernelGGL((k_ir_blk<Tst, M, G, PREF>), dim3(g.nblocks), dim3(32 * G * M / 16), 0, st, g.n,
+    hipLaunchKernelGGL((k_ir_blk<Tst, M, G, PREF>), dim3(g.nblocks), dim3(64 * blk_waves<M, G>()), 0, st, g.n,
                        g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps,
                        g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters);
     return hipGetLastError();
@@ -681,14 +701,19 @@ hipError_t li_g(const ir_args &g, hipStream_t st)
 template <typename Tst, int M>
 hipError_t li(const ir_args &g, hipStream_t st)
 {
-    int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
-    return G == 2 ? li_g<Tst, M, 2>(g, st) : li_g<Tst, M, 1>(g, st);
+    if constexpr (M == 16) {
+        return li_g<Tst, M, 1>(g, st);
+    } else {
+        int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
+        return G == 2 ? li_g<Tst, M, 2>(g, st) : li_g<Tst, M, 1>(g, st);
+    }
 }
 
 template <typename Tst>
 hipError_t li_m(const ir_args &g, hipStream_t st)
 {
     switch (g.n) {
+    case 16: return li<Tst, 16>(g, st);
     case 32: return li<Tst, 32>(g, st);
     case 64: return li<Tst, 64>(g, st);
     case 128: return li<Tst, 128>(g, st);
@@ -702,6 +727,7 @@ hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *fact
                 const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
 {
     switch (M) {
+    case 16: return lf<Tst, 16>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     case 32: return lf<Tst, 32>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, count, slot_base, state, st);
     case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, count, slot_base, state, st);
@@ -716,6 +742,7 @@ hipError_t ls_m(int M, int nb, const double *sc, const double *beta, const void 
                 int64_t slot_base, const uint32_t *state, hipStream_t st)
 {
     switch (M) {
+    case 16: return ls<Tst, 16>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 32: return ls<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 64: return ls<Tst, 64>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
     case 128: return ls<Tst, 128>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);

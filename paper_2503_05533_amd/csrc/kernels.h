@@ -18,10 +18,13 @@ enum : uint32_t {
 };
 
 // Whether grid n with factor dtype (mlmc_dtype code) uses the MFMA
-// block-layout factor and solves (else the register-tile kernels): from 32
-// cells per side for the low-precision factors, from 64 for FP64 (where the
-// tile kernels are faster at 32).
-inline bool use_blk(int dtype, int n) { return n >= (dtype == 0 ? 64 : 32); }
+// block-layout factor and solves (else the register-tile kernels): every grid
+// for the low-precision factors, from 64 cells per side for FP64 (where the
+// tile kernels are faster below).
+#ifndef MLMC_BLK_LOWP_MIN
+#define MLMC_BLK_LOWP_MIN 16
+#endif
+inline bool use_blk(int dtype, int n) { return n >= (dtype == 0 ? 64 : MLMC_BLK_LOWP_MIN); }
 
 size_t factor_entries_per_sample(int dtype, int n);
 
