@@ -13,7 +13,8 @@
 //
 // Stored factor: per Schur block j, NBL = NB(NB+1)/2 lower blocks b (row by
 // row), each in the MFMA result layout: entry (row drow(l/16, r), col l%16) of
-// block b at offset (b*4 + r)*64 + l.
+// block b at offset (b*64 + l)*4 + r, so that a lane's four entries of a block
+// are one contiguous vector access.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,6 +26,9 @@ namespace mlmc {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+// Four consecutive stored entries, accessed as one vector load or store.
+template <typename T> struct alignas(4 * sizeof(T)) quad { T v[4]; };
+
 template <typename T> struct vec4_of;
 template <> struct vec4_of<float> { using type = f32x4; };
 template <> struct vec4_of<double> { using type = f64x4; };
@@ -357,8 +361,10 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
             int I, J;
             slot_blk<NB, 1>(wj, q, I, J);
             const int bb = I * (I + 1) / 2 + J;
+            quad<Tst> qv;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) fb[(bb * 4 + r) * 64 + l] = store_traits<Tst>::store(acc[q][r]);
+            for (int r = 0; r < 4; ++r) qv.v[r] = store_traits<Tst>::store(acc[q][r]);
+            *(quad<Tst> *)(fb + ((size_t)bb * 64 + l) * 4) = qv;
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -412,7 +418,7 @@ __device__ inline double row16_total(double v)
 // factor entries are loaded while the current one is applied.  rs == NULL
 // means the constant rhs_const.
 template <typename Tst, int M, int G, bool PREF>
-__device__ inline void solve_blk_pass(const double *__restrict__ scs, const double *__restrict__ bs,
+__device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, const double *__restrict__ bs,
                                       const Tst *__restrict__ fs, const double *__restrict__ rs,
                                       double rhs_const, double *__restrict__ xs, int accumulate,
                                       double *__restrict__ zs)
@@ -443,10 +449,14 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
 #pragma unroll
         for (int q = 0; q < SPW; ++q) {
             int I, J;
-            if (!slot_blk<NB, G>(wq, q, I, J)) continue;
+            const bool valid = slot_blk<NB, G>(wq, q, I, J);
+            if constexpr (G > 1) {
+                if (!valid) continue;
+            }
             const int bb = I * (I + 1) / 2 + J;
+            const quad<Tst> qv = *(const quad<Tst> *)(fb + ((size_t)bb * 64 + l) * 4);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[q][r] = fb[(bb * 4 + r) * 64 + l];
+            for (int r = 0; r < 4; ++r) dst[q][r] = qv.v[r];
         }
     };
     // this wave's partials of F g for the block in `cur`
@@ -457,7 +467,10 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
 #pragma unroll
         for (int q = 0; q < SPW; ++q) {
             int I, J;
-            if (!slot_blk<NB, G>(wq, q, I, J)) continue;
+            const bool valid = slot_blk<NB, G>(wq, q, I, J);
+            if constexpr (G > 1) {
+                if (!valid) continue;
+            }
             Tac f[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) f[r] = store_traits<Tst>::load(cur[q][r]);
@@ -520,9 +533,13 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
     }
     if (PREF) load(0, cur);
     __syncthreads();
+    // The loop bodies are kept free of data-dependent branches (prefetch
+    // indices are clamped, a redundant load of the last block is harmless) so
+    // that waits for a block's factor entries do not also wait for the
+    // prefetch of the next one.
     for (int j = 0; j < m; ++j) {
         if constexpr (PREF) {
-            if (j + 1 < m) load(j + 1, nxt);
+            load(j + 1 < m ? j + 1 : j, nxt);
         } else {
             load(j, cur);
         }
@@ -531,16 +548,13 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
         if (own) {
             xc = -gather(t);
             zs[j * M + t] = (double)xc;
-            if (j + 1 < m) {
-                g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc;
-                if (j + 2 < m) {
-                    v_sc = scs[(j + 2) * M + t];
-                    v_b = bs[(j + 2) * M + t];
-                    v_r = rs ? rs[(j + 2) * M + t] : (t < m ? rhs_const : 0.0);
-                }
-            }
+            g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc;
+            const int jn = j + 2 < m ? j + 2 : m - 1;
+            v_sc = scs[jn * M + t];
+            v_b = bs[jn * M + t];
+            v_r = rs ? rs[jn * M + t] : (t < m ? rhs_const : 0.0);
         }
-        if (j + 1 < m) copy_next();
+        copy_next();
         __syncthreads();
     }
     // back: x_{m-1} = z_{m-1}; x_j = z_j + F_j (beta_{j+1} x_{j+1})
@@ -560,7 +574,7 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
     __syncthreads();
     for (int j = m - 2; j >= 0; --j) {
         if constexpr (PREF) {
-            if (j > 0) load(j - 1, nxt);
+            load(j > 0 ? j - 1 : 0, nxt);
         } else {
             load(j, cur);
         }
@@ -570,15 +584,14 @@ __device__ inline void solve_blk_pass(const double *__restrict__ scs, const doub
             xc = (Tac)v_z + gather(t);
             const double d = v_sc * (double)xc;
             xs[j * M + t] = accumulate ? v_x + d : d;
-            if (j > 0) {
-                g[t] = (Tac)v_b * xc;
-                v_z = zs[(j - 1) * M + t];
-                v_sc = scs[(j - 1) * M + t];
-                v_x = accumulate ? xs[(j - 1) * M + t] : 0.0;
-                v_b = (j > 1) ? bs[(j - 1) * M + t] : 0.0;
-            }
+            g[t] = (Tac)v_b * xc;
+            const int jp = j > 0 ? j - 1 : 0;
+            v_z = zs[jp * M + t];
+            v_sc = scs[jp * M + t];
+            v_x = accumulate ? xs[jp * M + t] : 0.0;
+            v_b = bs[jp * M + t];
         }
-        if (j > 0) copy_next();
+        copy_next();
         __syncthreads();
     }
 }
