@@ -40,9 +40,11 @@ DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 # HBM bytes per sample measured with FETCH_SIZE / WRITE_SIZE counters (scaled
 # by a copy kernel of known size) for the mixed FP32 step; valid only while the
 # kernel sources hash to TRAFFIC_SRC (otherwise the field is reported as null).
-TRAFFIC_SRC = "de22f28d22c1166a"
-TRAFFIC = {("factor", 128, "f32"): 4.9426e6, ("factor", 64, "f32"): 0.7100e6,
-           ("solve", 128, "f32"): 21.9472e6, ("solve", 64, "f32"): 3.2643e6}
+TRAFFIC_SRC = "33d2678da78dabf1"
+TRAFFIC = {("factor", 128, "f32"): 4.9425e6, ("factor", 64, "f32"): 0.7098e6,
+           ("factor", 32, "f32"): 0.1111e6, ("factor", 16, "f32"): 0.0192e6,
+           ("solve", 128, "f32"): 21.9785e6, ("solve", 64, "f32"): 3.2659e6,
+           ("solve", 32, "f32"): 0.2622e6, ("solve", 16, "f32"): 0.0453e6}
 
 
 def kernel_src_hash():
