@@ -665,6 +665,66 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) void k_ir_blk(
 }
 
 
+// ------------------------------------------------------------------ KL field
+
+// Z = xi Phi^T on all (n+1)^2 nodes and a = exp(Z), FP64 on v_mfma 16x16x4.
+// A workgroup computes 64 samples x 64 nodes, wave w the 32 x 32 quarter
+// (w / 2, w % 2) as 2 x 2 result tiles.  The contraction over the K modes
+// runs in chunks of 16; in slice kk of a chunk the lane row lr stands for
+// mode c0 + 4 lr + kk, so each lane reads four consecutive entries of a xi
+// row and four rows of Phi^T (coalesced over the 16 nodes of a lane row).
+// Modes beyond K contribute zero; rows and nodes beyond S and P are not
+// stored (their loads are clamped in bounds).
+__global__ __launch_bounds__(256) void k_field_mfma(int S, int K, int P, const double *__restrict__ xi,
+                                                    const double *__restrict__ phit,
+                                                    double *__restrict__ a)
+{
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, lr = l >> 4, lc = l & 15;
+    const int s0 = blockIdx.y * 64 + 32 * (w >> 1), p0 = blockIdx.x * 64 + 32 * (w & 1);
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = f64x4{0, 0, 0, 0};
+    int rowc[2], colc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        rowc[q] = min(s0 + 16 * q + lc, S - 1);
+        colc[q] = min(p0 + 16 * q + lc, P - 1);
+    }
+    for (int c0 = 0; c0 < K; c0 += 16) {
+        double av[2][4], bv[2][4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = c0 + 4 * lr + kk;
+            const bool in = k < K;
+            const int kc = in ? k : K - 1;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double x = xi[(size_t)rowc[q] * K + kc];
+                const double ph = phit[(size_t)kc * P + colc[q]];
+                av[q][kk] = in ? x : 0.0;
+                bv[q][kk] = in ? ph : 0.0;
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mfma4(av[ti][kk], bv[tj][kk], acc[ti][tj]);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = s0 + 16 * ti + drow<double>(lr, r), col = p0 + 16 * tj + lc;
+                if (row < S && col < P) a[(size_t)row * P + col] = exp(acc[ti][tj][r]);
+            }
+}
+
 // ------------------------------------------------------------------ launchers
 
 namespace {
@@ -764,6 +824,15 @@ hipError_t ls_m(int M, int nb, const double *sc, const double *beta, const void 
     return hipErrorInvalidValue;
 }
 }  // namespace
+
+hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double *phit, double *a,
+                             hipStream_t st)
+{
+    if (S == 0) return hipSuccess;
+    const dim3 grid((unsigned)((P + 63) / 64), (unsigned)((S + 63) / 64));
+    hipLaunchKernelGGL(k_field_mfma, grid, dim3(256), 0, st, S, K, P, xi, phit, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
                              void *factor, const int *idx, const int *count, int64_t slot_base,

@@ -50,6 +50,9 @@ hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, in
                           hipStream_t st);
 hipError_t launch_field(int S, int K, int P, const double *xi, const double *phit, double *a,
                         hipStream_t st);
+// Z = xi Phi^T, a = exp(Z) on FP64 MFMA (xi [S x K], phit [K x P], a [S x P]).
+hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double *phit, double *a,
+                             hipStream_t st);
 hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double *phit,
                             const double *gq, double *grad, hipStream_t st);
 hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,

@@ -153,33 +153,47 @@ __global__ __launch_bounds__(256) void k_gemm64(int R, int Cn, int L, const doub
 
 // Scaled block coefficients from the nodal coefficient a[(n+1)^2]:
 // sc = diag(A)^(-1/2), gam (to the right neighbour), beta (to the row below).
-__global__ void k_coeffs(int n, int S, const double *__restrict__ a, double *__restrict__ sc,
-                         double *__restrict__ gam, double *__restrict__ beta)
+// Diagonal scaling S = diag(A)^(-1/2) of the 5-point operator, one thread per
+// padded unknown (x = sample, y = block of unknowns): A_PP is the sum of the
+// four harmonic-mean edge coefficients around node P.
+__global__ void k_scale(int n, const double *__restrict__ a, double *__restrict__ sc)
 {
     const int m = n - 1, M = n, np = n + 1;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)S * m * M) return;
-    const int s = (int)(g / (m * M));
-    const int e = (int)(g % (m * M));
+    const int s = blockIdx.x, e = blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= m * M) return;
     const int j = e / M, i = e % M;
     const size_t o = (size_t)s * m * M + e;
     if (i >= m) {
         sc[o] = 0.0;
+        return;
+    }
+    const double *as = a + (size_t)s * np * np;
+    const int p = (j + 1) * np + (i + 1);
+    const double c = as[p];
+    const double d = hmean(c, as[p - 1]) + hmean(c, as[p + 1]) + hmean(c, as[p - np]) + hmean(c, as[p + np]);
+    sc[o] = 1.0 / sqrt(d);
+}
+
+// Scaled couplings of S A S: gam to the right neighbour (same grid row), beta
+// to the neighbour in the row below; 0 at the grid edge and in the pad.
+__global__ void k_coeffs(int n, const double *__restrict__ a, const double *__restrict__ sc,
+                         double *__restrict__ gam, double *__restrict__ beta)
+{
+    const int m = n - 1, M = n, np = n + 1;
+    const int s = blockIdx.x, e = blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= m * M) return;
+    const int j = e / M, i = e % M;
+    const size_t o = (size_t)s * m * M + e;
+    if (i >= m) {
         gam[o] = 0.0;
         beta[o] = 0.0;
         return;
     }
     const double *as = a + (size_t)s * np * np;
-    auto diag = [&](int ix, int iy) {
-        const int p = iy * np + ix;
-        const double c = as[p];
-        return hmean(c, as[p - 1]) + hmean(c, as[p + 1]) + hmean(c, as[p - np]) + hmean(c, as[p + np]);
-    };
-    const int ix = i + 1, iy = j + 1, p = iy * np + ix;
-    const double sP = 1.0 / sqrt(diag(ix, iy));
-    sc[o] = sP;
-    gam[o] = (i + 1 < m) ? -hmean(as[p], as[p + 1]) * sP / sqrt(diag(ix + 1, iy)) : 0.0;
-    beta[o] = (j > 0) ? -hmean(as[p], as[p - np]) * sP / sqrt(diag(ix, iy - 1)) : 0.0;
+    const int p = (j + 1) * np + (i + 1);
+    const double sP = sc[o];
+    gam[o] = (i + 1 < m) ? -hmean(as[p], as[p + 1]) * sP * sc[o + 1] : 0.0;
+    beta[o] = (j > 0) ? -hmean(as[p], as[p - np]) * sP * sc[o - M] : 0.0;
 }
 
 // ------------------------------------------------------------------ factor
@@ -625,7 +639,7 @@ __global__ __launch_bounds__(1024) void k_pair_sums(int S, const double *__restr
                                                     uint8_t *__restrict__ status,
                                                     double *__restrict__ sums)
 {
-    __shared__ double red[1024];
+    __shared__ double part[16][8];
     double sy = 0, sy2 = 0, sf = 0, scc = 0, npro = 0, nnc = 0, sit = 0, sitc = 0;
     for (int s = threadIdx.x; s < S; s += 1024) {
         const double f = qf[s], c = qc ? qc[s] : 0.0;
@@ -642,10 +656,24 @@ __global__ __launch_bounds__(1024) void k_pair_sums(int S, const double *__restr
         sit += itf ? (double)itf[s] : 0.0;
         sitc += itc ? (double)itc[s] : 0.0;
     }
+    // fixed-order reductions: a butterfly inside each wave, then the 16 wave
+    // partials in wave order (deterministic)
     double v[8] = {sy, sy2, sf, scc, npro, nnc, sit, sitc};
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
     for (int q = 0; q < 8; ++q) {
-        double r = block_sum<1024>(v[q], red);
-        if (threadIdx.x == 0) sums[q] = r;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) part[wv][q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double r = 0.0;
+        for (int w = 0; w < 16; ++w) r += part[w][threadIdx.x];
+        sums[threadIdx.x] = r;
     }
 }
 
@@ -772,10 +800,7 @@ hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, in
 hipError_t launch_field(int S, int K, int P, const double *xi, const double *phit, double *a,
                         hipStream_t st)
 {
-    dim3 grid((P + 63) / 64, (S + 63) / 64);
-    hipLaunchKernelGGL((k_gemm64<false, 0>), grid, dim3(256), 0, st, S, P, K, xi, K, phit, P, a, P,
-                       (const double *)nullptr);
-    return hipGetLastError();
+    return launch_field_mfma(S, K, P, xi, phit, a, st);
 }
 
 hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double *phit,
@@ -790,8 +815,10 @@ hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double 
 hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
                          hipStream_t st)
 {
-    const int64_t e = (int64_t)S * (n - 1) * n;
-    hipLaunchKernelGGL(k_coeffs, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, n, S, a, sc, gam, beta);
+    if (S == 0) return hipSuccess;
+    const dim3 grid((unsigned)S, (unsigned)(((n - 1) * n + 255) / 256));
+    hipLaunchKernelGGL(k_scale, grid, dim3(256), 0, st, n, a, sc);
+    hipLaunchKernelGGL(k_coeffs, grid, dim3(256), 0, st, n, a, sc, gam, beta);
     return hipGetLastError();
 }
 
