@@ -731,6 +731,8 @@ namespace {
 // Solve configuration: waves per row pair (G) and register double-buffering
 // of the next Schur block (PREF), within the register budget.
 template <typename Tst, int M> struct solve_cfg { static constexpr int G = 1; static constexpr bool PREF = true; };
+template <typename Tst> struct solve_cfg<Tst, 128> { static constexpr int G = 2; static constexpr bool PREF = true; };
+template <typename Tst> struct solve_cfg<Tst, 256> { static constexpr int G = 2; static constexpr bool PREF = true; };
 template <> struct solve_cfg<double, 64> { static constexpr int G = 2; static constexpr bool PREF = true; };
 template <> struct solve_cfg<double, 128> { static constexpr int G = 2; static constexpr bool PREF = true; };
 template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static constexpr bool PREF = false; };
