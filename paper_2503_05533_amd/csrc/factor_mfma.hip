@@ -1,5 +1,6 @@
 // Blocked symmetric-sweep factorisation on MFMA and the matching block solve
-// (grids with n >= 64 cells per side, M = n padded block size).
+// (M = n, the padded block size: every grid for the FP32/BF16/FP16 factors,
+// n >= 64 for the FP64 factor).
 //
 // Each Schur complement C_j (M x M, SPD) is inverted in place by the sweep
 // operator applied to 16-pivot panels: with V = C[:, K] (the panel columns,
@@ -441,7 +442,10 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
         partC[w][1][i] = 0;
     }
 
-    Tst cur[SPW][4], nxt[PREF ? SPW : 1][4];
+    // Blocks in flight while one is applied (PREF): two, or one where three
+    // rotating buffers would not fit the registers of a 1024-thread workgroup.
+    constexpr int DEPTH = !PREF ? 0 : (M >= 256 ? 1 : 2);
+    Tst bA[SPW][4], bB[SPW][4], bC[SPW][4];
     auto load = [&](int j, Tst (&dst)[SPW][4]) {
         int wq = w;
         asm volatile("" : "+s"(wq));
@@ -459,8 +463,8 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
             for (int r = 0; r < 4; ++r) dst[q][r] = qv.v[r];
         }
     };
-    // this wave's partials of F g for the block in `cur`
-    auto apply = [&]() {
+    // this wave's partials of F g for the block held in `cur`
+    auto apply = [&](const Tst (&cur)[SPW][4]) {
         int wq = w;
         asm volatile("" : "+s"(wq));
         Tac ra0[4] = {0, 0, 0, 0}, ra1[4] = {0, 0, 0, 0};
@@ -507,14 +511,6 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
         for (int ww = 0; ww < W; ++ww) v += partR[ww][i] + partC[ww][0][i] + partC[ww][1][i];
         return v;
     };
-    auto copy_next = [&]() {
-        if constexpr (PREF) {
-#pragma unroll
-            for (int q = 0; q < SPW; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) cur[q][r] = nxt[q][r];
-        }
-    };
 
     // Thread t < M owns vector entry t of every block; its inputs of the next
     // block are loaded one block ahead.
@@ -531,19 +527,17 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
             v_r = rs ? rs[M + t] : (t < m ? rhs_const : 0.0);
         }
     }
-    if (PREF) load(0, cur);
-    __syncthreads();
-    // The loop bodies are kept free of data-dependent branches (prefetch
-    // indices are clamped, a redundant load of the last block is harmless) so
-    // that waits for a block's factor entries do not also wait for the
-    // prefetch of the next one.
-    for (int j = 0; j < m; ++j) {
+    // One block of the forward pass: apply block j (in `use`) while block
+    // j + DEPTH (clamped; a redundant load of the last block is harmless)
+    // streams into `fill`.
+    auto fwd = [&](int j, const Tst (&use)[SPW][4], Tst (&fill)[SPW][4]) {
         if constexpr (PREF) {
-            load(j + 1 < m ? j + 1 : j, nxt);
+            load(j + DEPTH < m ? j + DEPTH : m - 1, fill);
+            apply(use);
         } else {
-            load(j, cur);
+            load(j, bA);
+            apply(bA);
         }
-        apply();
         __syncthreads();
         if (own) {
             xc = -gather(t);
@@ -554,8 +548,34 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
             v_b = bs[jn * M + t];
             v_r = rs ? rs[jn * M + t] : (t < m ? rhs_const : 0.0);
         }
-        copy_next();
         __syncthreads();
+    };
+    if constexpr (DEPTH >= 1) load(0, bA);
+    if constexpr (DEPTH == 2) load(m > 1 ? 1 : 0, bB);
+    __syncthreads();
+    // The loop bodies are kept free of data-dependent branches so that waits
+    // for a block's factor entries do not also wait for the blocks behind it;
+    // the buffers rotate by unrolling, never by register copies (a copy would
+    // wait for the load in flight).
+    {
+        int j = 0;
+        if constexpr (DEPTH == 2) {
+            for (; j + 3 <= m; j += 3) {
+                fwd(j, bA, bC);
+                fwd(j + 1, bB, bA);
+                fwd(j + 2, bC, bB);
+            }
+            if (j < m) fwd(j++, bA, bC);
+            if (j < m) fwd(j++, bB, bA);
+        } else if constexpr (DEPTH == 1) {
+            for (; j + 2 <= m; j += 2) {
+                fwd(j, bA, bB);
+                fwd(j + 1, bB, bA);
+            }
+            if (j < m) fwd(j++, bA, bB);
+        } else {
+            for (; j < m; ++j) fwd(j, bA, bA);
+        }
     }
     // back: x_{m-1} = z_{m-1}; x_j = z_j + F_j (beta_{j+1} x_{j+1})
     double v_z = 0.0, v_x = 0.0;
@@ -570,15 +590,16 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
             v_b = (m >= 3) ? bs[(m - 2) * M + t] : 0.0;
         }
     }
-    if (PREF && m >= 2) load(m - 2, cur);
-    __syncthreads();
-    for (int j = m - 2; j >= 0; --j) {
+    // One block of the back pass: apply block j while block j - DEPTH (clamped
+    // at 0) streams in.
+    auto back = [&](int j, const Tst (&use)[SPW][4], Tst (&fill)[SPW][4]) {
         if constexpr (PREF) {
-            load(j > 0 ? j - 1 : 0, nxt);
+            load(j >= DEPTH ? j - DEPTH : 0, fill);
+            apply(use);
         } else {
-            load(j, cur);
+            load(j, bA);
+            apply(bA);
         }
-        apply();
         __syncthreads();
         if (own) {
             xc = (Tac)v_z + gather(t);
@@ -591,8 +612,34 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
             v_x = accumulate ? xs[jp * M + t] : 0.0;
             v_b = bs[jp * M + t];
         }
-        copy_next();
         __syncthreads();
+    };
+    if constexpr (DEPTH >= 1) {
+        if (m >= 2) load(m - 2, bA);
+    }
+    if constexpr (DEPTH == 2) {
+        if (m >= 3) load(m - 3, bB);
+    }
+    __syncthreads();
+    {
+        int j = m - 2;
+        if constexpr (DEPTH == 2) {
+            for (; j - 2 >= 0; j -= 3) {
+                back(j, bA, bC);
+                back(j - 1, bB, bA);
+                back(j - 2, bC, bB);
+            }
+            if (j >= 0) back(j--, bA, bC);
+            if (j >= 0) back(j--, bB, bA);
+        } else if constexpr (DEPTH == 1) {
+            for (; j - 1 >= 0; j -= 2) {
+                back(j, bA, bB);
+                back(j - 1, bB, bA);
+            }
+            if (j >= 0) back(j--, bA, bB);
+        } else {
+            for (; j >= 0; --j) back(j, bA, bA);
+        }
     }
 }
 
@@ -620,8 +667,14 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) void k_solve_blk(const do
 // x0 = S Ahat^{-1} S b, then {r = b - A x (FP64); stop test; x += solve(r)}.
 // With `direct` the first residual only yields Q and the relative residual.
 // Workgroups b >= *count (when count is given) exit at once.
+// Two workgroups of the n = 128 low-precision refinement share a CU (>= 4
+// waves per SIMD), so that a batch of up to 512 samples runs in one round.
+template <typename Tst, int M, int G> constexpr int ir_min_waves()
+{
+    return (M == 128 && G == 2 && sizeof(Tst) <= 4) ? 4 : 1;
+}
 template <typename Tst, int M, int G, bool PREF>
-__global__ __launch_bounds__((64 * blk_waves<M, G>())) void k_ir_blk(
+__global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_waves_per_eu(ir_min_waves<Tst, M, G>()))) void k_ir_blk(
     int n, double fconst, const double *__restrict__ a, const double *__restrict__ sc,
     const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
     double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
