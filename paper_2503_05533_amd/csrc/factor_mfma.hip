@@ -135,24 +135,42 @@ __device__ inline double rows4_total(double v)
     return swap16_lo_hi(s, 0) + swap16_lo_hi(s, 1);
 }
 
+// p[c] += P[K][4g+c] * me for c = 0..3, with P[K][4g+c] the value of p[c] in
+// lane K of the 16-lane row: the row broadcast is the DPP operand of the
+// FMA.  One wait pair covers a VALU write of p just before; within the block
+// no instruction reads a register written by the one before it.
+template <int K> __device__ inline void fmac4_rowbcast(float p[4], float me)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f32_dpp %0, %0, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %1, %1, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %2, %2, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %3, %3, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf"
+                 : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]), "+v"(p[3])
+                 : "v"(me), "i"(K));
+}
+template <int K> __device__ inline void fmac4_rowbcast(double p[4], double me)
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) p[c] = fma(rowbcast<K>(p[c]), me, p[c]);
+}
+
 template <typename T, int K>
 __device__ inline void sweep_step(T p[4], int i, int g, bool &ok)
 {
-    T rk[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) rk[c] = rowbcast<K>(p[c]);               // P[K][4g+c]
     const T pik = __shfl(p[K & 3], 16 * (K >> 2) + i, 64);                 // P[i][K]
     const T d = bcast(p[K & 3], 16 * (K >> 2) + K);                        // P[K][K]
     ok = ok && (d > (T)0) && isfinite(d);
     const T inv = recip(d), f = pik * inv;
     const bool piv = (i == K);
     // rows i != K: P[i][c] - f P[K][c]; row K (whose lanes hold p == rk):
-    // P[K][c] / d, written P[K][c] - (1 - 1/d) P[K][c] so one FMA serves both.
-    // The pivots of the scaled SPD blocks are at most 1, so 1 - 1/d <= 0 up to
-    // rounding and the form is accurate to rounding.
-    const T fe = piv ? (T)1 - inv : f;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) p[c] = fma(-fe, rk[c], p[c]);
+    // P[K][c] / d, written P[K][c] + (1/d - 1) P[K][c] so one FMA serves both.
+    // The pivots of the scaled SPD blocks are at most 1, so 1/d - 1 >= 0 up to
+    // rounding and the form is accurate to rounding.  The multiplier is
+    // formed with its sign so that the row broadcast folds into the FMA as
+    // its DPP operand.
+    const T me = piv ? inv - (T)1 : -f;
+    fmac4_rowbcast<K>(p, me);  // p[c] += P[K][4g+c] me
     // column K sits in register K & 3 of lane row K >> 2: f there, -1/d at (K, K)
     constexpr int cK = K & 3;
     p[cK] = (g == (K >> 2)) ? (piv ? -inv : f) : p[cK];
