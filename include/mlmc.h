@@ -174,9 +174,13 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
  * xi_dev[i] ([n[i] x K]) under opts[i].  Every level's fine and coarse grids
  * run concurrently on streams forked from `stream` and joined back to it,
  * so uneven work (many small coarse samples, few large fine ones) shares the
- * GPU.  With use_graph != 0 the whole fork/join is captured once into a HIP
- * graph and replayed while the arguments (pointers, sizes, options) stay the
- * same.  The workspace is mlmc_levels_workspace_bytes() bytes; y_dev (may be
+ * GPU.  With use_graph == 0 the grids are spread over four streams of the
+ * context, one per hardware queue of the process: the most expensive grid
+ * alone on the first, the others longest first onto the least loaded.  With
+ * use_graph != 0 every level gets two streams (fine, coarse), and the whole
+ * fork/join is captured once into a HIP graph and replayed while the
+ * arguments (pointers, sizes, options) stay the same.  Both give the same
+ * results.  The workspace is mlmc_levels_workspace_bytes() bytes; y_dev (may be
  * NULL, or an array of n_levels device pointers, entries may be NULL) gets
  * Y_l; stats_host (may be NULL, else n_levels entries) makes the call
  * synchronise and report the level sums (gpu_ms: the whole call). */

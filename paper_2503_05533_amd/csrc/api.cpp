@@ -38,6 +38,9 @@ struct mlmc_ctx {
     std::vector<hipStream_t> lstreams;
     std::vector<hipEvent_t> levents;
     hipStream_t cap_stream = nullptr;
+    // eager multi-level launches: one stream per hardware queue, events
+    std::vector<hipStream_t> qstreams;
+    std::vector<hipEvent_t> qevents;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uintptr_t> graph_key;
@@ -431,6 +434,112 @@ int level_enqueue(mlmc_ctx *ctx, int level, int64_t n, const double *xi, const m
     return MLMC_OK;
 }
 
+
+// Eager multi-level schedule.  The device runs a process's work on a few
+// hardware queues (four by default) and every stream is bound to one of
+// them, so two independent chains on streams that share a queue run one
+// after the other.  The grids of all levels (fine and coarse) are therefore
+// spread over exactly kQueues streams created back to back: the most
+// expensive grid (the fine grid of the finest level, a latency-bound chain
+// of factor and refinement) alone on the first, the others longest first
+// onto the least loaded of the rest.  A level's pairing and sums are
+// enqueued after all grids (so that no grid waits behind them), on the
+// stream of its fine grid, after an event of its coarse grid.  Cost model:
+// samples x n^3.5 (between the n^3 of the solves and the n^4 of the
+// factorisation).
+constexpr int kQueues = 4;
+
+int enqueue_levels_queued(mlmc_ctx *ctx, int n_levels, const int32_t *levels, const int64_t *n,
+                          const double *const *xi_dev, const mlmc_level_opts *opts, void *ws_dev,
+                          const std::vector<level_layout> &LL, const std::vector<size_t> &off,
+                          double *const *y_dev, hipStream_t os)
+{
+    while (ctx->qstreams.size() < (size_t)kQueues) {
+        hipStream_t s2;
+        HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        ctx->qstreams.push_back(s2);
+    }
+    const size_t nev = 1 + 2 * (size_t)n_levels + kQueues;
+    while (ctx->qevents.size() < nev) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->qevents.push_back(e);
+    }
+    struct job { int li, coarse; double cost; };
+    std::vector<job> jobs;
+    for (int i = 0; i < n_levels; ++i) {
+        if (n[i] == 0) continue;
+        for (int c = 0; c < (levels[i] > 0 ? 2 : 1); ++c) {
+            const double nn = (double)(ctx->cfg.n0 << (levels[i] - c));
+            jobs.push_back({i, c, (double)n[i] * std::pow(nn, 3.5)});
+        }
+    }
+    std::stable_sort(jobs.begin(), jobs.end(), [](const job &a, const job &b) { return a.cost > b.cost; });
+    std::vector<int> qof(jobs.size());
+    double load[kQueues] = {};
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        int q = 0;
+        if (k > 0) {
+            q = 1;
+            for (int t = 2; t < kQueues; ++t)
+                if (load[t] < load[q]) q = t;
+        }
+        qof[k] = q;
+        load[q] += jobs[k].cost;
+    }
+    hipEvent_t fork = ctx->qevents[0];
+    HIPCHK(hipEventRecord(fork, os));
+    bool used[kQueues] = {};
+    for (size_t k = 0; k < jobs.size(); ++k) used[qof[k]] = true;
+    for (int q = 0; q < kQueues; ++q)
+        if (used[q]) HIPCHK(hipStreamWaitEvent(ctx->qstreams[q], fork, 0));
+    std::vector<int> fine_q(n_levels, 0), coarse_q(n_levels, 0);
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        const job &J = jobs[k];
+        const int i = J.li;
+        hipStream_t sq = ctx->qstreams[qof[k]];
+        void *w = (char *)ws_dev + off[i];
+        const level_layout &L = LL[i];
+        const mlmc_level_opts &o = opts[i];
+        const grid_layout &G = J.coarse ? L.coarse : L.fine;
+        void *wg = at<void>(w, J.coarse ? L.off_coarse : L.off_fine);
+        int rc = solve_grid(ctx, G, levels[i] - J.coarse, xi_dev[i], o, J.coarse ? o.eps_coarse : o.eps_fine, wg,
+                            at<double>(w, J.coarse ? L.off_qc : L.off_qf), at<int32_t>(wg, G.off_iters), sq);
+        if (rc) return rc;
+        if (J.coarse) {
+            coarse_q[i] = qof[k];
+            HIPCHK(hipEventRecord(ctx->qevents[1 + 2 * i], sq));
+        } else {
+            fine_q[i] = qof[k];
+        }
+    }
+    for (int i = 0; i < n_levels; ++i) {
+        if (n[i] == 0) continue;
+        hipStream_t sq = ctx->qstreams[fine_q[i]];
+        void *w = (char *)ws_dev + off[i];
+        const level_layout &L = LL[i];
+        void *wf = at<void>(w, L.off_fine);
+        const uint32_t *stc = nullptr;
+        const int32_t *itc = nullptr;
+        if (levels[i] > 0) {
+            if (coarse_q[i] != fine_q[i]) HIPCHK(hipStreamWaitEvent(sq, ctx->qevents[1 + 2 * i], 0));
+            void *wc = at<void>(w, L.off_coarse);
+            stc = at<uint32_t>(wc, L.coarse.off_state);
+            itc = at<int32_t>(wc, L.coarse.off_iters);
+        }
+        HIPCHK(launch_pair_sums((int)n[i], at<double>(w, L.off_qf), levels[i] > 0 ? at<double>(w, L.off_qc) : nullptr,
+                                at<uint32_t>(wf, L.fine.off_state), stc, at<int32_t>(wf, L.fine.off_iters), itc,
+                                y_dev ? y_dev[i] : nullptr, nullptr, at<double>(w, L.off_sums), sq));
+    }
+    for (int q = 0; q < kQueues; ++q) {
+        if (!used[q]) continue;
+        hipEvent_t e = ctx->qevents[1 + 2 * (size_t)n_levels + q];
+        HIPCHK(hipEventRecord(e, ctx->qstreams[q]));
+        HIPCHK(hipStreamWaitEvent(os, e, 0));
+    }
+    return MLMC_OK;
+}
+
 void fill_stats(mlmc_level_stats *out, int64_t n, const double *h, double ms)
 {
     memset(out, 0, sizeof *out);
@@ -510,6 +619,8 @@ int mlmc_destroy(mlmc_ctx *ctx)
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->levents) (void)hipEventDestroy(e);
     for (hipStream_t s2 : ctx->lstreams) (void)hipStreamDestroy(s2);
+    for (hipEvent_t e : ctx->qevents) (void)hipEventDestroy(e);
+    for (hipStream_t s2 : ctx->qstreams) (void)hipStreamDestroy(s2);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -735,7 +846,7 @@ int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, c
         }
         HIPCHK(hipGraphLaunch(ctx->graph_exec, st));
     } else {
-        int rc = enqueue_all(st);
+        int rc = enqueue_levels_queued(ctx, n_levels, levels, n, xi_dev, opts, ws_dev, LL, off, y_dev, st);
         if (rc) return rc;
     }
     if (stats_host) {

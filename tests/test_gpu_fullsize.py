@@ -79,9 +79,11 @@ def _check_y(y, idx, w, level, eps_f, eps_c, fp64=False):
     return float(np.max(err / (np.abs(qf) + np.abs(qc))))
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
 @pytest.mark.parametrize("dtype,solver", [("f32", "direct_ir"), ("f64", "direct")])
-def test_bench_step_fullsize(dtype, solver):
-    """mlmc4_n16-128_K64 at N_l = 20000/5000/1250/300, one replayed graph (the bench step)."""
+def test_bench_step_fullsize(dtype, solver, use_graph):
+    """mlmc4_n16-128_K64 at N_l = 20000/5000/1250/300: the eager one-stream-per-queue
+    schedule (the bench step) and the replayed graph."""
     torch = _torch()
     from paper_2503_05533_amd import MLMC, Config
     w = si.workload("mlmc4_n16-128_K64")
@@ -92,7 +94,7 @@ def test_bench_step_fullsize(dtype, solver):
     xis = [ctx.fill_xi(l, 0, N) for l, N in zip(levels, Ns)]
     opts = [dict(dtype=dtype, solver=solver, eps_fine=eps[l], eps_coarse=eps[l - 1] if l else 0.0)
             for l in levels]
-    plan = ctx.plan_levels(levels, xis, opts, use_graph=True)
+    plan = ctx.plan_levels(levels, xis, opts, use_graph=use_graph)
     plan.run()
     out = plan.run(stats=True)
     torch.cuda.synchronize()
@@ -104,7 +106,33 @@ def test_bench_step_fullsize(dtype, solver):
         assert st["sum_y"] == pytest.approx(float(y.sum()), rel=1e-9, abs=1e-15)
         idx = _picks(Ns[i], 10, 100 + l)
         worst = _check_y(y, idx, w, l, eps[l], eps[l - 1] if l else 0.0, fp64=(dtype == "f64"))
-        _say("bench step %s level %d: %d sampled rows, max rel err %.2e" % (dtype, l, len(idx), worst))
+        _say("bench step %s graph=%d level %d: %d sampled rows, max rel err %.2e"
+             % (dtype, use_graph, l, len(idx), worst))
+    ctx.close()
+
+
+def test_step_schedules_identical():
+    """The eager and the graph schedule run the same kernels on different streams:
+    Y and the level sums agree bit for bit (mixed path, full bench workload)."""
+    torch = _torch()
+    from paper_2503_05533_amd import MLMC, Config
+    w = si.workload("mlmc4_n16-128_K64")
+    levels, Ns, K = w["levels"], w["N"], w["K"]
+    ctx = MLMC(Config(n0=w["n0"], L_max=3, K=K, sigma2=w["sigma2"], corr_len=w["corr_len"],
+                      seed=w["seed"], ir_max_iter=10), device="cuda:0")
+    eps = ctx.accuracy_targets(3)
+    xis = [ctx.fill_xi(l, 0, N) for l, N in zip(levels, Ns)]
+    opts = [dict(dtype="f32", solver="direct_ir", eps_fine=eps[l], eps_coarse=eps[l - 1] if l else 0.0)
+            for l in levels]
+    res = []
+    for g in (False, True, False):
+        out = ctx.plan_levels(levels, xis, opts, use_graph=g).run(stats=True)
+        torch.cuda.synchronize()
+        res.append(([y.cpu().numpy().copy() for y in out["y"]], [st["sum_y"] for st in out["stats"]]))
+    for ys, sums in res[1:]:
+        for i in range(len(levels)):
+            assert np.array_equal(ys[i], res[0][0][i]), i
+            assert sums[i] == res[0][1][i], i
     ctx.close()
 
 
