@@ -42,11 +42,11 @@ DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 # HBM bytes per sample measured with FETCH_SIZE / WRITE_SIZE counters (scaled
 # by a copy kernel of known size) for the mixed FP32 step; valid only while the
 # kernel sources hash to TRAFFIC_SRC (otherwise the field is reported as null).
-TRAFFIC_SRC = "33d2678da78dabf1"
+TRAFFIC_SRC = "3db911e05894f5b1"
 TRAFFIC = {("factor", 128, "f32"): 4.9425e6, ("factor", 64, "f32"): 0.7098e6,
            ("factor", 32, "f32"): 0.1111e6, ("factor", 16, "f32"): 0.0192e6,
-           ("solve", 128, "f32"): 21.9785e6, ("solve", 64, "f32"): 3.2659e6,
-           ("solve", 32, "f32"): 0.2622e6, ("solve", 16, "f32"): 0.0453e6}
+           ("solve", 128, "f32"): 22.0890e6, ("solve", 64, "f32"): 3.2712e6,
+           ("solve", 32, "f32"): 0.2655e6, ("solve", 16, "f32"): 0.0455e6}
 
 
 def kernel_src_hash():
