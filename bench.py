@@ -227,6 +227,24 @@ def main():
         roof["traffic_unit"] = "bytes per launch (HBM, counters)"
     roof.update(kernel="%s n=%d" % (kind, n), avg_launch_ms=avg_ms, launches=r["launches"],
                 samples_per_launch=per_launch, per_unit=per_unit)
+    # The same kernel with its level running alone (in the step it shares the
+    # CUs with the other levels' kernels): context for frac, not the figure.
+    if n in cells:
+        i_dom = cells.index(n)
+        p1 = ctx.plan_levels([levels[i_dom]], [xis[i_dom]], [om[i_dom]], use_graph=False)
+        p1.run()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(3):
+            p1.run()
+        torch.cuda.synchronize()
+        r1 = ctx.profile_read(kind, n)
+        ctx.profile(False)
+        del p1
+        if r1["launches"]:
+            alone_ms = r1["ms"] / r1["launches"]
+            roof["alone_avg_launch_ms"] = alone_ms
+            roof["alone_frac"] = roof["frac"] * avg_ms / alone_ms
     log("dominant kernel", roof)
 
     # ---- per-level throughput (each level alone)
