@@ -319,7 +319,7 @@ int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o)
 // device-side compaction of the samples that did not converge and a second
 // pass with an FP64 factor for them.  Asynchronous on `st`.
 int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, double fconst,
-           double eps, double *x, double *q, int32_t *iters, hipStream_t st)
+           double eps, double *x, double *q, int32_t *iters, hipStream_t st, bool fwd_done = false)
 {
     const int n = L.n, S = (int)L.S;
     uint32_t *state = at<uint32_t>(ws, L.off_state);
@@ -343,6 +343,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
     g.q = q;
     g.iters = iters;
     g.variant = ctx->ir_variant[dt][ilog2(n)];
+    g.fwd_done = fwd_done ? 1 : 0;
     PROF(3, n, S, launch_ir(dt, g, st));
     if (L.promo_slots > 0 && dt != MLMC_F64) {
         int *idx = at<int>(ws, L.off_idx);
@@ -353,7 +354,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         HIPCHK(launch_collect(S, state, idx, cnt, st));
         HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
         PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
-                                     pf, idx, cnt, 0, state, st));
+                                     pf, idx, cnt, 0, state, nullptr, 0.0, nullptr, st));
         ir_args p = g;
         p.nblocks = np;
         p.factor = pf;
@@ -362,6 +363,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         p.imax = ctx->cfg.ir_max_iter;
         p.direct = 0;
         p.variant = ctx->ir_variant[MLMC_F64][ilog2(n)];
+        p.fwd_done = 0;
         PROF(7, n, np, launch_ir(MLMC_F64, p, st));
     }
     return MLMC_OK;
@@ -396,8 +398,12 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     const bool direct = o.solver == MLMC_DIRECT;
     const int dt = direct ? MLMC_F64 : o.factor_dtype;
     void *factor = at<void>(ws, L.off_factor);
-    PROF(2, n, S, launch_factor(dt, n, S, beta, gam, factor, nullptr, nullptr, 0, state, st));
-    return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, at<double>(ws, L.off_x), q, iters, st);
+    // the factorisation also runs the initial solve's forward sweep (rhs h^2 f)
+    const bool fwd = factor_fuses_forward(dt, n);
+    const double h = 1.0 / n;
+    PROF(2, n, S, launch_factor(dt, n, S, beta, gam, factor, nullptr, nullptr, 0, state, fwd ? sc : nullptr,
+                                h * h * ctx->cfg.f, fwd ? at<double>(ws, L.off_z) : nullptr, st));
+    return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, at<double>(ws, L.off_x), q, iters, st, fwd);
 }
 
 

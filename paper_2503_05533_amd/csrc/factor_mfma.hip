@@ -204,6 +204,38 @@ __device__ inline bool sweep16(T p[4], int l)
     return ok;
 }
 
+// Inclusive scan over the 16 lanes of a DPP row: lane 15 of each row ends
+// with the row total.
+template <int CTRL>
+__device__ inline float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float row16_total(float v)
+{
+    v += dpp_f32<0x111>(v);
+    v += dpp_f32<0x112>(v);
+    v += dpp_f32<0x114>(v);
+    v += dpp_f32<0x118>(v);
+    return v;
+}
+__device__ inline double row16_total(double v)
+{
+    v += dpp_f64<0x111>(v);
+    v += dpp_f64<0x112>(v);
+    v += dpp_f64<0x114>(v);
+    v += dpp_f64<0x118>(v);
+    return v;
+}
+
 // Wave-scope ordering of LDS accesses between lanes of one wave.
 __device__ inline void wave_lds_sync()
 {
@@ -212,6 +244,14 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Whether the factorisation also runs the forward sweep of the initial solve
+// (z_j = -F_j (s_j rhs - beta_j z_{j-1}) with each F_j as it is formed), so
+// that the solve starts with the back sweep: the FP32/BF16/FP16 factors.  In
+// FP64 the partial sums would add 12-50 KB of LDS to a workgroup that already
+// holds 36-130 KB, crowding out the kernels of the other levels that share
+// its CU in the multi-level step (measured: slower and erratic steps).
+template <typename Tac, int M> constexpr bool factor_fwd_ok() { return sizeof(Tac) == 4; }
+
 template <typename Tst, int M>
 __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S, const double *__restrict__ beta,
                                                              const double *__restrict__ gam,
@@ -219,16 +259,24 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                                                              const int *__restrict__ idx,
                                                              const int *__restrict__ count,
                                                              int64_t slot_base,
-                                                             uint32_t *__restrict__ state)
+                                                             uint32_t *__restrict__ state,
+                                                             const double *__restrict__ fsc, double frhs,
+                                                             double *__restrict__ fz)
 {
     using Tac = typename store_traits<Tst>::acc;
     using V4 = typename vec4_of<Tac>::type;
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = blk_waves<M, 1>(), SPW = blk_slots<M, 1>();
     constexpr int m = M - 1, LD = 17, NT = 64 * W;
+    constexpr bool FWD = factor_fwd_ok<Tac, M>();
     __shared__ Tac Vb[2][M * LD];      // panel columns C[:, K], double-buffered
     __shared__ Tac Pw[W][16 * LD];     // per wave: -P^{-1}
     __shared__ Tac Uw[W][2][16 * LD];  // per wave: U of its two block rows
     __shared__ Tac bj[2][M], gj[2][M];
+    // forward sweep (fz != NULL): right-hand side of the block, and per wave
+    // its row sums and column partials, each in its own slot (fixed-order sum)
+    __shared__ Tac gfw[FWD ? M : 1];
+    __shared__ Tac partR[FWD ? W : 1][FWD ? M : 1];
+    __shared__ Tac partC[FWD ? W : 1][2][FWD ? M : 1];
     __shared__ int bad;
     const int b = blockIdx.x;
     if (count && b >= *count) return;
@@ -241,6 +289,17 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
     const double *gs = gam + (size_t)s * m * M;
     Tst *fs = factor + (size_t)slot * m * NBL * 256;
     if (t == 0) bad = 0;
+    const bool fwd = FWD && fz != nullptr;
+    const double *fscs = fwd ? fsc + (size_t)s * m * M : nullptr;
+    double *fzs = fwd ? fz + (size_t)s * m * M : nullptr;
+    if constexpr (FWD) {
+        for (int i = l; i < M; i += 64) {
+            partR[w][i] = 0;
+            partC[w][0][i] = 0;
+            partC[w][1][i] = 0;
+        }
+    }
+    Tac zc = 0;  // z_{j-1}, entry t (t < M)
     V4 acc[SPW];
 #pragma unroll
     for (int q = 0; q < SPW; ++q) acc[q] = V4{0, 0, 0, 0};
@@ -386,6 +445,62 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
             *(quad<Tst> *)(fb + ((size_t)bb * 64 + l) * 4) = qv;
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (FWD) {
+            if (fwd) {
+                // z_j = -F_j g_j with F_j as stored (rounded to Tst), the same
+                // sums as the solve's forward sweep: row sums of the wave's tiles
+                // reduced across 16-lane rows, transposed contributions of the
+                // off-diagonal tiles across the four lane rows
+                if (t < M) {
+                    const Tac gv = (Tac)(fscs[j * M + t] * (t < m ? frhs : 0.0));
+                    gfw[t] = j > 0 ? gv - (Tac)bs[j * M + t] * zc : gv;
+                }
+                __syncthreads();
+                asm volatile("" : "+s"(wj));
+                Tac ra0[4] = {0, 0, 0, 0}, ra1[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < SPW; ++q) {
+                    int I, J;
+                    slot_blk<NB, 1>(wj, q, I, J);
+                    Tac f[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) f[r] = store_traits<Tst>::load(store_traits<Tst>::store(acc[q][r]));
+                    const Tac gjv = gfw[16 * J + lc];
+                    const bool first = (I == wj);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (first)
+                            ra0[r] = fma(f[r], gjv, ra0[r]);
+                        else
+                            ra1[r] = fma(f[r], gjv, ra1[r]);
+                    }
+                    if (I != J) {
+                        Tac c = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) c = fma(f[r], gfw[16 * I + drow<Tac>(lr, r)], c);
+                        c = rows4_total(c);
+                        if (lr == 0) partC[wj][first ? 0 : 1][16 * J + lc] = c;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const Tac v0 = row16_total(ra0[r]);
+                    const Tac v1 = row16_total(ra1[r]);
+                    if (lc == 15) {
+                        partR[wj][16 * wj + drow<Tac>(lr, r)] = v0;
+                        if (NB > 1) partR[wj][16 * (NB - 1 - wj) + drow<Tac>(lr, r)] = v1;
+                    }
+                }
+                __syncthreads();
+                if (t < M) {
+                    Tac v = 0;
+#pragma unroll
+                    for (int ww = 0; ww < W; ++ww) v += partR[ww][t] + partC[ww][0][t] + partC[ww][1][t];
+                    zc = -v;
+                    fzs[j * M + t] = (double)zc;
+                }
+            }
+        }
     }
     if (!okw) bad = 1;
     __syncthreads();
@@ -393,38 +508,6 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
 }
 
 // ------------------------------------------------------------------ block solve
-
-// Inclusive scan over the 16 lanes of a DPP row: lane 15 of each row ends
-// with the row total.
-template <int CTRL>
-__device__ inline float dpp_f32(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ inline double dpp_f64(double v)
-{
-    const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ inline float row16_total(float v)
-{
-    v += dpp_f32<0x111>(v);
-    v += dpp_f32<0x112>(v);
-    v += dpp_f32<0x114>(v);
-    v += dpp_f32<0x118>(v);
-    return v;
-}
-__device__ inline double row16_total(double v)
-{
-    v += dpp_f64<0x111>(v);
-    v += dpp_f64<0x112>(v);
-    v += dpp_f64<0x114>(v);
-    v += dpp_f64<0x118>(v);
-    return v;
-}
 
 // x (+)= S Ahat^{-1} S rhs for one sample with the block-layout factor fs
 // (all threads of the workgroup call it).  Wave w holds the blocks of its
@@ -440,7 +523,7 @@ template <typename Tst, int M, int G, bool PREF>
 __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, const double *__restrict__ bs,
                                       const Tst *__restrict__ fs, const double *__restrict__ rs,
                                       double rhs_const, double *__restrict__ xs, int accumulate,
-                                      double *__restrict__ zs)
+                                      double *__restrict__ zs, bool fwd_done = false)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = blk_waves<M, G>(), SPW = blk_slots<M, G>();
@@ -536,63 +619,68 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
     // forward: z_j = -F_j (s_j r_j - beta_j z_{j-1})
     Tac xc = 0;
     double v_sc = 0.0, v_b = 0.0, v_r = 0.0;
-    if (own) {
-        const double r0 = rs ? rs[t] : (t < m ? rhs_const : 0.0);
-        g[t] = (Tac)(scs[t] * r0);
-        if (m > 1) {
-            v_sc = scs[M + t];
-            v_b = bs[M + t];
-            v_r = rs ? rs[M + t] : (t < m ? rhs_const : 0.0);
-        }
-    }
-    // One block of the forward pass: apply block j (in `use`) while block
-    // j + DEPTH (clamped; a redundant load of the last block is harmless)
-    // streams into `fill`.
-    auto fwd = [&](int j, const Tst (&use)[SPW][4], Tst (&fill)[SPW][4]) {
-        if constexpr (PREF) {
-            load(j + DEPTH < m ? j + DEPTH : m - 1, fill);
-            apply(use);
-        } else {
-            load(j, bA);
-            apply(bA);
-        }
-        __syncthreads();
+    if (fwd_done) {
+        // the factorisation ran the forward sweep for this right-hand side
+        if (own) xc = (Tac)zs[(m - 1) * M + t];
+    } else {
         if (own) {
-            xc = -gather(t);
-            zs[j * M + t] = (double)xc;
-            g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc;
-            const int jn = j + 2 < m ? j + 2 : m - 1;
-            v_sc = scs[jn * M + t];
-            v_b = bs[jn * M + t];
-            v_r = rs ? rs[jn * M + t] : (t < m ? rhs_const : 0.0);
+            const double r0 = rs ? rs[t] : (t < m ? rhs_const : 0.0);
+            g[t] = (Tac)(scs[t] * r0);
+            if (m > 1) {
+                v_sc = scs[M + t];
+                v_b = bs[M + t];
+                v_r = rs ? rs[M + t] : (t < m ? rhs_const : 0.0);
+            }
         }
+        // One block of the forward pass: apply block j (in `use`) while block
+        // j + DEPTH (clamped; a redundant load of the last block is harmless)
+        // streams into `fill`.
+        auto fwd = [&](int j, const Tst (&use)[SPW][4], Tst (&fill)[SPW][4]) {
+            if constexpr (PREF) {
+                load(j + DEPTH < m ? j + DEPTH : m - 1, fill);
+                apply(use);
+            } else {
+                load(j, bA);
+                apply(bA);
+            }
+            __syncthreads();
+            if (own) {
+                xc = -gather(t);
+                zs[j * M + t] = (double)xc;
+                g[t] = (Tac)(v_sc * v_r) - (Tac)v_b * xc;
+                const int jn = j + 2 < m ? j + 2 : m - 1;
+                v_sc = scs[jn * M + t];
+                v_b = bs[jn * M + t];
+                v_r = rs ? rs[jn * M + t] : (t < m ? rhs_const : 0.0);
+            }
+            __syncthreads();
+        };
+        if constexpr (DEPTH >= 1) load(0, bA);
+        if constexpr (DEPTH == 2) load(m > 1 ? 1 : 0, bB);
         __syncthreads();
-    };
-    if constexpr (DEPTH >= 1) load(0, bA);
-    if constexpr (DEPTH == 2) load(m > 1 ? 1 : 0, bB);
-    __syncthreads();
-    // The loop bodies are kept free of data-dependent branches so that waits
-    // for a block's factor entries do not also wait for the blocks behind it;
-    // the buffers rotate by unrolling, never by register copies (a copy would
-    // wait for the load in flight).
-    {
-        int j = 0;
-        if constexpr (DEPTH == 2) {
-            for (; j + 3 <= m; j += 3) {
-                fwd(j, bA, bC);
-                fwd(j + 1, bB, bA);
-                fwd(j + 2, bC, bB);
+        // The loop bodies are kept free of data-dependent branches so that waits
+        // for a block's factor entries do not also wait for the blocks behind it;
+        // the buffers rotate by unrolling, never by register copies (a copy would
+        // wait for the load in flight).
+        {
+            int j = 0;
+            if constexpr (DEPTH == 2) {
+                for (; j + 3 <= m; j += 3) {
+                    fwd(j, bA, bC);
+                    fwd(j + 1, bB, bA);
+                    fwd(j + 2, bC, bB);
+                }
+                if (j < m) fwd(j++, bA, bC);
+                if (j < m) fwd(j++, bB, bA);
+            } else if constexpr (DEPTH == 1) {
+                for (; j + 2 <= m; j += 2) {
+                    fwd(j, bA, bB);
+                    fwd(j + 1, bB, bA);
+                }
+                if (j < m) fwd(j++, bA, bB);
+            } else {
+                for (; j < m; ++j) fwd(j, bA, bA);
             }
-            if (j < m) fwd(j++, bA, bC);
-            if (j < m) fwd(j++, bB, bA);
-        } else if constexpr (DEPTH == 1) {
-            for (; j + 2 <= m; j += 2) {
-                fwd(j, bA, bB);
-                fwd(j + 1, bB, bA);
-            }
-            if (j < m) fwd(j++, bA, bB);
-        } else {
-            for (; j < m; ++j) fwd(j, bA, bA);
         }
     }
     // back: x_{m-1} = z_{m-1}; x_j = z_j + F_j (beta_{j+1} x_{j+1})
@@ -698,7 +786,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
     const int *__restrict__ idx, const int *__restrict__ count, int64_t slot_base,
     uint32_t *__restrict__ state, double *__restrict__ relres, double *__restrict__ q,
-    int32_t *__restrict__ iters)
+    int32_t *__restrict__ iters, int fwd_done)
 {
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1, NT = 64 * blk_waves<M, G>();
     __shared__ double red[NT];
@@ -711,7 +799,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     double *xs = x + vo, *rsb = r + vo, *zs = zbuf + vo;
     const double *as = a + (size_t)s * (n + 1) * (n + 1);
     const double h = 1.0 / n;
-    solve_blk_pass<Tst, M, G, PREF>(scs, bs, fs, nullptr, h * h * fconst, xs, 0, zs);
+    solve_blk_pass<Tst, M, G, PREF>(scs, bs, fs, nullptr, h * h * fconst, xs, 0, zs, fwd_done != 0);
     uint32_t st = state[s] & ~(uint32_t)ST_DONE;
     double prev = INFINITY, rel = INFINITY, sx = 0.0;
     int trip = 0;
@@ -810,10 +898,11 @@ template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static c
 
 template <typename Tst, int M>
 hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const int *idx,
-              const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
+              const int *count, int64_t slot_base, uint32_t *state, const double *fsc, double frhs,
+              double *fz, hipStream_t st)
 {
     hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
-                       (Tst *)factor, idx, count, slot_base, state);
+                       (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
     return hipGetLastError();
 }
 
@@ -840,7 +929,8 @@ hipError_t li_g(const ir_args &g, hipStream_t st)
     constexpr bool PREF = ir_pref<Tst, M, G>::v;
     hipLaunchKernelGGL((k_ir_blk<Tst, M, G, PREF>), dim3(g.nblocks), dim3(64 * blk_waves<M, G>()), 0, st, g.n,
                        g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps,
-                       g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters);
+                       g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
+                       g.fwd_done);
     return hipGetLastError();
 }
 
@@ -870,14 +960,15 @@ hipError_t li_m(const ir_args &g, hipStream_t st)
 
 template <typename Tst>
 hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *factor, const int *idx,
-                const int *count, int64_t slot_base, uint32_t *state, hipStream_t st)
+                const int *count, int64_t slot_base, uint32_t *state, const double *fsc, double frhs,
+                double *fz, hipStream_t st)
 {
     switch (M) {
-    case 16: return lf<Tst, 16>(nb, beta, gam, factor, idx, count, slot_base, state, st);
-    case 32: return lf<Tst, 32>(nb, beta, gam, factor, idx, count, slot_base, state, st);
-    case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, count, slot_base, state, st);
-    case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, count, slot_base, state, st);
-    case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 16: return lf<Tst, 16>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 32: return lf<Tst, 32>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
     }
     return hipErrorInvalidValue;
 }
@@ -909,15 +1000,20 @@ hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double
 
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
                              void *factor, const int *idx, const int *count, int64_t slot_base,
-                             uint32_t *state, hipStream_t st)
+                             uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return lf_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
-    case 1: return lf_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
-    case 2: return lf_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
-    case 3: return lf_m<__half>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 0: return lf_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 1: return lf_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 3: return lf_m<__half>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
     }
     return hipErrorInvalidValue;
+}
+
+bool factor_fuses_forward(int dtype, int n)
+{
+    return use_blk(dtype, n) && dtype != 0;
 }
 
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st)

@@ -44,6 +44,7 @@ struct ir_args {
     double *relres, *q;
     int32_t *iters;
     int variant;  // refinement-kernel variant (0: built-in default; n >= 64: waves per row pair)
+    int fwd_done;  // the factorisation wrote the forward sweep of the initial solve to z
 };
 
 hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi,
@@ -57,9 +58,13 @@ hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double 
                             const double *gq, double *grad, hipStream_t st);
 hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
                          hipStream_t st);
+// With fz != NULL (and factor_fuses_forward), the factorisation also runs the
+// forward sweep of the solve for the right-hand side frhs (constant, interior
+// unknowns) scaled by fsc, writing z to fz (the refinement's z buffer).
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, const double *gam,
                          void *factor, const int *idx, const int *count, int64_t slot_base,
-                         uint32_t *state, hipStream_t st);
+                         uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st);
+bool factor_fuses_forward(int dtype, int n);
 // Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample.
 hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const double *beta,
@@ -68,7 +73,7 @@ hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const d
                         const uint32_t *state, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
                              void *factor, const int *idx, const int *count, int64_t slot_base,
-                             uint32_t *state, hipStream_t st);
+                             uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_solve_blk(int dtype, int n, int nblocks, const double *sc, const double *beta,
                             const void *factor, const double *rhs, double rhs_const, double *x,
