@@ -42,11 +42,11 @@ DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 # HBM bytes per sample measured with FETCH_SIZE / WRITE_SIZE counters (scaled
 # by a copy kernel of known size) for the mixed FP32 step; valid only while the
 # kernel sources hash to TRAFFIC_SRC (otherwise the field is reported as null).
-TRAFFIC_SRC = "3db911e05894f5b1"
-TRAFFIC = {("factor", 128, "f32"): 4.9425e6, ("factor", 64, "f32"): 0.7098e6,
-           ("factor", 32, "f32"): 0.1111e6, ("factor", 16, "f32"): 0.0192e6,
-           ("solve", 128, "f32"): 22.0890e6, ("solve", 64, "f32"): 3.2712e6,
-           ("solve", 32, "f32"): 0.2655e6, ("solve", 16, "f32"): 0.0455e6}
+TRAFFIC_SRC = "70440c7250b2356f"
+TRAFFIC = {("factor", 128, "f32"): 5.2378e6, ("factor", 64, "f32"): 0.7834e6,
+           ("factor", 32, "f32"): 0.1299e6, ("factor", 16, "f32"): 0.0231e6,
+           ("solve", 128, "f32"): 17.0529e6, ("solve", 64, "f32"): 2.5318e6,
+           ("solve", 32, "f32"): 0.1496e6, ("solve", 16, "f32"): 0.0282e6}
 
 
 def kernel_src_hash():
@@ -66,24 +66,28 @@ def factor_entries(n, dtype):
     """Entries of the stored factor per sample: m diagonal blocks of the
     block-tridiagonal LDL^T, each the symmetric inverse Schur complement of
     size n (padded), stored as its lower tr x tr tiles (16 x 16 MFMA tiles
-    from n = 32 for the low-precision factors and from n = 64 for FP64)."""
+    on every grid for the low-precision factors, from n = 64 for FP64)."""
     m = n - 1
-    blk = n >= (64 if dtype == "f64" else 32)
+    blk = n >= (64 if dtype == "f64" else 16)
     tr = 16 if blk else (2 if n <= 16 else 4)
     tn = n // tr
     return m * tn * (tn + 1) // 2 * tr * tr
 
 
 def refine_bytes(n, trips, dtype):
-    """Algorithmic HBM bytes per sample of the refinement kernel: the initial
-    solve and `trips` corrections each read the factor twice (forward and
-    backward block sweeps) and the row couplings and scaling; every residual
-    (1 + trips) reads the nodal coefficient and the iterate; x is written."""
+    """Algorithmic HBM bytes per sample of the refinement kernel: each of the
+    `trips` corrections reads the factor twice (forward and backward block
+    sweeps), the initial solve once for the low-precision factors (whose
+    factorisation ran the forward sweep) and twice for FP64, each solve also
+    the row couplings and scaling; every residual (1 + trips) reads the nodal
+    coefficient and the iterate; x is written."""
     m = n - 1
     N = m * n
-    per_solve = 2 * factor_entries(n, dtype) * DT_BYTES[dtype] + 3 * N * 8
+    f_pass = factor_entries(n, dtype) * DT_BYTES[dtype]
+    initial = (2 if dtype == "f64" else 1) * f_pass + 3 * N * 8
+    per_corr = 2 * f_pass + 3 * N * 8
     per_resid = (n + 1) ** 2 * 8 + N * 8
-    return (1 + trips) * (per_solve + per_resid) + N * 8
+    return initial + trips * per_corr + (1 + trips) * per_resid + N * 8
 
 
 def parse():
