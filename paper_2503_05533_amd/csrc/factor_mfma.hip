@@ -789,7 +789,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     int32_t *__restrict__ iters, int fwd_done)
 {
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1, NT = 64 * blk_waves<M, G>();
-    __shared__ double red[NT];
+    __shared__ double red[3 * NT];
     const int b = blockIdx.x;
     if (count && b >= *count) return;
     const int s = idx ? idx[b] : b;
@@ -805,7 +805,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     int trip = 0;
     for (;;) {
         __syncthreads();
-        const resid_out o = residual_pass<NT>(n, fconst, as, xs, rsb, red);
+        const resid_out o = residual_pass_m<NT, M>(fconst, as, xs, rsb, red);
         rel = sqrt(o.rr) / sqrt(o.bb);
         sx = o.sx;
         st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);

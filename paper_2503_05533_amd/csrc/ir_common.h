@@ -69,6 +69,76 @@ __device__ inline resid_out residual_pass(int n, double fconst, const double *__
     return o;
 }
 
+// The same three sums in one tree (red holds 3 NT doubles): the order of
+// each sum is that of wg_sum, with a third of the barriers.
+template <int NT>
+__device__ inline resid_out wg_sum3(double a, double b, double c, double *red)
+{
+    const int t = threadIdx.x;
+    red[t] = a;
+    red[NT + t] = b;
+    red[2 * NT + t] = c;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            red[t] += red[t + s];
+            red[NT + t] += red[NT + t + s];
+            red[2 * NT + t] += red[2 * NT + t + s];
+        }
+        __syncthreads();
+    }
+    resid_out o;
+    o.rr = red[0];
+    o.bb = red[NT];
+    o.sx = red[2 * NT];
+    __syncthreads();
+    return o;
+}
+
+// residual_pass for a compile-time block size M = n: the same arithmetic
+// and per-thread order, with shift/mask indexing, a fixed trip count
+// unrolled by four, and branch-free neighbours (clamped indices, selected
+// terms; x - 0.0 and r + 0.0 are exact), so that the loads of several
+// unknowns are in flight together.  red holds 3 NT doubles.
+template <int NT, int M>
+__device__ inline resid_out residual_pass_m(double fconst, const double *__restrict__ as,
+                                            const double *__restrict__ xs, double *__restrict__ rs,
+                                            double *red)
+{
+    constexpr int m = M - 1, np = M + 1, TOT = m * M, IT = (TOT + NT - 1) / NT;
+    const double h = 1.0 / M, bval = h * h * fconst;
+    double rr = 0.0, bb = 0.0, sx = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < IT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const bool live = e < TOT;
+        const int ec = live ? e : TOT - 1;
+        const int j = ec / M, i = ec % M;
+        const bool in = live && i < m;
+        // node of the unknown; for the pad entry (i = m) it is a boundary node
+        // whose neighbours are still inside the node array (values unused)
+        const int p = (j + 1) * np + (i + 1);
+        const double c = as[p];
+        const double aw = hmean2(c, as[p - 1]), ae = hmean2(c, as[p + 1]);
+        const double asu = hmean2(c, as[p - np]), an = hmean2(c, as[p + np]);
+        const double xv = xs[ec];
+        const double xw = xs[ec > 0 ? ec - 1 : 0], xe = xs[ec + 1 < TOT ? ec + 1 : TOT - 1];
+        const double xsn = xs[ec >= M ? ec - M : 0], xn = xs[ec + M < TOT ? ec + M : TOT - 1];
+        double ax = (aw + ae + asu + an) * xv;
+        ax -= i > 0 ? aw * xw : 0.0;
+        ax -= i + 1 < m ? ae * xe : 0.0;
+        ax -= j > 0 ? asu * xsn : 0.0;
+        ax -= j + 1 < m ? an * xn : 0.0;
+        const double rv = bval - ax;
+        if (rs && live) rs[ec] = in ? rv : 0.0;
+        rr += in ? rv * rv : 0.0;
+        bb += in ? bval * bval : 0.0;
+        sx += in ? xv : 0.0;
+    }
+    return wg_sum3<NT>(rr, bb, sx, red);
+}
+
 // Stop test of Algorithm 2.1 after `trip` corrections: converged when
 // relres < eps (strict); otherwise done at the trip limit, on a non-finite
 // value, or when the residual stopped decreasing.  Returns the new state.
