@@ -210,8 +210,12 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * sum_l s_l^2/N_l <= TOL^2/2 hold and no level needs more samples.
  * dtype_per_level[0..L_max] selects u_f per level (ignored for
  * MLMC_DIRECT/MLMC_MINRES).  mixed = 0 runs standard MLMC: every solve
- * uses eps = 0 targets replaced by the FP64 direct solve.  Allocates its own
- * device memory; synchronises once per round. */
+ * uses eps = 0 targets replaced by the FP64 direct solve.  Each level
+ * streams its chunks on one of the context's queue streams; one
+ * synchronisation per round.  Device memory: a per-level chunk workspace
+ * (8 GiB per level, up to 32 GiB for a level whose first n_init samples then
+ * fit one chunk), allocated on the first call and kept by the context for
+ * later calls (grown when a call needs more, freed by mlmc_destroy). */
 int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
                   mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream);
 

@@ -41,6 +41,9 @@ struct mlmc_ctx {
     // eager multi-level launches: one stream per hardware queue, events
     std::vector<hipStream_t> qstreams;
     std::vector<hipEvent_t> qevents;
+    // mlmc_estimate's workspace (chunk workspaces and xi buffers), kept
+    void *est_buf = nullptr;
+    size_t est_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uintptr_t> graph_key;
@@ -455,22 +458,29 @@ int level_enqueue(mlmc_ctx *ctx, int level, int64_t n, const double *xi, const m
 // factorisation).
 constexpr int kQueues = 4;
 
-int enqueue_levels_queued(mlmc_ctx *ctx, int n_levels, const int32_t *levels, const int64_t *n,
-                          const double *const *xi_dev, const mlmc_level_opts *opts, void *ws_dev,
-                          const std::vector<level_layout> &LL, const std::vector<size_t> &off,
-                          double *const *y_dev, hipStream_t os)
+// The context's kQueues streams (created back to back, default priority) and
+// at least nev events.
+int ensure_queues(mlmc_ctx *ctx, size_t nev)
 {
     while (ctx->qstreams.size() < (size_t)kQueues) {
         hipStream_t s2;
         HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
         ctx->qstreams.push_back(s2);
     }
-    const size_t nev = 1 + 2 * (size_t)n_levels + kQueues;
     while (ctx->qevents.size() < nev) {
         hipEvent_t e;
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         ctx->qevents.push_back(e);
     }
+    return MLMC_OK;
+}
+
+int enqueue_levels_queued(mlmc_ctx *ctx, int n_levels, const int32_t *levels, const int64_t *n,
+                          const double *const *xi_dev, const mlmc_level_opts *opts, void *ws_dev,
+                          const std::vector<level_layout> &LL, const std::vector<size_t> &off,
+                          double *const *y_dev, hipStream_t os)
+{
+    if (int rc = ensure_queues(ctx, 1 + 2 * (size_t)n_levels + kQueues)) return rc;
     struct job { int li, coarse; double cost; };
     std::vector<job> jobs;
     for (int i = 0; i < n_levels; ++i) {
@@ -626,6 +636,7 @@ int mlmc_destroy(mlmc_ctx *ctx)
     for (hipEvent_t e : ctx->levents) (void)hipEventDestroy(e);
     for (hipStream_t s2 : ctx->lstreams) (void)hipStreamDestroy(s2);
     for (hipEvent_t e : ctx->qevents) (void)hipEventDestroy(e);
+    if (ctx->est_buf) (void)hipFree(ctx->est_buf);
     for (hipStream_t s2 : ctx->qstreams) (void)hipStreamDestroy(s2);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -932,34 +943,54 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     const mlmc_config &c = ctx->cfg;
     const int Lmax = c.L_max;
     // Per-level chunk: as many samples as fit a per-level workspace budget, so
-    // that the fine levels fill the GPU; one workspace holds every level's
-    // chunk and the levels of a round run concurrently (mlmc_sample_levels).
+    // that the fine levels fill the GPU.  Each level has its own workspace and
+    // xi buffer and, within a round, streams its chunks back to back on one
+    // of the context's queue streams, so that a level with many chunks (the
+    // coarsest) and one with a few long ones (the finest) run side by side
+    // rather than in lockstep; every chunk's level sums are copied to pinned
+    // host memory and added in chunk order after the round's one
+    // synchronisation.
+    // A level's budget may grow to big_budget when that lets the chunk hold
+    // the initial N_l (rounded up to a power of two), so that a newly added
+    // fine level (few samples, each a long latency-bound chain) is one launch
+    // rather than several in sequence.
     const int64_t chunk_max = 1 << 18;
-    const size_t level_budget = (size_t)8 << 30;
+    const size_t level_budget = (size_t)8 << 30, big_budget = (size_t)32 << 30;
+    int64_t min_chunk = 1;
+    while (min_chunk < n_init) min_chunk *= 2;
     std::vector<int64_t> chunk(Lmax + 1);
     std::vector<mlmc_level_opts> lopt(Lmax + 1);
     size_t ws_bytes = 0, xi_bytes = 0;
-    std::vector<size_t> xi_off(Lmax + 1);
+    std::vector<size_t> xi_off(Lmax + 1), ws_off(Lmax + 1);
     for (int l = 0; l <= Lmax; ++l) {
         mlmc_level_opts o{};
         o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
         o.solver = mixed ? solver : MLMC_DIRECT;
         o.promote = 1;
         int64_t ch = chunk_max;
-        while (ch > 16 && make_level_layout(c, l, ch, o).bytes > level_budget) ch /= 2;
+        while (ch > 16) {
+            const size_t b = make_level_layout(c, l, ch, o).bytes;
+            if (b <= level_budget || (ch <= min_chunk && b <= big_budget)) break;
+            ch /= 2;
+        }
         chunk[l] = ch;
         lopt[l] = o;
+        ws_off[l] = ws_bytes;
         ws_bytes += align256(make_level_layout(c, l, ch, o).bytes);
         xi_off[l] = xi_bytes;
         xi_bytes += align256((size_t)ch * c.K * 8);
     }
-    void *ws = nullptr;
-    char *xi = nullptr;
-    HIPCHK(hipMalloc(&ws, ws_bytes));
-    if (hipMalloc(&xi, xi_bytes) != hipSuccess) {
-        (void)hipFree(ws);
-        return fail(ctx, MLMC_EHIP, "estimate: out of device memory");
+    const size_t need = align256(ws_bytes) + xi_bytes;
+    if (ctx->est_bytes < need) {
+        if (ctx->est_buf) (void)hipFree(ctx->est_buf);
+        ctx->est_buf = nullptr;
+        ctx->est_bytes = 0;
+        if (hipMalloc(&ctx->est_buf, need) != hipSuccess)
+            return fail(ctx, MLMC_ENOMEM, "estimate: out of device memory (%zu bytes)", need);
+        ctx->est_bytes = need;
     }
+    void *ws = ctx->est_buf;
+    char *xi = (char *)ctx->est_buf + align256(ws_bytes);
     auto cost = [&](int l) {
         auto f = [](int n) { const double m = n - 1; return m * m * m * m; };
         return f(c.n0 << l) + (l > 0 ? f(c.n0 << (l - 1)) : 0.0);
@@ -970,42 +1001,75 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     std::vector<double> yhat, var;
     const double bias_c = (std::pow((double)c.m, c.alpha) - 1.0) / std::sqrt(2.0) * tol;
     double gpu_ms = 0.0;
+    double *hbuf = nullptr;  // pinned: 8 sums per chunk of a round
+    int hcap = 0;
     int rc = MLMC_OK;
     int converged = 0;
     for (int round = 0; round < 200; ++round) {
         double eps[16];
         mlmc_accuracy_targets(ctx, L, eps);
-        // top every level up to N_l: one concurrent multi-level call per chunk
-        while (rc >= 0) {
-            int32_t lv[16];
-            int64_t cnt[16];
-            const double *xp[16];
-            mlmc_level_opts op[16];
-            int nl = 0;
+        // top every level up to N_l
+        auto round_enqueue = [&](std::vector<std::pair<int, int64_t>> &recs) -> int {
+            int nchunks = 0;
+            for (int l = 0; l <= L; ++l)
+                if (N[l] > done[l]) nchunks += (int)((N[l] - done[l] + chunk[l] - 1) / chunk[l]);
+            if (nchunks == 0) return MLMC_OK;
+            if (int e = ensure_queues(ctx, 1 + kQueues)) return e;
+            if (nchunks > hcap) {
+                if (hbuf) (void)hipHostFree(hbuf);
+                hbuf = nullptr;
+                hcap = 0;
+                HIPCHK(hipHostMalloc((void **)&hbuf, (size_t)nchunks * 8 * sizeof(double), 0));
+                hcap = nchunks;
+            }
+            hipEvent_t fork = ctx->qevents[0];
+            HIPCHK(hipEventRecord(ctx->ev0, st));
+            HIPCHK(hipEventRecord(fork, st));
+            bool used[kQueues] = {};
             for (int l = 0; l <= L; ++l) {
-                const int64_t need = N[l] - done[l];
-                if (need <= 0) continue;
-                cnt[nl] = std::min<int64_t>(need, chunk[l]);
+                if (N[l] <= done[l]) continue;
+                const int q = l % kQueues;
+                hipStream_t sl = ctx->qstreams[q];
+                if (!used[q]) HIPCHK(hipStreamWaitEvent(sl, fork, 0));
+                used[q] = true;
+                mlmc_level_opts o = lopt[l];
+                o.eps_fine = mixed ? eps[l] : 0.0;
+                o.eps_coarse = mixed && l > 0 ? eps[l - 1] : 0.0;
+                void *wl = (char *)ws + ws_off[l];
                 double *xl = (double *)(xi + xi_off[l]);
-                if ((rc = mlmc_fill_xi(ctx, l, done[l], cnt[nl], xl, st))) break;
-                lv[nl] = l;
-                xp[nl] = xl;
-                op[nl] = lopt[l];
-                op[nl].eps_fine = mixed ? eps[l] : 0.0;
-                op[nl].eps_coarse = mixed && l > 0 ? eps[l - 1] : 0.0;
-                ++nl;
+                for (int64_t d0 = done[l]; d0 < N[l]; d0 += chunk[l]) {
+                    const int64_t cnt = std::min<int64_t>(N[l] - d0, chunk[l]);
+                    if (int e = mlmc_fill_xi(ctx, l, d0, cnt, xl, sl)) return e;
+                    const level_layout LLc = make_level_layout(c, l, cnt, o);
+                    if (int e = level_enqueue(ctx, l, cnt, xl, o, wl, LLc, nullptr, nullptr, nullptr, nullptr, sl,
+                                              sl, nullptr))
+                        return e;
+                    HIPCHK(hipMemcpyAsync(hbuf + 8 * recs.size(), at<double>(wl, LLc.off_sums), 8 * sizeof(double),
+                                          hipMemcpyDeviceToHost, sl));
+                    recs.push_back({l, cnt});
+                }
             }
-            if (rc < 0 || nl == 0) break;
-            mlmc_level_stats stt[16];
-            rc = mlmc_sample_levels(ctx, nl, lv, cnt, xp, op, ws, ws_bytes, nullptr, stt, 0, st);
-            if (rc < 0) break;
-            rc = MLMC_OK;  // non-converged samples are counted in the stats, not fatal
-            for (int i = 0; i < nl; ++i) {
-                s1[lv[i]] += stt[i].sum_y;
-                s2[lv[i]] += stt[i].sum_y2;
-                done[lv[i]] += cnt[i];
+            for (int q = 0; q < kQueues; ++q) {
+                if (!used[q]) continue;
+                HIPCHK(hipEventRecord(ctx->qevents[1 + q], ctx->qstreams[q]));
+                HIPCHK(hipStreamWaitEvent(st, ctx->qevents[1 + q], 0));
             }
-            gpu_ms += stt[0].gpu_ms;
+            HIPCHK(hipEventRecord(ctx->ev1, st));
+            HIPCHK(hipStreamSynchronize(st));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            gpu_ms += ms;
+            return MLMC_OK;
+        };
+        std::vector<std::pair<int, int64_t>> recs;
+        rc = round_enqueue(recs);
+        if (rc < 0) break;
+        rc = MLMC_OK;
+        for (size_t k = 0; k < recs.size(); ++k) {
+            const int l = recs[k].first;
+            s1[l] += hbuf[8 * k];
+            s2[l] += hbuf[8 * k + 1];
+            done[l] += recs[k].second;
         }
         if (rc < 0) break;
         yhat.assign(L + 1, 0.0);
@@ -1035,8 +1099,11 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
             break;
         }
     }
-    (void)hipFree(ws);
-    (void)hipFree(xi);
+    // nothing may still run on the buffers (a round that failed part-way has
+    // not joined its queue streams)
+    for (hipStream_t q : ctx->qstreams) (void)hipStreamSynchronize(q);
+    (void)hipStreamSynchronize(st);
+    if (hbuf) (void)hipHostFree(hbuf);
     if (rc < 0) return rc;
     memset(out, 0, sizeof *out);
     out->L = L;
