@@ -100,7 +100,9 @@ __device__ inline resid_out wg_sum3(double a, double b, double c, double *red)
 // and per-thread order, with shift/mask indexing, a fixed trip count
 // unrolled by four, and branch-free neighbours (clamped indices, selected
 // terms; x - 0.0 and r + 0.0 are exact), so that the loads of several
-// unknowns are in flight together.  red holds 3 NT doubles.
+// unknowns are in flight together (four, two for n <= 32, whose one-wave
+// refinement kernel keeps four waves per SIMD that way).  red holds 3 NT
+// doubles.
 template <int NT, int M>
 __device__ inline resid_out residual_pass_m(double fconst, const double *__restrict__ as,
                                             const double *__restrict__ xs, double *__restrict__ rs,
@@ -109,7 +111,7 @@ __device__ inline resid_out residual_pass_m(double fconst, const double *__restr
     constexpr int m = M - 1, np = M + 1, TOT = m * M, IT = (TOT + NT - 1) / NT;
     const double h = 1.0 / M, bval = h * h * fconst;
     double rr = 0.0, bb = 0.0, sx = 0.0;
-#pragma unroll 4
+#pragma unroll (M <= 32 ? 2 : 4)
     for (int k = 0; k < IT; ++k) {
         const int e = threadIdx.x + k * NT;
         const bool live = e < TOT;
