@@ -209,3 +209,37 @@ def test_adjoint_fullsize():
     qref = oracle.solve_batch(128, _phi(128, K, w["sigma2"], w["corr_len"]), xr)
     assert np.allclose(q.cpu().numpy()[idx], qref, rtol=1e-9, atol=0)
     ctx.close()
+
+
+def test_estimate_chunks_fp64_fullsize():
+    """Algorithm 4.1 at the bench tolerance on the FP64 path: level 0 takes ~1.6M
+    samples, streamed as many chunks on one queue stream with per-chunk sums added
+    in order.  The FP64 solves do not depend on the round's accuracy targets, so an
+    independent pass over the same xi ranges (other chunk sizes) must give every
+    level's mean and variance to rounding."""
+    torch = _torch()
+    from paper_2503_05533_amd import MLMC, Config
+    w = si.workload("mlmc4_n16-128_K64")
+    ctx = MLMC(Config(n0=w["n0"], L_max=3, K=w["K"], sigma2=w["sigma2"], corr_len=w["corr_len"],
+                      seed=w["seed"]), device="cuda:0")
+    res = ctx.estimate(2e-5, n_init=1000, dtypes=["f64"] * 4, solver="direct", mixed=False)
+    assert res["converged"] and res["L"] == 3
+    assert res["N"][0] > 3 * (1 << 18), res["N"]  # several estimator chunks
+    step = 200000
+    for l, N in enumerate(res["N"]):
+        s1 = s2 = 0.0
+        for first in range(0, N, step):
+            cnt = min(step, N - first)
+            out = ctx.sample_level(l, ctx.fill_xi(l, first, cnt), dtype="f64", solver="direct")
+            y = out["y"]
+            s1 += float(y.sum())
+            s2 += float((y * y).sum())
+            del out, y
+        torch.cuda.synchronize()
+        mean = s1 / N
+        var = max(s2 / N - mean * mean, 0.0)
+        _say("level %d N=%d: estimator %.15e / %.6e, independent pass %.15e / %.6e"
+             % (l, N, res["Yhat"][l], res["s2"][l], mean, var))
+        assert mean == pytest.approx(res["Yhat"][l], rel=1e-11, abs=1e-16)
+        assert var == pytest.approx(res["s2"][l], rel=1e-8, abs=1e-18)
+    ctx.close()
