@@ -507,6 +507,223 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
     if (t == 0 && bad) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
 }
 
+// ------------------------------------------------- single-block grids (M = 16)
+//
+// For M = 16 (FP32 arithmetic) every Schur block is one 16 x 16 tile, and a
+// wave factors four samples at once: lane l works on sample l / 16 and holds
+// row i = l % 16 of the current block in 16 registers (register c = column c).
+// Pivot row K is the value of register c in lane K of the same 16-lane row,
+// the DPP row-broadcast operand of one FMA per register; pivot column K is the
+// lane's own register K.  No LDS and no barrier: samples never share lanes.
+
+// One wait pair before a DPP read of a register that a VALU wrote just before;
+// the DPP source of each line below is not written by the line before it.
+template <int K> __device__ inline float rowbcast_w(float v)
+{
+    float r;
+    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:%c2 row_mask:0xf bank_mask:0xf"
+                 : "=v"(r)
+                 : "v"(v), "i"(K));
+    return r;
+}
+
+// a[c] += P[K][c] me for all 16 registers (P[K][c] = a[c] in lane K).
+template <int K> __device__ inline void fmac16_rowbcast(float a[16], float me)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f32_dpp %0, %0, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %1, %1, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %2, %2, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %3, %3, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %4, %4, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %5, %5, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %6, %6, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %7, %7, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %8, %8, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %9, %9, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %10, %10, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %11, %11, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %12, %12, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %13, %13, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %14, %14, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %15, %15, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf"
+                 : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]), "+v"(a[7]),
+                   "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]), "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
+                 : "v"(me), "i"(K));
+}
+
+// a[c] *= bv_c, with bv_c the value of bv in lane c of the 16-lane row.
+__device__ inline void scale16_colbcast(float a[16], float bv)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_mul_f32_dpp %0, %16, %0 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %1, %16, %1 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %2, %16, %2 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %3, %16, %3 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %4, %16, %4 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %5, %16, %5 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %6, %16, %6 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %7, %16, %7 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %8, %16, %8 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %9, %16, %9 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %10, %16, %10 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %11, %16, %11 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %12, %16, %12 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %13, %16, %13 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %14, %16, %14 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_mul_f32_dpp %15, %16, %15 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+                 : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]), "+v"(a[7]),
+                   "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]), "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
+                 : "v"(bv));
+}
+
+// acc + sum_c f[c] gv_c, with gv_c the value of gv in lane c of the 16-lane
+// row (the sum in column order; operand 0 is acc, 1..16 are f, 17 is gv).
+__device__ inline float dot16_colbcast(const float f[16], float gv, float acc)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f32_dpp %0, %17, %1 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %3 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %4 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %5 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %6 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %7 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %8 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %9 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %10 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %11 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %12 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %13 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %14 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %15 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f32_dpp %0, %17, %16 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(f[0]), "v"(f[1]), "v"(f[2]), "v"(f[3]), "v"(f[4]), "v"(f[5]), "v"(f[6]), "v"(f[7]),
+                   "v"(f[8]), "v"(f[9]), "v"(f[10]), "v"(f[11]), "v"(f[12]), "v"(f[13]), "v"(f[14]), "v"(f[15]),
+                   "v"(gv));
+    return acc;
+}
+
+template <int K>
+__device__ inline void sweep_row_step(float a[16], int i, bool &ok)
+{
+    const float d = rowbcast_w<K>(a[K]);  // P[K][K]
+    ok = ok && (d > 0.0f) && isfinite(d);
+    const float inv = recip(d), f = a[K] * inv;
+    const bool piv = (i == K);
+    // rows i != K: P[i][c] - f P[K][c]; row K: P[K][c] / d (as in sweep_step)
+    const float me = piv ? inv - 1.0f : -f;
+    const float colK = piv ? -inv : f;
+    fmac16_rowbcast<K>(a, me);
+    a[K] = colK;
+}
+
+// -P^{-1} of the 16 x 16 SPD block held one row per lane (see above).
+__device__ inline bool sweep16_rows(float a[16], int i)
+{
+    bool ok = true;
+    sweep_row_step<0>(a, i, ok);
+    sweep_row_step<1>(a, i, ok);
+    sweep_row_step<2>(a, i, ok);
+    sweep_row_step<3>(a, i, ok);
+    sweep_row_step<4>(a, i, ok);
+    sweep_row_step<5>(a, i, ok);
+    sweep_row_step<6>(a, i, ok);
+    sweep_row_step<7>(a, i, ok);
+    sweep_row_step<8>(a, i, ok);
+    sweep_row_step<9>(a, i, ok);
+    sweep_row_step<10>(a, i, ok);
+    sweep_row_step<11>(a, i, ok);
+    sweep_row_step<12>(a, i, ok);
+    sweep_row_step<13>(a, i, ok);
+    sweep_row_step<14>(a, i, ok);
+    sweep_row_step<15>(a, i, ok);
+    return ok;
+}
+
+// Factorisation of one sample per 16 lanes, 16 samples per workgroup; same
+// arguments, stored layout and forward sweep as k_factor_mfma at M = 16.  The
+// stored block keeps lane l = 16 g + r's entries (row 4 g + c, column r) at
+// offset l * 4 + c; by symmetry those are row r's registers 4 g .. 4 g + 3,
+// so each lane stores four 4-entry vectors and the 16 lanes of a sample
+// cover every 256-entry block contiguously.
+template <typename Tst>
+__global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__restrict__ beta,
+                                                       const double *__restrict__ gam,
+                                                       Tst *__restrict__ factor,
+                                                       const int *__restrict__ idx,
+                                                       const int *__restrict__ count,
+                                                       int64_t slot_base, uint32_t *__restrict__ state,
+                                                       const double *__restrict__ fsc, double frhs,
+                                                       double *__restrict__ fz)
+{
+    constexpr int M = 16, m = M - 1;
+    const int i = threadIdx.x & 15;
+    const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
+    // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
+    if (b >= (count ? *count : S)) return;
+    const int s = idx ? idx[b] : b;
+    const int64_t slot = slot_base + b;
+    const double *bs = beta + (size_t)s * m * M;
+    const double *gs = gam + (size_t)s * m * M;
+    Tst *fs = factor + (size_t)slot * m * 256;
+    const bool fwd = fz != nullptr;
+    const double *fscs = fwd ? fsc + (size_t)s * m * M : nullptr;
+    double *fzs = fwd ? fz + (size_t)s * m * M : nullptr;
+
+    float a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = 0.0f;
+    float zc = 0.0f;  // z_{j-1}, entry i
+    double pb = bs[i], pg = gs[i], ps = fwd ? fscs[i] : 0.0;
+    bool ok = true;
+
+    for (int j = 0; j < m; ++j) {
+        const float bf = (float)pb, gf = (float)pg;
+        const double sj = ps;
+        if (j + 1 < m) {
+            pb = bs[(j + 1) * M + i];
+            pg = gs[(j + 1) * M + i];
+            if (fwd) ps = fscs[(j + 1) * M + i];
+        }
+        // C_j = T_j + diag(beta_j) (-C_{j-1}^{-1}) diag(beta_j); T_j has unit
+        // diagonal and gamma_j[c] at (c + 1, c) and (c, c + 1)
+        const float gl = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(gf), 0x111, 0xF, 0xF, false));  // gamma_j[i-1]
+        scale16_colbcast(a, bf);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            float tv = (c == i + 1) ? gf : 0.0f;
+            tv = (c + 1 == i) ? gl : tv;
+            tv = (c == i) ? 1.0f : tv;
+            a[c] = fmaf(bf, a[c], tv);
+        }
+        ok = sweep16_rows(a, i) && ok;
+        // store -C_j^{-1}
+        Tst *fb = fs + (size_t)j * 256;
+        float fr[16];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            quad<Tst> qv;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                qv.v[c] = store_traits<Tst>::store(a[4 * g + c]);
+                fr[4 * g + c] = store_traits<Tst>::load(qv.v[c]);
+            }
+            *(quad<Tst> *)(fb + (16 * g + i) * 4) = qv;
+        }
+        if (fwd) {
+            // z_j = -F_j (s_j rhs - beta_j z_{j-1}) with F_j as stored
+            const float gv0 = (float)(sj * (i < m ? frhs : 0.0));
+            const float gv = j > 0 ? gv0 - bf * zc : gv0;
+            zc = -dot16_colbcast(fr, gv, 0.0f);
+            fzs[j * M + i] = (double)zc;
+        }
+    }
+    if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
+}
+
 // ------------------------------------------------------------------ block solve
 
 // x (+)= S Ahat^{-1} S rhs for one sample with the block-layout factor fs
@@ -901,8 +1118,14 @@ hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const
               const int *count, int64_t slot_base, uint32_t *state, const double *fsc, double frhs,
               double *fz, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
-                       (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
+    if constexpr (M == 16 && sizeof(typename store_traits<Tst>::acc) == 4) {
+        if (nb == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_factor_rows16<Tst>), dim3((unsigned)((nb + 15) / 16)), dim3(256), 0, st, nb, beta,
+                           gam, (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
+    } else {
+        hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
+                           (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
+    }
     return hipGetLastError();
 }
 
