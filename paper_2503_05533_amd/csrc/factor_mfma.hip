@@ -724,6 +724,208 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
     if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
 }
 
+// Algorithm 2.1 on the n = 16 grid with the factor of k_factor_rows16: 16
+// lanes per sample (lane i owns the unknowns (i, j) of every grid row j and
+// row i of every stored F_j, the entries its factorisation lane stored), 16
+// samples per workgroup, no LDS.  The solution x and the forward-sweep
+// result z stay in registers; F_j is applied row by row with the vector it
+// multiplies broadcast along the 16-lane row.  The FP64 residual takes its
+// east and west neighbours by DPP row shifts and forms each face coefficient
+// once (the east face is the west face of the next lane, the south face the
+// north face of the row before); the per-sample sums are fixed-order DPP
+// reductions.  A correction recomputes the residual row by row inside its
+// forward sweep instead of storing it.  Same arguments and outputs as
+// k_ir_blk at M = 16, with the sample count S first.
+template <typename Tst>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ir_rows16(int S, double fconst, const double *__restrict__ a,
+                                                   const double *__restrict__ sc,
+                                                   const double *__restrict__ beta,
+                                                   const Tst *__restrict__ factor, double *__restrict__ x,
+                                                   const double *__restrict__ zbuf, double eps, int imax,
+                                                   int direct, const int *__restrict__ idx,
+                                                   const int *__restrict__ count, int64_t slot_base,
+                                                   uint32_t *__restrict__ state, double *__restrict__ relres,
+                                                   double *__restrict__ q, int32_t *__restrict__ iters,
+                                                   int fwd_done)
+{
+    constexpr int M = 16, m = M - 1, NP = M + 1;
+    const int i = threadIdx.x & 15;
+    const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
+    // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
+    if (b >= (count ? *count : S)) return;
+    const int s = idx ? idx[b] : b;
+    const size_t vo = (size_t)s * m * M + i;
+    const double *scs = sc + vo, *bs = beta + vo;
+    double *xs = x + vo;
+    const Tst *fs = factor + (size_t)(slot_base + b) * m * 256 + i * 4;  // row i: 4 entries at g * 64
+    const double *ac = a + (size_t)s * NP * NP + (i + 1);                // node column i + 1
+    const double h = 1.0 / M, bval = h * h * fconst;
+    const bool in = i < m;  // lane m is the identity pad
+
+    // Loads in the sweeps and residual passes take an offset the compiler cannot
+    // see through (opaque): without it, the addresses of all 60 factor loads and
+    // the loop-invariant coefficient loads of every row are hoisted out of the
+    // refinement loop and held in registers.
+    auto opaque = [](int v) {
+        asm volatile("" : "+v"(v));
+        return v;
+    };
+    auto ldq = [&](int j, quad<Tst> (&dst)[4]) {
+        const Tst *fb = fs + opaque(j * 256);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) dst[g] = *(const quad<Tst> *)(fb + g * 64);
+    };
+    auto row_of = [&](const quad<Tst> (&src)[4], float (&f)[16]) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) f[4 * g + c] = store_traits<Tst>::load(src[g].v[c]);
+    };
+
+    float z[m];    // z_j, entry i
+    double xv[m];  // x_j, entry i
+    // Every step uses operands loaded one step earlier and first requests the
+    // next step's (loads complete in order, so a wait for a late request would
+    // also wait for the prefetch in front of it).
+    quad<Tst> fq[2][4];
+    double scp[2], bp[2];
+
+    // Forward sweep z_j = -F_j (s_j r_j - beta_j z_{j-1}); rj(j) gives r_j and
+    // runs before the step's arithmetic (it may issue loads of its own).
+    auto forward = [&](auto &&rj) {
+        const int o = opaque(0);
+        const double *scq = scs + o, *bq = bs + o;
+        ldq(0, fq[0]);
+        scp[0] = scq[0];
+        bp[0] = 0.0;
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            if (j + 1 < m) {
+                ldq(j + 1, fq[(j + 1) & 1]);
+                scp[(j + 1) & 1] = scq[(j + 1) * M];
+                bp[(j + 1) & 1] = bq[(j + 1) * M];
+            }
+            const double r = rj(j);
+            const float gv0 = (float)(scp[j & 1] * r);
+            const float gv = j > 0 ? gv0 - (float)bp[j & 1] * z[j - 1] : gv0;
+            float f[16];
+            row_of(fq[j & 1], f);
+            z[j] = -dot16_colbcast(f, gv, 0.0f);
+            __builtin_amdgcn_sched_barrier(0);  // one grid row at a time: bounds the registers in flight
+        }
+    };
+    // back: x_{m-1} = s z_{m-1}; x_j = s_j (z_j + F_j (beta_{j+1} x~_{j+1})),
+    // x~ the unscaled iterate; accumulate adds to x
+    auto back = [&](bool accumulate) {
+        const int o = opaque(0);
+        const double *scq = scs + o, *bq = bs + o;
+        ldq(m - 2, fq[(m - 2) & 1]);
+        scp[(m - 2) & 1] = scq[(m - 2) * M];
+        bp[(m - 2) & 1] = bq[(m - 1) * M];
+        float xc = z[m - 1];
+        {
+            const double d = scq[(m - 1) * M] * (double)xc;
+            xv[m - 1] = accumulate ? xv[m - 1] + d : d;
+            xs[(m - 1) * M] = xv[m - 1];
+        }
+#pragma unroll
+        for (int j = m - 2; j >= 0; --j) {
+            if (j > 0) {
+                ldq(j - 1, fq[(j - 1) & 1]);
+                scp[(j - 1) & 1] = scq[(j - 1) * M];
+                bp[(j - 1) & 1] = bq[j * M];
+            }
+            const float gv = (float)bp[j & 1] * xc;
+            float f[16];
+            row_of(fq[j & 1], f);
+            xc = z[j] + dot16_colbcast(f, gv, 0.0f);
+            const double d = scp[j & 1] * (double)xc;
+            xv[j] = accumulate ? xv[j] + d : d;
+            xs[j * M] = xv[j];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // Residual r = b - A x row by row (entry i; 0 on the pad): the object keeps
+    // the carried face and the prefetched node values of the next row.
+    struct resid_rows {
+        const double *ac;
+        double c, aS, cN, w;  // centre of row j, its south face, prefetched north and west nodes
+    };
+    auto resid_start = [&]() {
+        resid_rows R;
+        R.ac = ac + opaque(0);  // face coefficients are formed anew in every pass
+        R.c = R.ac[NP];
+        R.aS = hmean2(R.c, R.ac[0]);
+        R.cN = R.ac[2 * NP];
+        R.w = R.ac[NP - 1];
+        return R;
+    };
+    auto resid_row = [&](resid_rows &R, int j) {
+        const double cN = R.cN, w = R.w;
+        if (j + 1 < m) {
+            R.cN = R.ac[(j + 3) * NP];
+            R.w = R.ac[(j + 2) * NP - 1];
+        }
+        const double aw = hmean2(R.c, w), an = hmean2(R.c, cN);
+        const double ae = dpp_f64<0x101>(aw);  // the next lane's west face
+        const double xw = dpp_f64<0x111>(xv[j]), xe = dpp_f64<0x101>(xv[j]);
+        double ax = (aw + ae + R.aS + an) * xv[j];
+        ax -= i > 0 ? aw * xw : 0.0;
+        ax -= i + 1 < m ? ae * xe : 0.0;
+        if (j > 0) ax -= R.aS * xv[j - 1];
+        if (j + 1 < m) ax -= an * xv[j + 1];
+        R.c = cN;
+        R.aS = an;
+        return in ? bval - ax : 0.0;
+    };
+
+    // initial solve
+    if (fwd_done) {
+#pragma unroll
+        for (int j = 0; j < m; ++j) z[j] = (float)zbuf[vo + j * M];
+    } else {
+        forward([&](int) { return in ? bval : 0.0; });
+    }
+    back(false);
+
+    uint32_t st = state[s] & ~(uint32_t)ST_DONE;
+    double prev = INFINITY, rel = INFINITY, sx = 0.0;
+    int trip = 0;
+    for (;;) {
+        double rr = 0.0, bb = 0.0, sxl = 0.0;
+        {
+            resid_rows R = resid_start();
+#pragma unroll
+            for (int j = 0; j < m; ++j) {
+                const double rv = resid_row(R, j);
+                rr += rv * rv;
+                bb += in ? bval * bval : 0.0;
+                sxl += in ? xv[j] : 0.0;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        rr = rowbcast<15>(row16_total(rr));
+        bb = rowbcast<15>(row16_total(bb));
+        sx = rowbcast<15>(row16_total(sxl));
+        rel = sqrt(rr) / sqrt(bb);
+        st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
+        if (st & ST_DONE) break;
+        prev = rel;
+        {
+            resid_rows R = resid_start();
+            forward([&](int j) { return resid_row(R, j); });
+        }
+        back(true);
+        ++trip;
+    }
+    if (i == 0) {
+        state[s] = st;
+        relres[s] = rel;
+        q[s] = h * h * sx;
+        if (iters) iters[s] = trip;
+    }
+}
+
 // ------------------------------------------------------------------ block solve
 
 // x (+)= S Ahat^{-1} S rhs for one sample with the block-layout factor fs
@@ -1160,7 +1362,14 @@ hipError_t li_g(const ir_args &g, hipStream_t st)
 template <typename Tst, int M>
 hipError_t li(const ir_args &g, hipStream_t st)
 {
-    if constexpr (M == 16) {
+    if constexpr (M == 16 && sizeof(typename store_traits<Tst>::acc) == 4) {
+        if (g.nblocks == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_ir_rows16<Tst>), dim3((unsigned)((g.nblocks + 15) / 16)), dim3(256), 0, st,
+                           g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
+                           g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
+                           g.fwd_done);
+        return hipGetLastError();
+    } else if constexpr (M == 16) {
         return li_g<Tst, M, 1>(g, st);
     } else {
         int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
