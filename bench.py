@@ -67,9 +67,10 @@ def factor_entries(n, dtype):
     """Entries of the stored factor per sample: m diagonal blocks of the
     block-tridiagonal LDL^T, each the symmetric inverse Schur complement of
     size n (padded), stored as its lower tr x tr tiles (16 x 16 MFMA tiles
-    on every grid for the low-precision factors, from n = 64 for FP64)."""
+    on every grid for the low-precision factors, at n = 16 and from n = 64
+    for FP64)."""
     m = n - 1
-    blk = n >= (64 if dtype == "f64" else 16)
+    blk = n >= (64 if dtype == "f64" else 16) or n == 16
     tr = 16 if blk else (2 if n <= 16 else 4)
     tn = n // tr
     return m * tn * (tn + 1) // 2 * tr * tr
@@ -78,14 +79,16 @@ def factor_entries(n, dtype):
 def refine_bytes(n, trips, dtype):
     """Algorithmic HBM bytes per sample of the refinement kernel: each of the
     `trips` corrections reads the factor twice (forward and backward block
-    sweeps), the initial solve once for the low-precision factors (whose
-    factorisation ran the forward sweep) and twice for FP64, each solve also
-    the row couplings and scaling; every residual (1 + trips) reads the nodal
-    coefficient and the iterate; x is written."""
+    sweeps), the initial solve once where the factorisation ran the forward
+    sweep (the low-precision factors, and FP64 at n = 16) and twice for
+    FP64 elsewhere, each solve also the row couplings and scaling; every
+    residual (1 + trips) reads the nodal coefficient and the iterate; x is
+    written."""
     m = n - 1
     N = m * n
     f_pass = factor_entries(n, dtype) * DT_BYTES[dtype]
-    initial = (2 if dtype == "f64" else 1) * f_pass + 3 * N * 8
+    fused = dtype != "f64" or n == 16
+    initial = (1 if fused else 2) * f_pass + 3 * N * 8
     per_corr = 2 * f_pass + 3 * N * 8
     per_resid = (n + 1) ** 2 * 8 + N * 8
     return initial + trips * per_corr + (1 + trips) * per_resid + N * 8

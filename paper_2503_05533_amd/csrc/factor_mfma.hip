@@ -605,49 +605,178 @@ __device__ inline float dot16_colbcast(const float f[16], float gv, float acc)
     return acc;
 }
 
-template <int K>
-__device__ inline void sweep_row_step(float a[16], int i, bool &ok)
+// FP64 forms of the row helpers: v_fmac_f64 takes the row broadcast as its DPP
+// operand; the 64-bit multiply has no DPP form, so the column scaling of the
+// Schur complement is folded into an FMA (see form_schur16).
+template <int K> __device__ inline double rowbcast_w(double v)
 {
-    const float d = rowbcast_w<K>(a[K]);  // P[K][K]
-    ok = ok && (d > 0.0f) && isfinite(d);
-    const float inv = recip(d), f = a[K] * inv;
+    double r;
+    asm volatile("s_nop 1\n\tv_mov_b64_dpp %0, %1 row_newbcast:%c2 row_mask:0xf bank_mask:0xf"
+                 : "=v"(r)
+                 : "v"(v), "i"(K));
+    return r;
+}
+template <int K> __device__ inline void fmac16_rowbcast(double a[16], double me)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %0, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %1, %1, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %2, %2, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %3, %3, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %4, %4, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %5, %5, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %6, %6, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %7, %7, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %8, %8, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %9, %9, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %10, %10, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %11, %11, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %12, %12, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %13, %13, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %14, %14, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %15, %15, %16 row_newbcast:%c17 row_mask:0xf bank_mask:0xf"
+                 : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]), "+v"(a[7]),
+                   "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]), "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
+                 : "v"(me), "i"(K));
+}
+__device__ inline double dot16_colbcast(const double f[16], double gv, double acc)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %17, %1 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %2 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %3 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %4 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %5 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %6 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %7 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %8 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %9 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %10 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %11 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %12 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %13 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %14 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %15 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %17, %16 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(f[0]), "v"(f[1]), "v"(f[2]), "v"(f[3]), "v"(f[4]), "v"(f[5]), "v"(f[6]), "v"(f[7]),
+                   "v"(f[8]), "v"(f[9]), "v"(f[10]), "v"(f[11]), "v"(f[12]), "v"(f[13]), "v"(f[14]), "v"(f[15]),
+                   "v"(gv));
+    return acc;
+}
+// t[c] += bv_c u[c] for c in [8 H, 8 H + 8), bv_c the value of bv in lane c of
+// the 16-lane row (operands: t 0..7, bv 16, u 8..15)
+__device__ inline void fma8_colbcast_lo(double t[8], const double u[8], double bv)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %16, %8 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %1, %16, %9 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %2, %16, %10 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %3, %16, %11 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %4, %16, %12 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %5, %16, %13 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %6, %16, %14 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %7, %16, %15 row_newbcast:7 row_mask:0xf bank_mask:0xf"
+                 : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]), "+v"(t[7])
+                 : "v"(u[0]), "v"(u[1]), "v"(u[2]), "v"(u[3]), "v"(u[4]), "v"(u[5]), "v"(u[6]), "v"(u[7]),
+                   "v"(bv));
+}
+__device__ inline void fma8_colbcast_hi(double t[8], const double u[8], double bv)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %16, %8 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %1, %16, %9 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %2, %16, %10 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %3, %16, %11 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %4, %16, %12 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %5, %16, %13 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %6, %16, %14 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %7, %16, %15 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+                 : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]), "+v"(t[7])
+                 : "v"(u[0]), "v"(u[1]), "v"(u[2]), "v"(u[3]), "v"(u[4]), "v"(u[5]), "v"(u[6]), "v"(u[7]),
+                   "v"(bv));
+}
+
+// Entry c of row i of T_j (unit diagonal, gamma_j[c] at (c + 1, c) and
+// (c, c + 1)): gf = gamma_j[i], gl = gamma_j[i - 1].
+template <typename T>
+__device__ inline T tri_entry(int c, int i, T gf, T gl)
+{
+    T tv = (c == i + 1) ? gf : (T)0;
+    tv = (c + 1 == i) ? gl : tv;
+    return (c == i) ? (T)1 : tv;
+}
+// C_j = T_j + diag(beta_j) (-C_{j-1}^{-1}) diag(beta_j), row i per lane.
+__device__ inline void form_schur16(float a[16], float bf, float gf, float gl, int i)
+{
+    scale16_colbcast(a, bf);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = fmaf(bf, a[c], tri_entry(c, i, gf, gl));
+}
+__device__ inline void form_schur16(double a[16], double bf, double gf, double gl, int i)
+{
+    double t[16], u[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        t[c] = tri_entry(c, i, gf, gl);
+        u[c] = bf * a[c];
+    }
+    fma8_colbcast_lo(t, u, bf);
+    fma8_colbcast_hi(t + 8, u + 8, bf);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = t[c];
+}
+
+template <typename T, int K>
+__device__ inline void sweep_row_step(T a[16], int i, bool &ok)
+{
+    const T d = rowbcast_w<K>(a[K]);  // P[K][K]
+    ok = ok && (d > (T)0) && isfinite(d);
+    const T inv = recip(d), f = a[K] * inv;
     const bool piv = (i == K);
     // rows i != K: P[i][c] - f P[K][c]; row K: P[K][c] / d (as in sweep_step)
-    const float me = piv ? inv - 1.0f : -f;
-    const float colK = piv ? -inv : f;
+    const T me = piv ? inv - (T)1 : -f;
+    const T colK = piv ? -inv : f;
     fmac16_rowbcast<K>(a, me);
     a[K] = colK;
 }
 
 // -P^{-1} of the 16 x 16 SPD block held one row per lane (see above).
-__device__ inline bool sweep16_rows(float a[16], int i)
+template <typename T>
+__device__ inline bool sweep16_rows(T a[16], int i)
 {
     bool ok = true;
-    sweep_row_step<0>(a, i, ok);
-    sweep_row_step<1>(a, i, ok);
-    sweep_row_step<2>(a, i, ok);
-    sweep_row_step<3>(a, i, ok);
-    sweep_row_step<4>(a, i, ok);
-    sweep_row_step<5>(a, i, ok);
-    sweep_row_step<6>(a, i, ok);
-    sweep_row_step<7>(a, i, ok);
-    sweep_row_step<8>(a, i, ok);
-    sweep_row_step<9>(a, i, ok);
-    sweep_row_step<10>(a, i, ok);
-    sweep_row_step<11>(a, i, ok);
-    sweep_row_step<12>(a, i, ok);
-    sweep_row_step<13>(a, i, ok);
-    sweep_row_step<14>(a, i, ok);
-    sweep_row_step<15>(a, i, ok);
+    sweep_row_step<T, 0>(a, i, ok);
+    sweep_row_step<T, 1>(a, i, ok);
+    sweep_row_step<T, 2>(a, i, ok);
+    sweep_row_step<T, 3>(a, i, ok);
+    sweep_row_step<T, 4>(a, i, ok);
+    sweep_row_step<T, 5>(a, i, ok);
+    sweep_row_step<T, 6>(a, i, ok);
+    sweep_row_step<T, 7>(a, i, ok);
+    sweep_row_step<T, 8>(a, i, ok);
+    sweep_row_step<T, 9>(a, i, ok);
+    sweep_row_step<T, 10>(a, i, ok);
+    sweep_row_step<T, 11>(a, i, ok);
+    sweep_row_step<T, 12>(a, i, ok);
+    sweep_row_step<T, 13>(a, i, ok);
+    sweep_row_step<T, 14>(a, i, ok);
+    sweep_row_step<T, 15>(a, i, ok);
     return ok;
 }
 
+// Value of lane i - 1 of the 16-lane row (0 in lane 0).
+__device__ inline float row_shr1(float v) { return dpp_f32<0x111>(v); }
+__device__ inline double row_shr1(double v) { return dpp_f64<0x111>(v); }
+
 // Factorisation of one sample per 16 lanes, 16 samples per workgroup; same
-// arguments, stored layout and forward sweep as k_factor_mfma at M = 16.  The
-// stored block keeps lane l = 16 g + r's entries (row 4 g + c, column r) at
-// offset l * 4 + c; by symmetry those are row r's registers 4 g .. 4 g + 3,
-// so each lane stores four 4-entry vectors and the 16 lanes of a sample
-// cover every 256-entry block contiguously.
+// arguments and stored layout as k_factor_mfma at M = 16, and the forward
+// sweep of the initial solve for every factor type.  The stored block keeps
+// the entry (row drow(g, c), column r) of MFMA lane l = 16 g + r at offset
+// l * 4 + c; by symmetry that is entry drow(g, c) of row r, so each lane
+// stores four 4-entry vectors and the 16 lanes of a sample cover every
+// 256-entry block contiguously.  The solves read each lane's vectors back as
+// its row.
 template <typename Tst>
 __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__restrict__ beta,
                                                        const double *__restrict__ gam,
@@ -658,11 +787,12 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
                                                        const double *__restrict__ fsc, double frhs,
                                                        double *__restrict__ fz)
 {
+    using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1;
     const int i = threadIdx.x & 15;
     const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
     // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
-    if (b >= (count ? *count : S)) return;
+    if (b >= S || (count && b >= *count)) return;
     const int s = idx ? idx[b] : b;
     const int64_t slot = slot_base + b;
     const double *bs = beta + (size_t)s * m * M;
@@ -672,57 +802,52 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
     const double *fscs = fwd ? fsc + (size_t)s * m * M : nullptr;
     double *fzs = fwd ? fz + (size_t)s * m * M : nullptr;
 
-    float a[16];
+    Tac a[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) a[c] = 0.0f;
-    float zc = 0.0f;  // z_{j-1}, entry i
+    for (int c = 0; c < 16; ++c) a[c] = 0;
+    Tac zc = 0;  // z_{j-1}, entry i
     double pb = bs[i], pg = gs[i], ps = fwd ? fscs[i] : 0.0;
     bool ok = true;
 
     for (int j = 0; j < m; ++j) {
-        const float bf = (float)pb, gf = (float)pg;
+        const Tac bf = (Tac)pb, gf = (Tac)pg;
         const double sj = ps;
         if (j + 1 < m) {
             pb = bs[(j + 1) * M + i];
             pg = gs[(j + 1) * M + i];
             if (fwd) ps = fscs[(j + 1) * M + i];
         }
-        // C_j = T_j + diag(beta_j) (-C_{j-1}^{-1}) diag(beta_j); T_j has unit
-        // diagonal and gamma_j[c] at (c + 1, c) and (c, c + 1)
-        const float gl = __int_as_float(
-            __builtin_amdgcn_update_dpp(0, __float_as_int(gf), 0x111, 0xF, 0xF, false));  // gamma_j[i-1]
-        scale16_colbcast(a, bf);
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            float tv = (c == i + 1) ? gf : 0.0f;
-            tv = (c + 1 == i) ? gl : tv;
-            tv = (c == i) ? 1.0f : tv;
-            a[c] = fmaf(bf, a[c], tv);
-        }
+        const Tac gl = row_shr1(gf);  // gamma_j[i-1] (0 in lane 0)
+        form_schur16(a, bf, gf, gl, i);
         ok = sweep16_rows(a, i) && ok;
         // store -C_j^{-1}
         Tst *fb = fs + (size_t)j * 256;
-        float fr[16];
+        Tac fr[16];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             quad<Tst> qv;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                qv.v[c] = store_traits<Tst>::store(a[4 * g + c]);
-                fr[4 * g + c] = store_traits<Tst>::load(qv.v[c]);
+                qv.v[c] = store_traits<Tst>::store(a[drow<Tac>(g, c)]);
+                fr[drow<Tac>(g, c)] = store_traits<Tst>::load(qv.v[c]);
             }
             *(quad<Tst> *)(fb + (16 * g + i) * 4) = qv;
         }
         if (fwd) {
             // z_j = -F_j (s_j rhs - beta_j z_{j-1}) with F_j as stored
-            const float gv0 = (float)(sj * (i < m ? frhs : 0.0));
-            const float gv = j > 0 ? gv0 - bf * zc : gv0;
-            zc = -dot16_colbcast(fr, gv, 0.0f);
+            const Tac gv0 = (Tac)(sj * (i < m ? frhs : 0.0));
+            const Tac gv = j > 0 ? gv0 - bf * zc : gv0;
+            zc = -dot16_colbcast(fr, gv, (Tac)0);
             fzs[j * M + i] = (double)zc;
         }
     }
     if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
 }
+
+// Waves per SIMD the n = 16 refinement kernel is held to: four with FP32
+// arithmetic (128 registers), three in FP64, whose z, x and two factor rows
+// in flight take 124 registers by themselves.
+template <typename Tst> constexpr int ir_rows_waves() { return sizeof(typename store_traits<Tst>::acc) == 4 ? 4 : 3; }
 
 // Algorithm 2.1 on the n = 16 grid with the factor of k_factor_rows16: 16
 // lanes per sample (lane i owns the unknowns (i, j) of every grid row j and
@@ -735,9 +860,9 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
 // north face of the row before); the per-sample sums are fixed-order DPP
 // reductions.  A correction recomputes the residual row by row inside its
 // forward sweep instead of storing it.  Same arguments and outputs as
-// k_ir_blk at M = 16, with the sample count S first.
+// k_ir_blk at M = 16, with the sample count S first; every factor type.
 template <typename Tst>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ir_rows16(int S, double fconst, const double *__restrict__ a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_waves<Tst>()))) void k_ir_rows16(int S, double fconst, const double *__restrict__ a,
                                                    const double *__restrict__ sc,
                                                    const double *__restrict__ beta,
                                                    const Tst *__restrict__ factor, double *__restrict__ x,
@@ -748,11 +873,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                    double *__restrict__ q, int32_t *__restrict__ iters,
                                                    int fwd_done)
 {
+    using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
     const int i = threadIdx.x & 15;
     const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
     // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
-    if (b >= (count ? *count : S)) return;
+    if (b >= S || (count && b >= *count)) return;
     const int s = idx ? idx[b] : b;
     const size_t vo = (size_t)s * m * M + i;
     const double *scs = sc + vo, *bs = beta + vo;
@@ -775,14 +901,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int g = 0; g < 4; ++g) dst[g] = *(const quad<Tst> *)(fb + g * 64);
     };
-    auto row_of = [&](const quad<Tst> (&src)[4], float (&f)[16]) {
+    auto row_of = [&](const quad<Tst> (&src)[4], Tac (&f)[16]) {
 #pragma unroll
         for (int g = 0; g < 4; ++g)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) f[4 * g + c] = store_traits<Tst>::load(src[g].v[c]);
+            for (int c = 0; c < 4; ++c) f[drow<Tac>(g, c)] = store_traits<Tst>::load(src[g].v[c]);
     };
 
-    float z[m];    // z_j, entry i
+    Tac z[m];      // z_j, entry i
     double xv[m];  // x_j, entry i
     // Every step uses operands loaded one step earlier and first requests the
     // next step's (loads complete in order, so a wait for a late request would
@@ -806,11 +932,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 bp[(j + 1) & 1] = bq[(j + 1) * M];
             }
             const double r = rj(j);
-            const float gv0 = (float)(scp[j & 1] * r);
-            const float gv = j > 0 ? gv0 - (float)bp[j & 1] * z[j - 1] : gv0;
-            float f[16];
+            const Tac gv0 = (Tac)(scp[j & 1] * r);
+            const Tac gv = j > 0 ? gv0 - (Tac)bp[j & 1] * z[j - 1] : gv0;
+            Tac f[16];
             row_of(fq[j & 1], f);
-            z[j] = -dot16_colbcast(f, gv, 0.0f);
+            z[j] = -dot16_colbcast(f, gv, (Tac)0);
             __builtin_amdgcn_sched_barrier(0);  // one grid row at a time: bounds the registers in flight
         }
     };
@@ -822,7 +948,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         ldq(m - 2, fq[(m - 2) & 1]);
         scp[(m - 2) & 1] = scq[(m - 2) * M];
         bp[(m - 2) & 1] = bq[(m - 1) * M];
-        float xc = z[m - 1];
+        Tac xc = z[m - 1];
         {
             const double d = scq[(m - 1) * M] * (double)xc;
             xv[m - 1] = accumulate ? xv[m - 1] + d : d;
@@ -835,10 +961,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 scp[(j - 1) & 1] = scq[(j - 1) * M];
                 bp[(j - 1) & 1] = bq[j * M];
             }
-            const float gv = (float)bp[j & 1] * xc;
-            float f[16];
+            const Tac gv = (Tac)bp[j & 1] * xc;
+            Tac f[16];
             row_of(fq[j & 1], f);
-            xc = z[j] + dot16_colbcast(f, gv, 0.0f);
+            xc = z[j] + dot16_colbcast(f, gv, (Tac)0);
             const double d = scp[j & 1] * (double)xc;
             xv[j] = accumulate ? xv[j] + d : d;
             xs[j * M] = xv[j];
@@ -882,7 +1008,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // initial solve
     if (fwd_done) {
 #pragma unroll
-        for (int j = 0; j < m; ++j) z[j] = (float)zbuf[vo + j * M];
+        for (int j = 0; j < m; ++j) z[j] = (Tac)zbuf[vo + j * M];
     } else {
         forward([&](int) { return in ? bval : 0.0; });
     }
@@ -1320,7 +1446,7 @@ hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const
               const int *count, int64_t slot_base, uint32_t *state, const double *fsc, double frhs,
               double *fz, hipStream_t st)
 {
-    if constexpr (M == 16 && sizeof(typename store_traits<Tst>::acc) == 4) {
+    if constexpr (M == 16) {
         if (nb == 0) return hipSuccess;
         hipLaunchKernelGGL((k_factor_rows16<Tst>), dim3((unsigned)((nb + 15) / 16)), dim3(256), 0, st, nb, beta,
                            gam, (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
@@ -1362,15 +1488,13 @@ hipError_t li_g(const ir_args &g, hipStream_t st)
 template <typename Tst, int M>
 hipError_t li(const ir_args &g, hipStream_t st)
 {
-    if constexpr (M == 16 && sizeof(typename store_traits<Tst>::acc) == 4) {
+    if constexpr (M == 16) {
         if (g.nblocks == 0) return hipSuccess;
         hipLaunchKernelGGL((k_ir_rows16<Tst>), dim3((unsigned)((g.nblocks + 15) / 16)), dim3(256), 0, st,
                            g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
                            g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
                            g.fwd_done);
         return hipGetLastError();
-    } else if constexpr (M == 16) {
-        return li_g<Tst, M, 1>(g, st);
     } else {
         int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
         return G == 2 ? li_g<Tst, M, 2>(g, st) : li_g<Tst, M, 1>(g, st);
@@ -1445,7 +1569,7 @@ hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, 
 
 bool factor_fuses_forward(int dtype, int n)
 {
-    return use_blk(dtype, n) && dtype != 0;
+    return use_blk(dtype, n) && (dtype != 0 || n == 16);
 }
 
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st)

@@ -17,14 +17,12 @@ enum : uint32_t {
     ST_DONE = 1u << 31,  // no further refinement work for this sample
 };
 
-// Whether grid n with factor dtype (mlmc_dtype code) uses the MFMA
-// block-layout factor and solves (else the register-tile kernels): every grid
-// for the low-precision factors, from 64 cells per side for FP64 (where the
-// tile kernels are faster below).
-#ifndef MLMC_BLK_LOWP_MIN
-#define MLMC_BLK_LOWP_MIN 16
-#endif
-inline bool use_blk(int dtype, int n) { return n >= (dtype == 0 ? 64 : MLMC_BLK_LOWP_MIN); }
+// Whether grid n with factor dtype (mlmc_dtype code) uses the block-layout
+// factor and solves (else the register-tile kernels): from n = 16 for the
+// low-precision factors; for FP64 the n = 16 grid (one-row-per-lane kernels)
+// and n >= 64 (MFMA kernels), the tile kernels being faster at n = 32.  The
+// grids below 16 keep the tile kernels.
+inline bool use_blk(int dtype, int n) { return n == 16 || n >= (dtype == 0 ? 64 : 16); }
 
 size_t factor_entries_per_sample(int dtype, int n);
 
