@@ -1,6 +1,7 @@
-// Blocked symmetric-sweep factorisation on MFMA and the matching block solve
-// (M = n, the padded block size: every grid for the FP32/BF16/FP16 factors,
-// n >= 64 for the FP64 factor).
+// Block-layout factorisations and refinement (M = n, the padded block size):
+// the MFMA kernels for M >= 32 (every such grid for the FP32/BF16/FP16
+// factors, n >= 64 for the FP64 factor), and one-row-per-lane kernels for
+// the n = 16 grid (every factor type), further below.
 //
 // Each Schur complement C_j (M x M, SPD) is inverted in place by the sweep
 // operator applied to 16-pivot panels: with V = C[:, K] (the panel columns,
@@ -342,93 +343,82 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (NB == 1 && drow<Tac>(1, 0) == 4) {
-            // a single 16 x 16 block in FP32: its result layout (register r of lane
-            // row lr holds C[4 lr + r][lc]) is, by symmetry, the sweep layout
-            Tac p[4];
+        for (int K = 0; K < NB; ++K) {
+            int wk = w;
+            asm volatile("" : "+s"(wk));
+            Tac *V = Vb[K & 1];
+            // publish the panel columns C[:, K]
 #pragma unroll
-            for (int r = 0; r < 4; ++r) p[r] = acc[0][r];
-            okw = sweep16(p, l) && okw;
+            for (int q = 0; q < SPW; ++q) {
+                int I, J;
+                slot_blk<NB, 1>(wk, q, I, J);
+                if (J == K) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[0][r] = p[r];
-        } else {
-            for (int K = 0; K < NB; ++K) {
-                int wk = w;
-                asm volatile("" : "+s"(wk));
-                Tac *V = Vb[K & 1];
-                // publish the panel columns C[:, K]
+                    for (int r = 0; r < 4; ++r) V[(16 * I + drow<Tac>(lr, r)) * LD + lc] = acc[q][r];
+                } else if (I == K) {
 #pragma unroll
-                for (int q = 0; q < SPW; ++q) {
-                    int I, J;
-                    slot_blk<NB, 1>(wk, q, I, J);
-                    if (J == K) {
+                    for (int r = 0; r < 4; ++r) V[(16 * J + lc) * LD + drow<Tac>(lr, r)] = acc[q][r];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            asm volatile("" : "+s"(wk));
+            // every wave: -P^{-1} (redundantly), then U for its two block rows
+            Tac *P = Pw[wk];
+            {
+                Tac p[4];  // lane 16 g + i: P[i][4g .. 4g+3]
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) V[(16 * I + drow<Tac>(lr, r)) * LD + lc] = acc[q][r];
-                    } else if (I == K) {
+                for (int c = 0; c < 4; ++c) p[c] = V[(16 * K + lc) * LD + 4 * lr + c];
+                okw = sweep16(p, l) && okw;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) V[(16 * J + lc) * LD + drow<Tac>(lr, r)] = acc[q][r];
+                for (int c = 0; c < 4; ++c) P[lc * LD + 4 * lr + c] = p[c];
+            }
+            wave_lds_sync();
+            // -P^{-1}[4kc+lr][lc] (= [lc][4kc+lr] by symmetry) is the B operand of U and
+            // the A operand of row K; U rows are re-read in the A layout per block below
+            // (operands are re-read from LDS rather than held, to bound registers).
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int row = x ? NB - 1 - wk : wk;
+                V4 u = V4{0, 0, 0, 0};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+                    u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Uw[wk][x][drow<Tac>(lr, r) * LD + lc] = u[r];
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int q = 0; q < SPW; ++q) {
+                int I, J;
+                slot_blk<NB, 1>(wk, q, I, J);
+                const Tac *U = Uw[wk][(q <= wk) ? 0 : 1];  // which of the wave's two rows
+                if (I != K && J != K) {
+                    // C[I,J] += U_I V_J^T
+                    Tac av[4], bv[4];
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) {
+                        av[kc] = U[lc * LD + 4 * kc + lr];
+                        bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
                     }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                __syncthreads();
-                asm volatile("" : "+s"(wk));
-                // every wave: -P^{-1} (redundantly), then U for its two block rows
-                Tac *P = Pw[wk];
-                {
-                    Tac p[4];  // lane 16 g + i: P[i][4g .. 4g+3]
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) p[c] = V[(16 * K + lc) * LD + 4 * lr + c];
-                    okw = sweep16(p, l) && okw;
+                    for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
+                } else if (I == K && J == K) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) P[lc * LD + 4 * lr + c] = p[c];
-                }
-                wave_lds_sync();
-                // -P^{-1}[4kc+lr][lc] (= [lc][4kc+lr] by symmetry) is the B operand of U and
-                // the A operand of row K; U rows are re-read in the A layout per block below
-                // (operands are re-read from LDS rather than held, to bound registers).
+                    for (int r = 0; r < 4; ++r) acc[q][r] = P[drow<Tac>(lr, r) * LD + lc];
+                } else if (J == K) {
+                    // C[I,K] = V_I P^{-1} = -U_I
 #pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    const int row = x ? NB - 1 - wk : wk;
-                    V4 u = V4{0, 0, 0, 0};
+                    for (int r = 0; r < 4; ++r) acc[q][r] = -U[drow<Tac>(lr, r) * LD + lc];
+                } else {
+                    // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
+                    V4 z = V4{0, 0, 0, 0};
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc)
-                        u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) Uw[wk][x][drow<Tac>(lr, r) * LD + lc] = u[r];
+                        z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
+                    acc[q] = -z;
                 }
-                wave_lds_sync();
-#pragma unroll
-                for (int q = 0; q < SPW; ++q) {
-                    int I, J;
-                    slot_blk<NB, 1>(wk, q, I, J);
-                    const Tac *U = Uw[wk][(q <= wk) ? 0 : 1];  // which of the wave's two rows
-                    if (I != K && J != K) {
-                        // C[I,J] += U_I V_J^T
-                        Tac av[4], bv[4];
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) {
-                            av[kc] = U[lc * LD + 4 * kc + lr];
-                            bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
-                        }
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
-                    } else if (I == K && J == K) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[q][r] = P[drow<Tac>(lr, r) * LD + lc];
-                    } else if (J == K) {
-                        // C[I,K] = V_I P^{-1} = -U_I
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[q][r] = -U[drow<Tac>(lr, r) * LD + lc];
-                    } else {
-                        // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
-                        V4 z = V4{0, 0, 0, 0};
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc)
-                            z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
-                        acc[q] = -z;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // store -C_j^{-1}
@@ -770,7 +760,7 @@ __device__ inline float row_shr1(float v) { return dpp_f32<0x111>(v); }
 __device__ inline double row_shr1(double v) { return dpp_f64<0x111>(v); }
 
 // Factorisation of one sample per 16 lanes, 16 samples per workgroup; same
-// arguments and stored layout as k_factor_mfma at M = 16, and the forward
+// arguments as k_factor_mfma, its stored layout at M = 16, and the forward
 // sweep of the initial solve for every factor type.  The stored block keeps
 // the entry (row drow(g, c), column r) of MFMA lane l = 16 g + r at offset
 // l * 4 + c; by symmetry that is entry drow(g, c) of row r, so each lane
@@ -860,7 +850,7 @@ template <typename Tst> constexpr int ir_rows_waves() { return sizeof(typename s
 // north face of the row before); the per-sample sums are fixed-order DPP
 // reductions.  A correction recomputes the residual row by row inside its
 // forward sweep instead of storing it.  Same arguments and outputs as
-// k_ir_blk at M = 16, with the sample count S first; every factor type.
+// k_ir_blk, with the sample count S first; every factor type.
 template <typename Tst>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_waves<Tst>()))) void k_ir_rows16(int S, double fconst, const double *__restrict__ a,
                                                    const double *__restrict__ sc,
@@ -1294,25 +1284,6 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
     }
 }
 
-template <typename Tst, int M, int G, bool PREF>
-__global__ __launch_bounds__((64 * blk_waves<M, G>())) void k_solve_blk(const double *__restrict__ sc,
-                                                      const double *__restrict__ beta,
-                                                      const Tst *__restrict__ factor,
-                                                      const double *__restrict__ rhs,
-                                                      double rhs_const, double *__restrict__ x,
-                                                      int accumulate, double *__restrict__ zbuf,
-                                                      const int *__restrict__ idx,
-                                                      int64_t slot_base,
-                                                      const uint32_t *__restrict__ state)
-{
-    constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1;
-    const int b = blockIdx.x;
-    const int s = idx ? idx[b] : b;
-    if (state && (state[s] & ST_DONE)) return;
-    const size_t vo = (size_t)s * m * M;
-    solve_blk_pass<Tst, M, G, PREF>(sc + vo, beta + vo, factor + (size_t)(slot_base + b) * m * NBL * 256,
-                                    rhs ? rhs + vo : nullptr, rhs_const, x + vo, accumulate, zbuf + vo);
-}
 
 // Algorithm 2.1 for one sample per workgroup, after the factorisation:
 // x0 = S Ahat^{-1} S b, then {r = b - A x (FP64); stop test; x += solve(r)}.
@@ -1457,17 +1428,6 @@ hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const
     return hipGetLastError();
 }
 
-template <typename Tst, int M>
-hipError_t ls(int nb, const double *sc, const double *beta, const void *factor, const double *rhs,
-              double rc, double *x, int acc, double *zbuf, const int *idx, int64_t slot_base,
-              const uint32_t *state, hipStream_t st)
-{
-    constexpr int G = solve_cfg<Tst, M>::G;
-    constexpr bool PREF = solve_cfg<Tst, M>::PREF;
-    hipLaunchKernelGGL((k_solve_blk<Tst, M, G, PREF>), dim3(nb), dim3(64 * blk_waves<M, G>()), 0, st, sc, beta,
-                       (const Tst *)factor, rhs, rc, x, acc, zbuf, idx, slot_base, state);
-    return hipGetLastError();
-}
 
 // Refinement kernel variants: G waves per block-row pair (1 or 2); the FP64
 // n = 256 variant keeps no register double-buffer (register budget).
@@ -1529,20 +1489,6 @@ hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *fact
     return hipErrorInvalidValue;
 }
 
-template <typename Tst>
-hipError_t ls_m(int M, int nb, const double *sc, const double *beta, const void *factor,
-                const double *rhs, double rc, double *x, int acc, double *zbuf, const int *idx,
-                int64_t slot_base, const uint32_t *state, hipStream_t st)
-{
-    switch (M) {
-    case 16: return ls<Tst, 16>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 32: return ls<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 64: return ls<Tst, 64>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 128: return ls<Tst, 128>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 256: return ls<Tst, 256>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    }
-    return hipErrorInvalidValue;
-}
 }  // namespace
 
 hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double *phit, double *a,
@@ -1583,18 +1529,5 @@ hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_solve_blk(int dtype, int n, int nblocks, const double *sc, const double *beta,
-                            const void *factor, const double *rhs, double rhs_const, double *x,
-                            int accumulate, double *zbuf, const int *idx, int64_t slot_base,
-                            const uint32_t *state, hipStream_t st)
-{
-    switch (dtype) {
-    case 0: return ls_m<double>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    case 1: return ls_m<float>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    case 2: return ls_m<__hip_bfloat16>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    case 3: return ls_m<__half>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    }
-    return hipErrorInvalidValue;
-}
 
 }  // namespace mlmc

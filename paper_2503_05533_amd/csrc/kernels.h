@@ -65,22 +65,10 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, cons
 bool factor_fuses_forward(int dtype, int n);
 // Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample.
 hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
-hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const double *beta,
-                        const void *factor, const double *rhs, double rhs_const, double *x,
-                        int accumulate, double *zbuf, const int *idx, int64_t slot_base,
-                        const uint32_t *state, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
                              void *factor, const int *idx, const int *count, int64_t slot_base,
                              uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
-hipError_t launch_solve_blk(int dtype, int n, int nblocks, const double *sc, const double *beta,
-                            const void *factor, const double *rhs, double rhs_const, double *x,
-                            int accumulate, double *zbuf, const int *idx, int64_t slot_base,
-                            const uint32_t *state, hipStream_t st);
-hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, const double *x,
-                           double *r, double eps, int trip, int imax, int direct, const int *idx,
-                           uint32_t *state, double *relres, double *q, int32_t *iters,
-                           int *n_active, hipStream_t st);
 hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
                          const double *gam, const double *beta, double *x, double *r, double *vecs,
                          double eps, int maxit, uint32_t *state, double *relres, double *q,

@@ -405,24 +405,6 @@ __device__ inline void solve_tile_pass(const double *__restrict__ scs, const dou
     }
 }
 
-template <typename Tst, int M, int TR, int NT>
-__global__ __launch_bounds__(NT) void k_solve(const double *__restrict__ sc,
-                                              const double *__restrict__ beta,
-                                              const Tst *__restrict__ factor,
-                                              const double *__restrict__ rhs, double rhs_const,
-                                              double *__restrict__ x, int accumulate,
-                                              double *__restrict__ zbuf,
-                                              const int *__restrict__ idx, int64_t slot_base,
-                                              const uint32_t *__restrict__ state)
-{
-    constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR, m = M - 1;
-    const int b = blockIdx.x;
-    const int s = idx ? idx[b] : b;
-    if (state && (state[s] & ST_DONE)) return;
-    const size_t vo = (size_t)s * m * M;
-    solve_tile_pass<Tst, M, TR, NT>(sc + vo, beta + vo, factor + (size_t)(slot_base + b) * m * T * E,
-                                    rhs ? rhs + vo : nullptr, rhs_const, x + vo, accumulate, zbuf + vo);
-}
 
 // Algorithm 2.1 for one sample per workgroup (tile-layout factor): x0, then
 // {r = b - A x (FP64); stop test; x += solve(r)}; `direct`: residual only.
@@ -472,73 +454,6 @@ __global__ __launch_bounds__(NT) void k_ir_tile(
 
 // ------------------------------------------------------------------ residual
 
-// r = b - A x in FP64 from the nodal coefficient (matrix-free 5-point
-// stencil), ||r||/||b||, Q = h^2 sum x, and the refinement control of
-// Algorithm 2.1: converged when relres < eps (strict), otherwise flagged at
-// the trip limit, on a non-finite value, or when the residual stopped
-// decreasing (then the sample is a candidate for promotion).
-__global__ __launch_bounds__(256) void k_residual(int n, double h, double fconst,
-                                                  const double *__restrict__ a,
-                                                  const double *__restrict__ x,
-                                                  double *__restrict__ r, double eps, int trip,
-                                                  int imax, int direct,
-                                                  const int *__restrict__ idx,
-                                                  uint32_t *__restrict__ state,
-                                                  double *__restrict__ relres,
-                                                  double *__restrict__ q,
-                                                  int32_t *__restrict__ iters,
-                                                  int *__restrict__ n_active)
-{
-    __shared__ double red[256];
-    const int m = n - 1, M = n, np = n + 1;
-    const int s = idx ? idx[blockIdx.x] : blockIdx.x;
-    const uint32_t st0 = state[s];
-    if (st0 & ST_DONE) return;
-    const double *as = a + (size_t)s * np * np;
-    const double *xs = x + (size_t)s * m * M;
-    double *rsp = r ? r + (size_t)s * m * M : nullptr;
-    const double bval = h * h * fconst;
-    double rr = 0.0, bb = 0.0, sx = 0.0;
-    for (int e = threadIdx.x; e < m * M; e += 256) {
-        const int j = e / M, i = e % M;
-        if (i >= m) {
-            if (rsp) rsp[e] = 0.0;
-            continue;
-        }
-        const int p = (j + 1) * np + (i + 1);
-        const double c = as[p];
-        const double aw = hmean(c, as[p - 1]), ae = hmean(c, as[p + 1]);
-        const double asu = hmean(c, as[p - np]), an = hmean(c, as[p + np]);
-        const double xv = xs[e];
-        double ax = (aw + ae + asu + an) * xv;
-        if (i > 0) ax -= aw * xs[e - 1];
-        if (i + 1 < m) ax -= ae * xs[e + 1];
-        if (j > 0) ax -= asu * xs[e - M];
-        if (j + 1 < m) ax -= an * xs[e + M];
-        const double rv = bval - ax;
-        if (rsp) rsp[e] = rv;
-        rr += rv * rv;
-        bb += bval * bval;
-        sx += xv;
-    }
-    rr = block_sum<256>(rr, red);
-    bb = block_sum<256>(bb, red);
-    sx = block_sum<256>(sx, red);
-    if (threadIdx.x == 0) {
-        const double rel = sqrt(rr) / sqrt(bb);
-        const double prev = relres[s];
-        relres[s] = rel;
-        q[s] = h * h * sx;
-        if (iters) iters[s] = trip;
-        uint32_t st = st0;
-        if (!isfinite(rel) || !isfinite(sx)) st |= ST_NONFINITE | ST_DONE;
-        else if (direct || rel < eps) st |= ST_CONVERGED | ST_DONE;
-        else if (trip >= imax) st |= ST_IMAX | ST_DONE;
-        else if (trip > 0 && !(rel < prev)) st |= ST_STALL | ST_DONE;
-        state[s] = st;
-        if (!(st & ST_DONE) && n_active) atomicAdd(n_active, 1);
-    }
-}
 
 // dQ/dZ at every node for the adjoint gradient: with u and lambda the
 // (padded) primal and adjoint solutions (0 on the boundary),
@@ -731,18 +646,6 @@ hipError_t launch_ir_m(const ir_args &g, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
-template <typename Tst, int M>
-hipError_t launch_solve_t(int nblocks, const double *sc, const double *beta, const void *factor,
-                          const double *rhs, double rhs_const, double *x, int accumulate,
-                          double *zbuf, const int *idx, int64_t slot_base, const uint32_t *state,
-                          hipStream_t st)
-{
-    constexpr int TR = tile_cfg<M>::TR, NT = nthreads<Tst, M, TR>();
-    hipLaunchKernelGGL((k_solve<Tst, M, TR, NT>), dim3(nblocks), dim3(NT), 0, st, sc, beta,
-                       (const Tst *)factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base,
-                       state);
-    return hipGetLastError();
-}
 
 template <typename Tst>
 hipError_t launch_factor_m(int M, int nb, const double *beta, const double *gam, void *factor,
@@ -758,19 +661,6 @@ hipError_t launch_factor_m(int M, int nb, const double *beta, const double *gam,
     return hipErrorInvalidValue;
 }
 
-template <typename Tst>
-hipError_t launch_solve_m(int M, int nb, const double *sc, const double *beta, const void *factor,
-                          const double *rhs, double rc, double *x, int acc, double *zbuf,
-                          const int *idx, int64_t slot_base, const uint32_t *state, hipStream_t st)
-{
-    switch (M) {
-    case 4: return launch_solve_t<Tst, 4>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 8: return launch_solve_t<Tst, 8>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 16: return launch_solve_t<Tst, 16>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    case 32: return launch_solve_t<Tst, 32>(nb, sc, beta, factor, rhs, rc, x, acc, zbuf, idx, slot_base, state, st);
-    }
-    return hipErrorInvalidValue;
-}
 }  // namespace
 
 namespace mlmc {
@@ -853,34 +743,6 @@ hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_solve(int dtype, int n, int nblocks, const double *sc, const double *beta,
-                        const void *factor, const double *rhs, double rhs_const, double *x,
-                        int accumulate, double *zbuf, const int *idx, int64_t slot_base,
-                        const uint32_t *state, hipStream_t st)
-{
-    if (nblocks == 0) return hipSuccess;
-    if (use_blk(dtype, n))
-        return launch_solve_blk(dtype, n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate,
-                                zbuf, idx, slot_base, state, st);
-    switch (dtype) {
-    case 0: return launch_solve_m<double>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    case 1: return launch_solve_m<float>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    case 2: return launch_solve_m<__hip_bfloat16>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    case 3: return launch_solve_m<__half>(n, nblocks, sc, beta, factor, rhs, rhs_const, x, accumulate, zbuf, idx, slot_base, state, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_residual(int n, int nblocks, double fconst, const double *a, const double *x,
-                           double *r, double eps, int trip, int imax, int direct, const int *idx,
-                           uint32_t *state, double *relres, double *q, int32_t *iters,
-                           int *n_active, hipStream_t st)
-{
-    if (nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_residual, dim3(nblocks), dim3(256), 0, st, n, 1.0 / n, fconst, a, x, r, eps,
-                       trip, imax, direct, idx, state, relres, q, iters, n_active);
-    return hipGetLastError();
-}
 
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
                              double *gz, hipStream_t st)
