@@ -356,8 +356,9 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         HIPCHK(launch_zero_int(cnt, 1, st));
         HIPCHK(launch_collect(S, state, idx, cnt, st));
         HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
-        PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_beta), at<double>(ws, L.off_gam),
-                                     pf, idx, cnt, 0, state, nullptr, 0.0, nullptr, st));
+        PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_a), at<double>(ws, L.off_sc),
+                                     at<double>(ws, L.off_beta), at<double>(ws, L.off_gam), pf, idx, cnt, 0,
+                                     state, 0.0, nullptr, st));
         ir_args p = g;
         p.nblocks = np;
         p.factor = pf;
@@ -390,7 +391,8 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     uint32_t *state = at<uint32_t>(ws, L.off_state);
     double *relres = at<double>(ws, L.off_relres);
     PROF(0, n, S, launch_field(S, K, P, xi, ctx->phit[level], a, st));
-    PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, st));
+    // the n = 16 factorisation forms the scaled operator itself
+    if (o.solver == MLMC_MINRES || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, st));
     HIPCHK(launch_init_state(S, state, relres, st));
     if (o.solver == MLMC_MINRES) {
         PROF(5, n, S, launch_minres(n, S, ctx->cfg.f, a, sc, gam, beta, at<double>(ws, L.off_x),
@@ -404,8 +406,8 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     // the factorisation also runs the initial solve's forward sweep (rhs h^2 f)
     const bool fwd = factor_fuses_forward(dt, n);
     const double h = 1.0 / n;
-    PROF(2, n, S, launch_factor(dt, n, S, beta, gam, factor, nullptr, nullptr, 0, state, fwd ? sc : nullptr,
-                                h * h * ctx->cfg.f, fwd ? at<double>(ws, L.off_z) : nullptr, st));
+    PROF(2, n, S, launch_factor(dt, n, S, a, sc, beta, gam, factor, nullptr, nullptr, 0, state, h * h * ctx->cfg.f,
+                                fwd ? at<double>(ws, L.off_z) : nullptr, st));
     return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, at<double>(ws, L.off_x), q, iters, st, fwd);
 }
 

@@ -759,57 +759,90 @@ __device__ inline bool sweep16_rows(T a[16], int i)
 __device__ inline float row_shr1(float v) { return dpp_f32<0x111>(v); }
 __device__ inline double row_shr1(double v) { return dpp_f64<0x111>(v); }
 
-// Factorisation of one sample per 16 lanes, 16 samples per workgroup; same
-// arguments as k_factor_mfma, its stored layout at M = 16, and the forward
-// sweep of the initial solve for every factor type.  The stored block keeps
+// Factorisation of one sample per 16 lanes, 16 samples per workgroup: the
+// stored layout of k_factor_mfma at M = 16, and the forward sweep of the
+// initial solve for every factor type.  It reads the nodal coefficient a and
+// forms the scaled operator itself (the assembly pass is not run for this
+// grid), writing the scaling and the row couplings the refinement uses.  The stored block keeps
 // the entry (row drow(g, c), column r) of MFMA lane l = 16 g + r at offset
 // l * 4 + c; by symmetry that is entry drow(g, c) of row r, so each lane
 // stores four 4-entry vectors and the 16 lanes of a sample cover every
 // 256-entry block contiguously.  The solves read each lane's vectors back as
 // its row.
 template <typename Tst>
-__global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__restrict__ beta,
-                                                       const double *__restrict__ gam,
+__global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__restrict__ a,
+                                                       double *__restrict__ sc, double *__restrict__ beta,
                                                        Tst *__restrict__ factor,
                                                        const int *__restrict__ idx,
                                                        const int *__restrict__ count,
                                                        int64_t slot_base, uint32_t *__restrict__ state,
-                                                       const double *__restrict__ fsc, double frhs,
-                                                       double *__restrict__ fz)
+                                                       double frhs, double *__restrict__ fz)
 {
     using Tac = typename store_traits<Tst>::acc;
-    constexpr int M = 16, m = M - 1;
+    constexpr int M = 16, m = M - 1, NP = M + 1;
     const int i = threadIdx.x & 15;
     const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
     // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
     if (b >= S || (count && b >= *count)) return;
     const int s = idx ? idx[b] : b;
     const int64_t slot = slot_base + b;
-    const double *bs = beta + (size_t)s * m * M;
-    const double *gs = gam + (size_t)s * m * M;
+    const size_t vo = (size_t)s * m * M + i;
+    const double *ac = a + (size_t)s * NP * NP + (i + 1);  // node column i + 1
+    // the first pass over a batch writes the scaling and the row couplings for
+    // the refinement; a pass over promoted samples (idx) forms the same values
+    const bool wr = idx == nullptr;
+    double *scs = sc + vo, *bs = beta + vo;
     Tst *fs = factor + (size_t)slot * m * 256;
     const bool fwd = fz != nullptr;
-    const double *fscs = fwd ? fsc + (size_t)s * m * M : nullptr;
-    double *fzs = fwd ? fz + (size_t)s * m * M : nullptr;
+    double *fzs = fwd ? fz + vo : nullptr;
+    const bool in = i < m;  // lane m is the identity pad
 
-    Tac a[16];
+    Tac a16[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) a[c] = 0;
+    for (int c = 0; c < 16; ++c) a16[c] = 0;
     Tac zc = 0;  // z_{j-1}, entry i
-    double pb = bs[i], pg = gs[i], ps = fwd ? fscs[i] : 0.0;
+    // Scaled operator S A S of grid row j from the nodal coefficient, with the
+    // assembly's operations in its order: the four face coefficients (the east
+    // face is the next lane's west face, the south face the row before's
+    // north face), s = 1/sqrt(their sum), gamma to the east neighbour and
+    // beta to the row below; 0 in the pad.  Row j + 1's values are formed
+    // while row j is swept (independent work for the sweep's latency gaps),
+    // and the nodes they need were requested one row before that.
+    double c = ac[NP], cN = ac[2 * NP], w = ac[NP - 1];
+    double aS = hmean2(c, ac[0]), sS = 0.0;
+    auto coeffs = [&](int j, double &sj, double &bj, double &gj) {
+        double cNN = 0.0, wN = 0.0;
+        if (j + 1 < m) {
+            cNN = ac[(j + 3) * NP];
+            wN = ac[(j + 2) * NP - 1];
+        }
+        const double aw = hmean2(c, w), an = hmean2(c, cN);
+        const double ae = dpp_f64<0x101>(aw);
+        sj = in ? 1.0 / sqrt(aw + ae + aS + an) : 0.0;
+        const double sE = dpp_f64<0x101>(sj);
+        gj = (i + 1 < m) ? -ae * sj * sE : 0.0;
+        bj = (in && j > 0) ? -aS * sj * sS : 0.0;
+        if (wr) {
+            scs[j * M] = sj;
+            bs[j * M] = bj;
+        }
+        aS = an;
+        sS = sj;
+        c = cN;
+        cN = cNN;
+        w = wN;
+    };
+    double sjn, bjn, gjn;
+    coeffs(0, sjn, bjn, gjn);
     bool ok = true;
 
     for (int j = 0; j < m; ++j) {
-        const Tac bf = (Tac)pb, gf = (Tac)pg;
-        const double sj = ps;
-        if (j + 1 < m) {
-            pb = bs[(j + 1) * M + i];
-            pg = gs[(j + 1) * M + i];
-            if (fwd) ps = fscs[(j + 1) * M + i];
-        }
+        const double sj = sjn, bj = bjn, gj = gjn;
+        if (j + 1 < m) coeffs(j + 1, sjn, bjn, gjn);
+        const Tac bf = (Tac)bj, gf = (Tac)gj;
         const Tac gl = row_shr1(gf);  // gamma_j[i-1] (0 in lane 0)
-        form_schur16(a, bf, gf, gl, i);
-        ok = sweep16_rows(a, i) && ok;
+        form_schur16(a16, bf, gf, gl, i);
+        ok = sweep16_rows(a16, i) && ok;
         // store -C_j^{-1}
         Tst *fb = fs + (size_t)j * 256;
         Tac fr[16];
@@ -817,18 +850,18 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
         for (int g = 0; g < 4; ++g) {
             quad<Tst> qv;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                qv.v[c] = store_traits<Tst>::store(a[drow<Tac>(g, c)]);
-                fr[drow<Tac>(g, c)] = store_traits<Tst>::load(qv.v[c]);
+            for (int cc = 0; cc < 4; ++cc) {
+                qv.v[cc] = store_traits<Tst>::store(a16[drow<Tac>(g, cc)]);
+                fr[drow<Tac>(g, cc)] = store_traits<Tst>::load(qv.v[cc]);
             }
             *(quad<Tst> *)(fb + (16 * g + i) * 4) = qv;
         }
         if (fwd) {
             // z_j = -F_j (s_j rhs - beta_j z_{j-1}) with F_j as stored
-            const Tac gv0 = (Tac)(sj * (i < m ? frhs : 0.0));
+            const Tac gv0 = (Tac)(sj * (in ? frhs : 0.0));
             const Tac gv = j > 0 ? gv0 - bf * zc : gv0;
             zc = -dot16_colbcast(fr, gv, (Tac)0);
-            fzs[j * M + i] = (double)zc;
+            fzs[j * M] = (double)zc;
         }
     }
     if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
@@ -1413,17 +1446,17 @@ template <> struct solve_cfg<double, 128> { static constexpr int G = 2; static c
 template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static constexpr bool PREF = false; };
 
 template <typename Tst, int M>
-hipError_t lf(int nb, const double *beta, const double *gam, void *factor, const int *idx,
-              const int *count, int64_t slot_base, uint32_t *state, const double *fsc, double frhs,
+hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
+              const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
               double *fz, hipStream_t st)
 {
     if constexpr (M == 16) {
         if (nb == 0) return hipSuccess;
-        hipLaunchKernelGGL((k_factor_rows16<Tst>), dim3((unsigned)((nb + 15) / 16)), dim3(256), 0, st, nb, beta,
-                           gam, (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
+        hipLaunchKernelGGL((k_factor_rows16<Tst>), dim3((unsigned)((nb + 15) / 16)), dim3(256), 0, st, nb, a,
+                           sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz);
     } else {
         hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
-                           (Tst *)factor, idx, count, slot_base, state, fsc, frhs, fz);
+                           (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
     }
     return hipGetLastError();
 }
@@ -1475,16 +1508,16 @@ hipError_t li_m(const ir_args &g, hipStream_t st)
 }
 
 template <typename Tst>
-hipError_t lf_m(int M, int nb, const double *beta, const double *gam, void *factor, const int *idx,
-                const int *count, int64_t slot_base, uint32_t *state, const double *fsc, double frhs,
+hipError_t lf_m(int M, int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
+                const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
                 double *fz, hipStream_t st)
 {
     switch (M) {
-    case 16: return lf<Tst, 16>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 32: return lf<Tst, 32>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 64: return lf<Tst, 64>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 128: return lf<Tst, 128>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 256: return lf<Tst, 256>(nb, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1500,15 +1533,15 @@ hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double
     return hipGetLastError();
 }
 
-hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                             void *factor, const int *idx, const int *count, int64_t slot_base,
-                             uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st)
+hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
+                             const double *gam, void *factor, const int *idx, const int *count,
+                             int64_t slot_base, uint32_t *state, double frhs, double *fz, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return lf_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 1: return lf_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 2: return lf_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
-    case 3: return lf_m<__half>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, fsc, frhs, fz, st);
+    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
     }
     return hipErrorInvalidValue;
 }

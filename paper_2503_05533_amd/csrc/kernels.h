@@ -56,18 +56,23 @@ hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double 
                             const double *gq, double *grad, hipStream_t st);
 hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
                          hipStream_t st);
-// With fz != NULL (and factor_fuses_forward), the factorisation also runs the
+// Factorisation of the scaled operator.  It reads the couplings beta, gam,
+// except where factor_forms_coeffs(n): there it reads the nodal coefficient a
+// and forms them itself, writing the scaling sc and beta for the refinement
+// (not in a pass over promoted samples, idx != NULL, which forms the same
+// values).  With fz != NULL (and factor_fuses_forward) it also runs the
 // forward sweep of the solve for the right-hand side frhs (constant, interior
-// unknowns) scaled by fsc, writing z to fz (the refinement's z buffer).
-hipError_t launch_factor(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                         void *factor, const int *idx, const int *count, int64_t slot_base,
-                         uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st);
+// unknowns) scaled by sc, writing z to fz (the refinement's z buffer).
+hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
+                         const double *gam, void *factor, const int *idx, const int *count,
+                         int64_t slot_base, uint32_t *state, double frhs, double *fz, hipStream_t st);
 bool factor_fuses_forward(int dtype, int n);
+inline bool factor_forms_coeffs(int n) { return n == 16; }
 // Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample.
 hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
-hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *beta, const double *gam,
-                             void *factor, const int *idx, const int *count, int64_t slot_base,
-                             uint32_t *state, const double *fsc, double frhs, double *fz, hipStream_t st);
+hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
+                             const double *gam, void *factor, const int *idx, const int *count,
+                             int64_t slot_base, uint32_t *state, double frhs, double *fz, hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
                          const double *gam, const double *beta, double *x, double *r, double *vecs,

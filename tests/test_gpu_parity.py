@@ -130,6 +130,23 @@ def test_fp64_edge_batches():
     ctx.close()
 
 
+@pytest.mark.parametrize("dtype,solver,tol", [("f64", "direct", 1e-12), ("f32", "direct_ir", 1e-9)])
+def test_n16_ragged_batches(dtype, solver, tol):
+    """The n = 16 kernels hold 16 samples per workgroup: batch sizes around
+    that (a partial last workgroup, a single sample) against the oracle."""
+    torch = _torch()
+    ctx = _ctx(n0=16, L_max=1, K=16, seed=6)
+    phi = _phi(16, 16, 1.0, 0.3)
+    for S in (1, 15, 16, 17, 33):
+        xi = si.splitmix64_normals(6, 0, 0, S, 16)
+        out = ctx.solve(0, torch.from_numpy(xi), dtype=dtype, solver=solver, eps=1e-11)
+        q = out["q"].cpu().numpy()
+        qref = oracle.solve_batch(16, phi, xi)
+        assert np.all(out["status"].cpu().numpy() & 1), S
+        assert np.all(np.abs(q - qref) <= tol * qref), (S, np.max(np.abs(q - qref) / qref))
+    ctx.close()
+
+
 def test_determinism_bitwise():
     torch = _torch()
     ctx = _ctx(n0=16, L_max=2, K=64, seed=9)
@@ -234,18 +251,22 @@ def test_initial_solve_residual(n, S):
     ctx.close()
 
 
-def test_promotion_rescues_unreachable_low_precision():
-    """eps below what a BF16 factor reaches in 2 corrections: promotion to FP64 converges."""
+@pytest.mark.parametrize("level,S", [(2, 20), (0, 37)])
+def test_promotion_rescues_unreachable_low_precision(level, S):
+    """eps below what a BF16 factor reaches in 2 corrections: promotion to FP64
+    converges (n = 64: the MFMA kernels; n = 16: the row kernels, with the
+    promoted samples addressed through the device-built index list)."""
     torch = _torch()
+    n = 16 << level
     ctx = _ctx(n0=16, L_max=2, K=128, sigma2=2.0, corr_len=0.1, ir_max_iter=2, seed=11)
-    xi = si.splitmix64_normals(11, 2, 0, 20, 128)
-    out = ctx.solve(2, torch.from_numpy(xi), dtype="bf16", solver="direct_ir", eps=1e-11,
+    xi = si.splitmix64_normals(11, level, 0, S, 128)
+    out = ctx.solve(level, torch.from_numpy(xi), dtype="bf16", solver="direct_ir", eps=1e-11,
                     promote=True)
     st = out["status"].cpu().numpy()
     assert np.all(st & 1)
     assert np.any(st & 2)
     q = out["q"].cpu().numpy()
-    qref = oracle.solve_batch(64, _phi(64, 128, 2.0, 0.1), xi)
+    qref = oracle.solve_batch(n, _phi(n, 128, 2.0, 0.1), xi)
     assert np.all(np.abs(q - qref) / qref < 1e-10)
     ctx.close()
 
