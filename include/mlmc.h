@@ -212,7 +212,10 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * MLMC_DIRECT/MLMC_MINRES).  mixed = 0 runs standard MLMC: every solve
  * uses eps = 0 targets replaced by the FP64 direct solve.  Each level
  * streams its chunks on one of the context's queue streams; one
- * synchronisation per round.  Device memory: a per-level chunk workspace
+ * synchronisation per round, and within a round the host waits for the
+ * finest level alone: when its samples make the level test add a level, that
+ * level's first n_init samples start in the same round (the decisions, N_l
+ * and results are those of starting them in the next round).  Device memory: a per-level chunk workspace
  * (8 GiB per level, up to 32 GiB for a level whose first n_init samples then
  * fit one chunk), allocated on the first call and kept by the context for
  * later calls (grown when a call needs more, freed by mlmc_destroy). */

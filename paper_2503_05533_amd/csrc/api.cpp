@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -1010,13 +1011,34 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     for (int round = 0; round < 200; ++round) {
         double eps[16];
         mlmc_accuracy_targets(ctx, L, eps);
+        // Algorithm 4.1 adds level L + 1 (with n_init samples) when |Y_L| is
+        // above the bias bound after a round.  That decision is known as soon as
+        // level L's samples of the round are in (at once if it has none to add):
+        // the new level's first samples then run in this round, beside the other
+        // levels' top-ups, with the accuracy targets of L + 1 levels.  The
+        // decisions and sums are those of running them in the next round.
+        auto next_level_due = [&](double s1L, int64_t doneL) {
+            return L < Lmax && doneL > 0 && std::fabs(s1L / (double)doneL) > bias_c;
+        };
+        double eps_next[16];
+        if (L < Lmax) mlmc_accuracy_targets(ctx, L + 1, eps_next);
+        struct job { int l; int64_t from, to; double ef, ec; };
+        const job next_job{L + 1, 0, n_init, mixed ? eps_next[L + 1] : 0.0, mixed ? eps_next[L] : 0.0};
+        const bool early = N[L] <= done[L] && next_level_due(s1[L], done[L]);
+        std::vector<job> jobs;
+        // finest first: issuing level 0's many chunks takes the host milliseconds
+        if (early) jobs.push_back(next_job);
+        for (int l = L; l >= 0; --l)
+            if (N[l] > done[l])
+                jobs.push_back({l, done[l], N[l], mixed ? eps[l] : 0.0, mixed && l > 0 ? eps[l - 1] : 0.0});
+        auto job_chunks = [&](const job &jb) { return (int)((jb.to - jb.from + chunk[jb.l] - 1) / chunk[jb.l]); };
         // top every level up to N_l
         auto round_enqueue = [&](std::vector<std::pair<int, int64_t>> &recs) -> int {
             int nchunks = 0;
-            for (int l = 0; l <= L; ++l)
-                if (N[l] > done[l]) nchunks += (int)((N[l] - done[l] + chunk[l] - 1) / chunk[l]);
+            for (const job &jb : jobs) nchunks += job_chunks(jb);
             if (nchunks == 0) return MLMC_OK;
-            if (int e = ensure_queues(ctx, 1 + kQueues)) return e;
+            if (!early && L < Lmax) nchunks += job_chunks(next_job);
+            if (int e = ensure_queues(ctx, 2 + kQueues)) return e;
             if (nchunks > hcap) {
                 if (hbuf) (void)hipHostFree(hbuf);
                 hbuf = nullptr;
@@ -1028,19 +1050,51 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
             HIPCHK(hipEventRecord(ctx->ev0, st));
             HIPCHK(hipEventRecord(fork, st));
             bool used[kQueues] = {};
-            for (int l = 0; l <= L; ++l) {
-                if (N[l] <= done[l]) continue;
-                const int q = l % kQueues;
+            // The first three context streams have hardware queues of their own
+            // (the fourth shares one): level 0 (the most chunks) and the finest
+            // level with work (the longest per-sample chain) take one each, the
+            // levels between share the rest.
+            const int top = jobs.front().l;
+            auto level_queue = [&](int l) { return l == 0 ? 0 : (l >= top ? 1 : 2 + (l & 1)); };
+            // Level L's decision is taken as soon as its samples are in: the host
+            // polls its stream between the chunks it issues for the other levels
+            // (and waits for it at the end of issuing).
+            const bool probe = !early && L < Lmax && top == L;
+            bool probed = false;
+            hipEvent_t evL = ctx->qevents[1 + kQueues];
+            std::function<int(const job &)> enqueue_job;
+            auto poll = [&](bool block) -> int {
+                if (!probe || probed) return MLMC_OK;
+                if (block) {
+                    HIPCHK(hipEventSynchronize(evL));
+                } else {
+                    const hipError_t q = hipEventQuery(evL);
+                    if (q == hipErrorNotReady) return MLMC_OK;
+                    HIPCHK(q);
+                }
+                probed = true;
+                double s1L = s1[L];
+                int64_t dL = done[L];
+                for (size_t k = 0; k < recs.size(); ++k)
+                    if (recs[k].first == L) {
+                        s1L += hbuf[8 * k];
+                        dL += recs[k].second;
+                    }
+                return next_level_due(s1L, dL) ? enqueue_job(next_job) : MLMC_OK;
+            };
+            enqueue_job = [&](const job &jb) -> int {
+                const int l = jb.l;
+                const int q = level_queue(l);
                 hipStream_t sl = ctx->qstreams[q];
                 if (!used[q]) HIPCHK(hipStreamWaitEvent(sl, fork, 0));
                 used[q] = true;
                 mlmc_level_opts o = lopt[l];
-                o.eps_fine = mixed ? eps[l] : 0.0;
-                o.eps_coarse = mixed && l > 0 ? eps[l - 1] : 0.0;
+                o.eps_fine = jb.ef;
+                o.eps_coarse = jb.ec;
                 void *wl = (char *)ws + ws_off[l];
                 double *xl = (double *)(xi + xi_off[l]);
-                for (int64_t d0 = done[l]; d0 < N[l]; d0 += chunk[l]) {
-                    const int64_t cnt = std::min<int64_t>(N[l] - d0, chunk[l]);
+                for (int64_t d0 = jb.from; d0 < jb.to; d0 += chunk[l]) {
+                    const int64_t cnt = std::min<int64_t>(jb.to - d0, chunk[l]);
                     if (int e = mlmc_fill_xi(ctx, l, d0, cnt, xl, sl)) return e;
                     const level_layout LLc = make_level_layout(c, l, cnt, o);
                     if (int e = level_enqueue(ctx, l, cnt, xl, o, wl, LLc, nullptr, nullptr, nullptr, nullptr, sl,
@@ -1049,8 +1103,15 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
                     HIPCHK(hipMemcpyAsync(hbuf + 8 * recs.size(), at<double>(wl, LLc.off_sums), 8 * sizeof(double),
                                           hipMemcpyDeviceToHost, sl));
                     recs.push_back({l, cnt});
+                    if (l < L)
+                        if (int e = poll(false)) return e;
                 }
-            }
+                if (probe && l == L) HIPCHK(hipEventRecord(evL, sl));
+                return MLMC_OK;
+            };
+            for (const job &jb : jobs)
+                if (int e = enqueue_job(jb)) return e;
+            if (int e = poll(true)) return e;
             for (int q = 0; q < kQueues; ++q) {
                 if (!used[q]) continue;
                 HIPCHK(hipEventRecord(ctx->qevents[1 + q], ctx->qstreams[q]));
@@ -1067,13 +1128,20 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         rc = round_enqueue(recs);
         if (rc < 0) break;
         rc = MLMC_OK;
+        int64_t next_done = 0;
+        double next_s1 = 0.0, next_s2 = 0.0;
         for (size_t k = 0; k < recs.size(); ++k) {
             const int l = recs[k].first;
+            if (l > L) {
+                next_s1 += hbuf[8 * k];
+                next_s2 += hbuf[8 * k + 1];
+                next_done += recs[k].second;
+                continue;
+            }
             s1[l] += hbuf[8 * k];
             s2[l] += hbuf[8 * k + 1];
             done[l] += recs[k].second;
         }
-        if (rc < 0) break;
         yhat.assign(L + 1, 0.0);
         var.assign(L + 1, 0.0);
         double tot = 0.0;
@@ -1087,9 +1155,9 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         if (std::fabs(yhat[L]) > bias_c && L < Lmax) {
             ++L;
             N.push_back(n_init);
-            done.push_back(0);
-            s1.push_back(0);
-            s2.push_back(0);
+            done.push_back(next_done);
+            s1.push_back(next_s1);
+            s2.push_back(next_s2);
             continue;
         }
         bool need_more = false;
