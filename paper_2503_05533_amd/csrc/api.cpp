@@ -1020,7 +1020,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         auto next_level_due = [&](double s1L, int64_t doneL) {
             return L < Lmax && doneL > 0 && std::fabs(s1L / (double)doneL) > bias_c;
         };
-        double eps_next[16];
+        double eps_next[16] = {};
         if (L < Lmax) mlmc_accuracy_targets(ctx, L + 1, eps_next);
         struct job { int l; int64_t from, to; double ef, ec; };
         const job next_job{L + 1, 0, n_init, mixed ? eps_next[L + 1] : 0.0, mixed ? eps_next[L] : 0.0};
