@@ -1,0 +1,54 @@
+// Host-only driver of the C ABI against the stub runtime: the multi-level
+// step (graph and eager, FP32 refinement and FP64 direct) with the four-level
+// workload shapes, three times each, then the adaptive estimator (mixed and
+// standard).  Run under AddressSanitizer by tests/test_host_logic.py.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+#include "mlmc.h"
+int main()
+{
+    mlmc_config c{};
+    c.n0 = 16; c.m = 2; c.L_max = 3; c.K = 64; c.sigma2 = 1.0; c.corr_len = 0.3; c.f = 1.0; c.k_p = 0.05;
+    c.alpha = 2; c.beta = 4; c.gamma = 4; c.ir_max_iter = 10; c.minres_max_iter = 5000; c.seed = 1001;
+    mlmc_ctx *ctx = nullptr;
+    int rc = mlmc_create(&c, &ctx);
+    printf("create rc=%d\n", rc);
+    int32_t lv[4] = {0, 1, 2, 3};
+    int64_t N[4] = {20000, 5000, 1250, 300};
+    for (int dt = 1; dt >= 0; --dt) {
+        mlmc_level_opts o[4];
+        double eps[16];
+        mlmc_accuracy_targets(ctx, 3, eps);
+        for (int i = 0; i < 4; ++i) {
+            o[i] = mlmc_level_opts{};
+            o[i].factor_dtype = (mlmc_dtype)dt;
+            o[i].solver = dt ? MLMC_DIRECT_IR : MLMC_DIRECT;
+            o[i].eps_fine = eps[i];
+            o[i].eps_coarse = i ? eps[i - 1] : 0.0;
+            o[i].promote = 1;
+        }
+        size_t nb = mlmc_levels_workspace_bytes(ctx, 4, lv, N, o);
+        printf("dt=%d ws %zu bytes\n", dt, nb);
+        // fake device pointers: the stub launchers never touch them
+        void *ws = (void *)(uintptr_t)0x100000000ull;
+        std::vector<double> xi0(1), y0(1);
+        const double *xi[4] = {xi0.data(), xi0.data(), xi0.data(), xi0.data()};
+        double *y[4] = {y0.data(), y0.data(), y0.data(), y0.data()};
+        for (int g = 1; g >= 0; --g)
+            for (int r = 0; r < 3; ++r) {
+                rc = mlmc_sample_levels(ctx, 4, lv, N, xi, o, ws, nb, y, nullptr, g, nullptr);
+                printf("dt=%d graph=%d rep=%d rc=%d %s\n", dt, g, r, rc, rc ? mlmc_last_error(ctx) : "");
+            }
+    }
+    {
+        mlmc_dtype dts[4] = {MLMC_F32, MLMC_F32, MLMC_F32, MLMC_F32};
+        mlmc_result res;
+        for (int mixed = 1; mixed >= 0; --mixed) {
+            rc = mlmc_estimate(ctx, 2e-5, 1000, dts, MLMC_DIRECT_IR, mixed, &res, nullptr);
+            printf("estimate mixed=%d rc=%d L=%d N0=%lld %s\n", mixed, rc, res.L, (long long)res.N[0], rc ? mlmc_last_error(ctx) : "");
+        }
+    }
+    mlmc_destroy(ctx);
+    return 0;
+}
