@@ -240,8 +240,9 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
 /* Kernel timing for measurement.  While enabled, the library brackets each
  * launch of the field, assembly, factor, solve and residual kernels with HIP
  * events on the caller's stream and records (kernel kind, grid n, samples).
- * mlmc_profile_read synchronises, and for kind (0 field, 1 assembly,
- * 2 factor, 3 refinement (initial solve + Algorithm 2.1 loop), 4 residual,
+ * mlmc_profile_read synchronises, and for kind (0 field, 1 assembly (none on
+ * the n = 16 grid, whose factorisation forms the scaled operator itself and
+ * counts under 2, except for MINRES), 2 factor, 3 refinement (initial solve + Algorithm 2.1 loop), 4 residual,
  * 5 MINRES, 6 FP64 re-factorisation of promoted samples, 7 FP64 refinement
  * of promoted samples; 6 and 7 launch over the promotion slots and exit at
  * once for slots beyond the device-side count) and grid n returns the
