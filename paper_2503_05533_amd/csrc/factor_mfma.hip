@@ -499,9 +499,10 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
 
 // ------------------------------------------------- single-block grids (M = 16)
 //
-// For M = 16 (FP32 arithmetic) every Schur block is one 16 x 16 tile, and a
-// wave factors four samples at once: lane l works on sample l / 16 and holds
-// row i = l % 16 of the current block in 16 registers (register c = column c).
+// For M = 16 every Schur block is one 16 x 16 tile, and a wave factors four
+// samples at once (FP32 arithmetic for the FP32/BF16/FP16 factors, FP64 for
+// the FP64 factor): lane l works on sample l / 16 and holds row i = l % 16 of
+// the current block in 16 registers (register c = column c).
 // Pivot row K is the value of register c in lane K of the same 16-lane row,
 // the DPP row-broadcast operand of one FMA per register; pivot column K is the
 // lane's own register K.  No LDS and no barrier: samples never share lanes.
@@ -763,8 +764,9 @@ __device__ inline double row_shr1(double v) { return dpp_f64<0x111>(v); }
 // stored layout of k_factor_mfma at M = 16, and the forward sweep of the
 // initial solve for every factor type.  It reads the nodal coefficient a and
 // forms the scaled operator itself (the assembly pass is not run for this
-// grid), writing the scaling and the row couplings the refinement uses.  The stored block keeps
-// the entry (row drow(g, c), column r) of MFMA lane l = 16 g + r at offset
+// grid), writing the scaling and the row couplings the refinement uses.  The
+// stored block keeps the entry (row drow(g, c), column r) of MFMA lane
+// l = 16 g + r at offset
 // l * 4 + c; by symmetry that is entry drow(g, c) of row r, so each lane
 // stores four 4-entry vectors and the 16 lanes of a sample cover every
 // 256-entry block contiguously.  The solves read each lane's vectors back as
@@ -882,19 +884,16 @@ template <typename Tst> constexpr int ir_rows_waves() { return sizeof(typename s
 // once (the east face is the west face of the next lane, the south face the
 // north face of the row before); the per-sample sums are fixed-order DPP
 // reductions.  A correction recomputes the residual row by row inside its
-// forward sweep instead of storing it.  Same arguments and outputs as
-// k_ir_blk, with the sample count S first; every factor type.
+// forward sweep instead of storing it.  The arguments and outputs of
+// k_ir_blk, with the sample count S in place of n and no residual buffer;
+// every factor type.
 template <typename Tst>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_waves<Tst>()))) void k_ir_rows16(int S, double fconst, const double *__restrict__ a,
-                                                   const double *__restrict__ sc,
-                                                   const double *__restrict__ beta,
-                                                   const Tst *__restrict__ factor, double *__restrict__ x,
-                                                   const double *__restrict__ zbuf, double eps, int imax,
-                                                   int direct, const int *__restrict__ idx,
-                                                   const int *__restrict__ count, int64_t slot_base,
-                                                   uint32_t *__restrict__ state, double *__restrict__ relres,
-                                                   double *__restrict__ q, int32_t *__restrict__ iters,
-                                                   int fwd_done)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_waves<Tst>()))) void k_ir_rows16(
+    int S, double fconst, const double *__restrict__ a, const double *__restrict__ sc,
+    const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
+    const double *__restrict__ zbuf, double eps, int imax, int direct, const int *__restrict__ idx,
+    const int *__restrict__ count, int64_t slot_base, uint32_t *__restrict__ state,
+    double *__restrict__ relres, double *__restrict__ q, int32_t *__restrict__ iters, int fwd_done)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
