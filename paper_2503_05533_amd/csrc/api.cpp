@@ -359,7 +359,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
         PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_a), at<double>(ws, L.off_sc),
                                      at<double>(ws, L.off_beta), at<double>(ws, L.off_gam), pf, idx, cnt, 0,
-                                     state, 0.0, nullptr, st));
+                                     state, 0.0, nullptr, nullptr, st));
         ir_args p = g;
         p.nblocks = np;
         p.factor = pf;
@@ -404,12 +404,15 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     const bool direct = o.solver == MLMC_DIRECT;
     const int dt = direct ? MLMC_F64 : o.factor_dtype;
     void *factor = at<void>(ws, L.off_factor);
-    // the factorisation also runs the initial solve's forward sweep (rhs h^2 f)
+    // the factorisation also runs the initial solve's forward sweep (rhs h^2 f),
+    // at n = 16 the whole initial solve
     const bool fwd = factor_fuses_forward(dt, n);
     const double h = 1.0 / n;
+    double *x = at<double>(ws, L.off_x);
     PROF(2, n, S, launch_factor(dt, n, S, a, sc, beta, gam, factor, nullptr, nullptr, 0, state, h * h * ctx->cfg.f,
-                                fwd ? at<double>(ws, L.off_z) : nullptr, st));
-    return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, at<double>(ws, L.off_x), q, iters, st, fwd);
+                                fwd ? at<double>(ws, L.off_z) : nullptr,
+                                fwd && factor_solves_initial(n) ? x : nullptr, st));
+    return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, x, q, iters, st, fwd);
 }
 
 

@@ -770,7 +770,9 @@ __device__ inline double row_shr1(double v) { return dpp_f64<0x111>(v); }
 // l * 4 + c; by symmetry that is entry drow(g, c) of row r, so each lane
 // stores four 4-entry vectors and the 16 lanes of a sample cover every
 // 256-entry block contiguously.  The solves read each lane's vectors back as
-// its row.
+// its row.  With x0 != NULL it also runs the back sweep of the initial solve
+// and writes x0 there (z goes to fz on the way), so the refinement starts
+// with the residual.
 template <typename Tst>
 __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__restrict__ a,
                                                        double *__restrict__ sc, double *__restrict__ beta,
@@ -778,7 +780,8 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
                                                        const int *__restrict__ idx,
                                                        const int *__restrict__ count,
                                                        int64_t slot_base, uint32_t *__restrict__ state,
-                                                       double frhs, double *__restrict__ fz)
+                                                       double frhs, double *__restrict__ fz,
+                                                       double *__restrict__ x0)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
@@ -864,6 +867,39 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
             const Tac gv = j > 0 ? gv0 - bf * zc : gv0;
             zc = -dot16_colbcast(fr, gv, (Tac)0);
             fzs[j * M] = (double)zc;
+        }
+    }
+    if (fwd && x0 && wr) {
+        // The back sweep of the initial solve, right after the factorisation, so
+        // that the refinement only forms the residual when no correction is
+        // needed: x_{m-1} = s z_{m-1}; x_j = s_j (z_j + F_j (beta_{j+1} x~_{j+1}))
+        // with the arithmetic of the refinement kernel's back sweep.  Every
+        // operand was stored by this lane above; each step requests the next
+        // step's first.
+        double *x0s = x0 + vo;
+        quad<Tst> fq[2][4];
+        double zp[2], sp[2], bp[2];
+        auto req = [&](int j) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) fq[j & 1][g] = *(const quad<Tst> *)(fs + (size_t)j * 256 + (16 * g + i) * 4);
+            zp[j & 1] = fzs[j * M];
+            sp[j & 1] = scs[j * M];
+            bp[j & 1] = bs[(j + 1) * M];
+        };
+        req(m - 2);
+        Tac xc = (Tac)fzs[(m - 1) * M];
+        x0s[(m - 1) * M] = scs[(m - 1) * M] * (double)xc;
+#pragma unroll
+        for (int j = m - 2; j >= 0; --j) {
+            if (j > 0) req(j - 1);
+            const Tac gv = (Tac)bp[j & 1] * xc;
+            Tac f[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) f[drow<Tac>(g, cc)] = store_traits<Tst>::load(fq[j & 1][g].v[cc]);
+            xc = (Tac)zp[j & 1] + dot16_colbcast(f, gv, (Tac)0);
+            x0s[j * M] = sp[j & 1] * (double)xc;
         }
     }
     if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
@@ -1027,14 +1063,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_wav
         return in ? bval - ax : 0.0;
     };
 
-    // initial solve
+    // initial solve (fwd_done: the factorisation ran it and x holds x0)
     if (fwd_done) {
 #pragma unroll
-        for (int j = 0; j < m; ++j) z[j] = (Tac)zbuf[vo + j * M];
+        for (int j = 0; j < m; ++j) xv[j] = xs[j * M];
     } else {
         forward([&](int) { return in ? bval : 0.0; });
+        back(false);
     }
-    back(false);
 
     uint32_t st = state[s] & ~(uint32_t)ST_DONE;
     double prev = INFINITY, rel = INFINITY, sx = 0.0;
@@ -1447,12 +1483,12 @@ template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static c
 template <typename Tst, int M>
 hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
               const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
-              double *fz, hipStream_t st)
+              double *fz, double *x0, hipStream_t st)
 {
     if constexpr (M == 16) {
         if (nb == 0) return hipSuccess;
         hipLaunchKernelGGL((k_factor_rows16<Tst>), dim3((unsigned)((nb + 15) / 16)), dim3(256), 0, st, nb, a,
-                           sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz);
+                           sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
     } else {
         hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
                            (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
@@ -1509,14 +1545,14 @@ hipError_t li_m(const ir_args &g, hipStream_t st)
 template <typename Tst>
 hipError_t lf_m(int M, int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
                 const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
-                double *fz, hipStream_t st)
+                double *fz, double *x0, hipStream_t st)
 {
     switch (M) {
-    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1534,13 +1570,14 @@ hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double
 
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,
-                             int64_t slot_base, uint32_t *state, double frhs, double *fz, hipStream_t st)
+                             int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
+                             hipStream_t st)
 {
     switch (dtype) {
-    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
-    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, st);
+    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
     }
     return hipErrorInvalidValue;
 }

@@ -62,17 +62,25 @@ hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam,
 // (not in a pass over promoted samples, idx != NULL, which forms the same
 // values).  With fz != NULL (and factor_fuses_forward) it also runs the
 // forward sweep of the solve for the right-hand side frhs (constant, interior
-// unknowns) scaled by sc, writing z to fz (the refinement's z buffer).
+// unknowns) scaled by sc, writing z to fz (the refinement's z buffer); where
+// factor_solves_initial(n), with x0 != NULL, the back sweep as well, writing
+// the initial solve to x0.
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                          const double *gam, void *factor, const int *idx, const int *count,
-                         int64_t slot_base, uint32_t *state, double frhs, double *fz, hipStream_t st);
+                         int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
+                         hipStream_t st);
 bool factor_fuses_forward(int dtype, int n);
 inline bool factor_forms_coeffs(int n) { return n == 16; }
-// Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample.
+inline bool factor_solves_initial(int n) { return n == 16; }
+// Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample
+// (16 samples per workgroup at n = 16).  fwd_done: the factorisation ran the
+// forward sweep (z in the z buffer), or at n = 16 the whole initial solve
+// (x0 in x).
 hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,
-                             int64_t slot_base, uint32_t *state, double frhs, double *fz, hipStream_t st);
+                             int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
+                             hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
                          const double *gam, const double *beta, double *x, double *r, double *vecs,

@@ -52,7 +52,7 @@ hipError_t launch_fill_xi(uint64_t, int, int64_t, int64_t, int, double *, hipStr
 hipError_t launch_field(int, int, int, const double *, const double *, double *, hipStream_t) ST()
 hipError_t launch_grad_gemm(int, int, int, const double *, const double *, const double *, double *, hipStream_t) ST()
 hipError_t launch_coeffs(int, int, const double *, double *, double *, double *, hipStream_t) ST()
-hipError_t launch_factor(int, int, int, const double *, double *, double *, const double *, void *, const int *, const int *, int64_t, uint32_t *, double, double *, hipStream_t) ST()
+hipError_t launch_factor(int, int, int, const double *, double *, double *, const double *, void *, const int *, const int *, int64_t, uint32_t *, double, double *, double *, hipStream_t) ST()
 bool factor_fuses_forward(int dtype, int n) { return use_blk(dtype, n) && (dtype != 0 || n == 16); }
 hipError_t launch_ir(int, const ir_args &, hipStream_t) ST()
 hipError_t launch_minres(int, int, double, const double *, const double *, const double *, const double *, double *, double *, double *, double, int, uint32_t *, double *, double *, int32_t *, hipStream_t) ST()
