@@ -773,7 +773,10 @@ __device__ inline double row_shr1(double v) { return dpp_f64<0x111>(v); }
 // its row.  With x0 != NULL it also runs the back sweep of the initial solve
 // and writes x0 there (z goes to fz on the way), so the refinement starts
 // with the residual.
-template <typename Tst>
+// STRIDE: a pass over promoted samples, launched with a capped grid (its
+// device-side count is usually zero); its workgroups step through the slots
+// by the grid.
+template <typename Tst, bool STRIDE>
 __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__restrict__ a,
                                                        double *__restrict__ sc, double *__restrict__ beta,
                                                        Tst *__restrict__ factor,
@@ -786,123 +789,125 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
     using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
     const int i = threadIdx.x & 15;
-    const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
-    // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
-    if (b >= S || (count && b >= *count)) return;
-    const int s = idx ? idx[b] : b;
-    const int64_t slot = slot_base + b;
-    const size_t vo = (size_t)s * m * M + i;
-    const double *ac = a + (size_t)s * NP * NP + (i + 1);  // node column i + 1
-    // the first pass over a batch writes the scaling and the row couplings for
-    // the refinement; a pass over promoted samples (idx) forms the same values
-    const bool wr = idx == nullptr;
-    double *scs = sc + vo, *bs = beta + vo;
-    Tst *fs = factor + (size_t)slot * m * 256;
-    const bool fwd = fz != nullptr;
-    double *fzs = fwd ? fz + vo : nullptr;
-    const bool in = i < m;  // lane m is the identity pad
+    for (int b = blockIdx.x * 16 + (threadIdx.x >> 4);; b += gridDim.x * 16) {
+        // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
+        if (b >= S || (count && b >= *count)) return;
+        const int s = idx ? idx[b] : b;
+        const int64_t slot = slot_base + b;
+        const size_t vo = (size_t)s * m * M + i;
+        const double *ac = a + (size_t)s * NP * NP + (i + 1);  // node column i + 1
+        // the first pass over a batch writes the scaling and the row couplings for
+        // the refinement; a pass over promoted samples (idx) forms the same values
+        const bool wr = idx == nullptr;
+        double *scs = sc + vo, *bs = beta + vo;
+        Tst *fs = factor + (size_t)slot * m * 256;
+        const bool fwd = fz != nullptr;
+        double *fzs = fwd ? fz + vo : nullptr;
+        const bool in = i < m;  // lane m is the identity pad
 
-    Tac a16[16];
+        Tac a16[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) a16[c] = 0;
-    Tac zc = 0;  // z_{j-1}, entry i
-    // Scaled operator S A S of grid row j from the nodal coefficient, with the
-    // assembly's operations in its order: the four face coefficients (the east
-    // face is the next lane's west face, the south face the row before's
-    // north face), s = 1/sqrt(their sum), gamma to the east neighbour and
-    // beta to the row below; 0 in the pad.  Row j + 1's values are formed
-    // while row j is swept (independent work for the sweep's latency gaps),
-    // and the nodes they need were requested one row before that.
-    double c = ac[NP], cN = ac[2 * NP], w = ac[NP - 1];
-    double aS = hmean2(c, ac[0]), sS = 0.0;
-    auto coeffs = [&](int j, double &sj, double &bj, double &gj) {
-        double cNN = 0.0, wN = 0.0;
-        if (j + 1 < m) {
-            cNN = ac[(j + 3) * NP];
-            wN = ac[(j + 2) * NP - 1];
-        }
-        const double aw = hmean2(c, w), an = hmean2(c, cN);
-        const double ae = dpp_f64<0x101>(aw);
-        sj = in ? 1.0 / sqrt(aw + ae + aS + an) : 0.0;
-        const double sE = dpp_f64<0x101>(sj);
-        gj = (i + 1 < m) ? -ae * sj * sE : 0.0;
-        bj = (in && j > 0) ? -aS * sj * sS : 0.0;
-        if (wr) {
-            scs[j * M] = sj;
-            bs[j * M] = bj;
-        }
-        aS = an;
-        sS = sj;
-        c = cN;
-        cN = cNN;
-        w = wN;
-    };
-    double sjn, bjn, gjn;
-    coeffs(0, sjn, bjn, gjn);
-    bool ok = true;
-
-    for (int j = 0; j < m; ++j) {
-        const double sj = sjn, bj = bjn, gj = gjn;
-        if (j + 1 < m) coeffs(j + 1, sjn, bjn, gjn);
-        const Tac bf = (Tac)bj, gf = (Tac)gj;
-        const Tac gl = row_shr1(gf);  // gamma_j[i-1] (0 in lane 0)
-        form_schur16(a16, bf, gf, gl, i);
-        ok = sweep16_rows(a16, i) && ok;
-        // store -C_j^{-1}
-        Tst *fb = fs + (size_t)j * 256;
-        Tac fr[16];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            quad<Tst> qv;
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-                qv.v[cc] = store_traits<Tst>::store(a16[drow<Tac>(g, cc)]);
-                fr[drow<Tac>(g, cc)] = store_traits<Tst>::load(qv.v[cc]);
+        for (int c = 0; c < 16; ++c) a16[c] = 0;
+        Tac zc = 0;  // z_{j-1}, entry i
+        // Scaled operator S A S of grid row j from the nodal coefficient, with the
+        // assembly's operations in its order: the four face coefficients (the east
+        // face is the next lane's west face, the south face the row before's
+        // north face), s = 1/sqrt(their sum), gamma to the east neighbour and
+        // beta to the row below; 0 in the pad.  Row j + 1's values are formed
+        // while row j is swept (independent work for the sweep's latency gaps),
+        // and the nodes they need were requested one row before that.
+        double c = ac[NP], cN = ac[2 * NP], w = ac[NP - 1];
+        double aS = hmean2(c, ac[0]), sS = 0.0;
+        auto coeffs = [&](int j, double &sj, double &bj, double &gj) {
+            double cNN = 0.0, wN = 0.0;
+            if (j + 1 < m) {
+                cNN = ac[(j + 3) * NP];
+                wN = ac[(j + 2) * NP - 1];
             }
-            *(quad<Tst> *)(fb + (16 * g + i) * 4) = qv;
-        }
-        if (fwd) {
-            // z_j = -F_j (s_j rhs - beta_j z_{j-1}) with F_j as stored
-            const Tac gv0 = (Tac)(sj * (in ? frhs : 0.0));
-            const Tac gv = j > 0 ? gv0 - bf * zc : gv0;
-            zc = -dot16_colbcast(fr, gv, (Tac)0);
-            fzs[j * M] = (double)zc;
-        }
-    }
-    if (fwd && x0 && wr) {
-        // The back sweep of the initial solve, right after the factorisation, so
-        // that the refinement only forms the residual when no correction is
-        // needed: x_{m-1} = s z_{m-1}; x_j = s_j (z_j + F_j (beta_{j+1} x~_{j+1}))
-        // with the arithmetic of the refinement kernel's back sweep.  Every
-        // operand was stored by this lane above; each step requests the next
-        // step's first.
-        double *x0s = x0 + vo;
-        quad<Tst> fq[2][4];
-        double zp[2], sp[2], bp[2];
-        auto req = [&](int j) {
-#pragma unroll
-            for (int g = 0; g < 4; ++g) fq[j & 1][g] = *(const quad<Tst> *)(fs + (size_t)j * 256 + (16 * g + i) * 4);
-            zp[j & 1] = fzs[j * M];
-            sp[j & 1] = scs[j * M];
-            bp[j & 1] = bs[(j + 1) * M];
+            const double aw = hmean2(c, w), an = hmean2(c, cN);
+            const double ae = dpp_f64<0x101>(aw);
+            sj = in ? 1.0 / sqrt(aw + ae + aS + an) : 0.0;
+            const double sE = dpp_f64<0x101>(sj);
+            gj = (i + 1 < m) ? -ae * sj * sE : 0.0;
+            bj = (in && j > 0) ? -aS * sj * sS : 0.0;
+            if (wr) {
+                scs[j * M] = sj;
+                bs[j * M] = bj;
+            }
+            aS = an;
+            sS = sj;
+            c = cN;
+            cN = cNN;
+            w = wN;
         };
-        req(m - 2);
-        Tac xc = (Tac)fzs[(m - 1) * M];
-        x0s[(m - 1) * M] = scs[(m - 1) * M] * (double)xc;
+        double sjn, bjn, gjn;
+        coeffs(0, sjn, bjn, gjn);
+        bool ok = true;
+
+        for (int j = 0; j < m; ++j) {
+            const double sj = sjn, bj = bjn, gj = gjn;
+            if (j + 1 < m) coeffs(j + 1, sjn, bjn, gjn);
+            const Tac bf = (Tac)bj, gf = (Tac)gj;
+            const Tac gl = row_shr1(gf);  // gamma_j[i-1] (0 in lane 0)
+            form_schur16(a16, bf, gf, gl, i);
+            ok = sweep16_rows(a16, i) && ok;
+            // store -C_j^{-1}
+            Tst *fb = fs + (size_t)j * 256;
+            Tac fr[16];
 #pragma unroll
-        for (int j = m - 2; j >= 0; --j) {
-            if (j > 0) req(j - 1);
-            const Tac gv = (Tac)bp[j & 1] * xc;
-            Tac f[16];
+            for (int g = 0; g < 4; ++g) {
+                quad<Tst> qv;
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-#pragma unroll
-                for (int cc = 0; cc < 4; ++cc) f[drow<Tac>(g, cc)] = store_traits<Tst>::load(fq[j & 1][g].v[cc]);
-            xc = (Tac)zp[j & 1] + dot16_colbcast(f, gv, (Tac)0);
-            x0s[j * M] = sp[j & 1] * (double)xc;
+                for (int cc = 0; cc < 4; ++cc) {
+                    qv.v[cc] = store_traits<Tst>::store(a16[drow<Tac>(g, cc)]);
+                    fr[drow<Tac>(g, cc)] = store_traits<Tst>::load(qv.v[cc]);
+                }
+                *(quad<Tst> *)(fb + (16 * g + i) * 4) = qv;
+            }
+            if (fwd) {
+                // z_j = -F_j (s_j rhs - beta_j z_{j-1}) with F_j as stored
+                const Tac gv0 = (Tac)(sj * (in ? frhs : 0.0));
+                const Tac gv = j > 0 ? gv0 - bf * zc : gv0;
+                zc = -dot16_colbcast(fr, gv, (Tac)0);
+                fzs[j * M] = (double)zc;
+            }
         }
+        if (fwd && x0 && wr) {
+            // The back sweep of the initial solve, right after the factorisation, so
+            // that the refinement only forms the residual when no correction is
+            // needed: x_{m-1} = s z_{m-1}; x_j = s_j (z_j + F_j (beta_{j+1} x~_{j+1}))
+            // with the arithmetic of the refinement kernel's back sweep.  Every
+            // operand was stored by this lane above; each step requests the next
+            // step's first.
+            double *x0s = x0 + vo;
+            quad<Tst> fq[2][4];
+            double zp[2], sp[2], bp[2];
+            auto req = [&](int j) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) fq[j & 1][g] = *(const quad<Tst> *)(fs + (size_t)j * 256 + (16 * g + i) * 4);
+                zp[j & 1] = fzs[j * M];
+                sp[j & 1] = scs[j * M];
+                bp[j & 1] = bs[(j + 1) * M];
+            };
+            req(m - 2);
+            Tac xc = (Tac)fzs[(m - 1) * M];
+            x0s[(m - 1) * M] = scs[(m - 1) * M] * (double)xc;
+#pragma unroll
+            for (int j = m - 2; j >= 0; --j) {
+                if (j > 0) req(j - 1);
+                const Tac gv = (Tac)bp[j & 1] * xc;
+                Tac f[16];
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) f[drow<Tac>(g, cc)] = store_traits<Tst>::load(fq[j & 1][g].v[cc]);
+                xc = (Tac)zp[j & 1] + dot16_colbcast(f, gv, (Tac)0);
+                x0s[j * M] = sp[j & 1] * (double)xc;
+            }
+        }
+        if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
+        if constexpr (!STRIDE) return;
     }
-    if (!ok && i == 0) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
 }
 
 // Waves per SIMD the n = 16 refinement kernel is held to: four with FP32
@@ -923,7 +928,7 @@ template <typename Tst> constexpr int ir_rows_waves() { return sizeof(typename s
 // forward sweep instead of storing it.  The arguments and outputs of
 // k_ir_blk, with the sample count S in place of n and no residual buffer;
 // every factor type.
-template <typename Tst>
+template <typename Tst, bool STRIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_waves<Tst>()))) void k_ir_rows16(
     int S, double fconst, const double *__restrict__ a, const double *__restrict__ sc,
     const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
@@ -934,179 +939,181 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_wav
     using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
     const int i = threadIdx.x & 15;
-    const int b = blockIdx.x * 16 + (threadIdx.x >> 4);
-    // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
-    if (b >= S || (count && b >= *count)) return;
-    const int s = idx ? idx[b] : b;
-    const size_t vo = (size_t)s * m * M + i;
-    const double *scs = sc + vo, *bs = beta + vo;
-    double *xs = x + vo;
-    const Tst *fs = factor + (size_t)(slot_base + b) * m * 256 + i * 4;  // row i: 4 entries at g * 64
-    const double *ac = a + (size_t)s * NP * NP + (i + 1);                // node column i + 1
-    const double h = 1.0 / M, bval = h * h * fconst;
-    const bool in = i < m;  // lane m is the identity pad
+    for (int b = blockIdx.x * 16 + (threadIdx.x >> 4);; b += gridDim.x * 16) {
+        // whole 16-lane rows leave together, so no DPP source lane of a live row is idle
+        if (b >= S || (count && b >= *count)) return;
+        const int s = idx ? idx[b] : b;
+        const size_t vo = (size_t)s * m * M + i;
+        const double *scs = sc + vo, *bs = beta + vo;
+        double *xs = x + vo;
+        const Tst *fs = factor + (size_t)(slot_base + b) * m * 256 + i * 4;  // row i: 4 entries at g * 64
+        const double *ac = a + (size_t)s * NP * NP + (i + 1);                // node column i + 1
+        const double h = 1.0 / M, bval = h * h * fconst;
+        const bool in = i < m;  // lane m is the identity pad
 
-    // Loads in the sweeps and residual passes take an offset the compiler cannot
-    // see through (opaque): without it, the addresses of all 60 factor loads and
-    // the loop-invariant coefficient loads of every row are hoisted out of the
-    // refinement loop and held in registers.
-    auto opaque = [](int v) {
-        asm volatile("" : "+v"(v));
-        return v;
-    };
-    auto ldq = [&](int j, quad<Tst> (&dst)[4]) {
-        const Tst *fb = fs + opaque(j * 256);
+        // Loads in the sweeps and residual passes take an offset the compiler cannot
+        // see through (opaque): without it, the addresses of all 60 factor loads and
+        // the loop-invariant coefficient loads of every row are hoisted out of the
+        // refinement loop and held in registers.
+        auto opaque = [](int v) {
+            asm volatile("" : "+v"(v));
+            return v;
+        };
+        auto ldq = [&](int j, quad<Tst> (&dst)[4]) {
+            const Tst *fb = fs + opaque(j * 256);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) dst[g] = *(const quad<Tst> *)(fb + g * 64);
-    };
-    auto row_of = [&](const quad<Tst> (&src)[4], Tac (&f)[16]) {
+            for (int g = 0; g < 4; ++g) dst[g] = *(const quad<Tst> *)(fb + g * 64);
+        };
+        auto row_of = [&](const quad<Tst> (&src)[4], Tac (&f)[16]) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+            for (int g = 0; g < 4; ++g)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) f[drow<Tac>(g, c)] = store_traits<Tst>::load(src[g].v[c]);
-    };
+                for (int c = 0; c < 4; ++c) f[drow<Tac>(g, c)] = store_traits<Tst>::load(src[g].v[c]);
+        };
 
-    Tac z[m];      // z_j, entry i
-    double xv[m];  // x_j, entry i
-    // Every step uses operands loaded one step earlier and first requests the
-    // next step's (loads complete in order, so a wait for a late request would
-    // also wait for the prefetch in front of it).
-    quad<Tst> fq[2][4];
-    double scp[2], bp[2];
+        Tac z[m];      // z_j, entry i
+        double xv[m];  // x_j, entry i
+        // Every step uses operands loaded one step earlier and first requests the
+        // next step's (loads complete in order, so a wait for a late request would
+        // also wait for the prefetch in front of it).
+        quad<Tst> fq[2][4];
+        double scp[2], bp[2];
 
-    // Forward sweep z_j = -F_j (s_j r_j - beta_j z_{j-1}); rj(j) gives r_j and
-    // runs before the step's arithmetic (it may issue loads of its own).
-    auto forward = [&](auto &&rj) {
-        const int o = opaque(0);
-        const double *scq = scs + o, *bq = bs + o;
-        ldq(0, fq[0]);
-        scp[0] = scq[0];
-        bp[0] = 0.0;
-#pragma unroll
-        for (int j = 0; j < m; ++j) {
-            if (j + 1 < m) {
-                ldq(j + 1, fq[(j + 1) & 1]);
-                scp[(j + 1) & 1] = scq[(j + 1) * M];
-                bp[(j + 1) & 1] = bq[(j + 1) * M];
-            }
-            const double r = rj(j);
-            const Tac gv0 = (Tac)(scp[j & 1] * r);
-            const Tac gv = j > 0 ? gv0 - (Tac)bp[j & 1] * z[j - 1] : gv0;
-            Tac f[16];
-            row_of(fq[j & 1], f);
-            z[j] = -dot16_colbcast(f, gv, (Tac)0);
-            __builtin_amdgcn_sched_barrier(0);  // one grid row at a time: bounds the registers in flight
-        }
-    };
-    // back: x_{m-1} = s z_{m-1}; x_j = s_j (z_j + F_j (beta_{j+1} x~_{j+1})),
-    // x~ the unscaled iterate; accumulate adds to x
-    auto back = [&](bool accumulate) {
-        const int o = opaque(0);
-        const double *scq = scs + o, *bq = bs + o;
-        ldq(m - 2, fq[(m - 2) & 1]);
-        scp[(m - 2) & 1] = scq[(m - 2) * M];
-        bp[(m - 2) & 1] = bq[(m - 1) * M];
-        Tac xc = z[m - 1];
-        {
-            const double d = scq[(m - 1) * M] * (double)xc;
-            xv[m - 1] = accumulate ? xv[m - 1] + d : d;
-            xs[(m - 1) * M] = xv[m - 1];
-        }
-#pragma unroll
-        for (int j = m - 2; j >= 0; --j) {
-            if (j > 0) {
-                ldq(j - 1, fq[(j - 1) & 1]);
-                scp[(j - 1) & 1] = scq[(j - 1) * M];
-                bp[(j - 1) & 1] = bq[j * M];
-            }
-            const Tac gv = (Tac)bp[j & 1] * xc;
-            Tac f[16];
-            row_of(fq[j & 1], f);
-            xc = z[j] + dot16_colbcast(f, gv, (Tac)0);
-            const double d = scp[j & 1] * (double)xc;
-            xv[j] = accumulate ? xv[j] + d : d;
-            xs[j * M] = xv[j];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    };
-    // Residual r = b - A x row by row (entry i; 0 on the pad): the object keeps
-    // the carried face and the prefetched node values of the next row.
-    struct resid_rows {
-        const double *ac;
-        double c, aS, cN, w;  // centre of row j, its south face, prefetched north and west nodes
-    };
-    auto resid_start = [&]() {
-        resid_rows R;
-        R.ac = ac + opaque(0);  // face coefficients are formed anew in every pass
-        R.c = R.ac[NP];
-        R.aS = hmean2(R.c, R.ac[0]);
-        R.cN = R.ac[2 * NP];
-        R.w = R.ac[NP - 1];
-        return R;
-    };
-    auto resid_row = [&](resid_rows &R, int j) {
-        const double cN = R.cN, w = R.w;
-        if (j + 1 < m) {
-            R.cN = R.ac[(j + 3) * NP];
-            R.w = R.ac[(j + 2) * NP - 1];
-        }
-        const double aw = hmean2(R.c, w), an = hmean2(R.c, cN);
-        const double ae = dpp_f64<0x101>(aw);  // the next lane's west face
-        const double xw = dpp_f64<0x111>(xv[j]), xe = dpp_f64<0x101>(xv[j]);
-        double ax = (aw + ae + R.aS + an) * xv[j];
-        ax -= i > 0 ? aw * xw : 0.0;
-        ax -= i + 1 < m ? ae * xe : 0.0;
-        if (j > 0) ax -= R.aS * xv[j - 1];
-        if (j + 1 < m) ax -= an * xv[j + 1];
-        R.c = cN;
-        R.aS = an;
-        return in ? bval - ax : 0.0;
-    };
-
-    // initial solve (fwd_done: the factorisation ran it and x holds x0)
-    if (fwd_done) {
-#pragma unroll
-        for (int j = 0; j < m; ++j) xv[j] = xs[j * M];
-    } else {
-        forward([&](int) { return in ? bval : 0.0; });
-        back(false);
-    }
-
-    uint32_t st = state[s] & ~(uint32_t)ST_DONE;
-    double prev = INFINITY, rel = INFINITY, sx = 0.0;
-    int trip = 0;
-    for (;;) {
-        double rr = 0.0, bb = 0.0, sxl = 0.0;
-        {
-            resid_rows R = resid_start();
+        // Forward sweep z_j = -F_j (s_j r_j - beta_j z_{j-1}); rj(j) gives r_j and
+        // runs before the step's arithmetic (it may issue loads of its own).
+        auto forward = [&](auto &&rj) {
+            const int o = opaque(0);
+            const double *scq = scs + o, *bq = bs + o;
+            ldq(0, fq[0]);
+            scp[0] = scq[0];
+            bp[0] = 0.0;
 #pragma unroll
             for (int j = 0; j < m; ++j) {
-                const double rv = resid_row(R, j);
-                rr += rv * rv;
-                bb += in ? bval * bval : 0.0;
-                sxl += in ? xv[j] : 0.0;
+                if (j + 1 < m) {
+                    ldq(j + 1, fq[(j + 1) & 1]);
+                    scp[(j + 1) & 1] = scq[(j + 1) * M];
+                    bp[(j + 1) & 1] = bq[(j + 1) * M];
+                }
+                const double r = rj(j);
+                const Tac gv0 = (Tac)(scp[j & 1] * r);
+                const Tac gv = j > 0 ? gv0 - (Tac)bp[j & 1] * z[j - 1] : gv0;
+                Tac f[16];
+                row_of(fq[j & 1], f);
+                z[j] = -dot16_colbcast(f, gv, (Tac)0);
+                __builtin_amdgcn_sched_barrier(0);  // one grid row at a time: bounds the registers in flight
+            }
+        };
+        // back: x_{m-1} = s z_{m-1}; x_j = s_j (z_j + F_j (beta_{j+1} x~_{j+1})),
+        // x~ the unscaled iterate; accumulate adds to x
+        auto back = [&](bool accumulate) {
+            const int o = opaque(0);
+            const double *scq = scs + o, *bq = bs + o;
+            ldq(m - 2, fq[(m - 2) & 1]);
+            scp[(m - 2) & 1] = scq[(m - 2) * M];
+            bp[(m - 2) & 1] = bq[(m - 1) * M];
+            Tac xc = z[m - 1];
+            {
+                const double d = scq[(m - 1) * M] * (double)xc;
+                xv[m - 1] = accumulate ? xv[m - 1] + d : d;
+                xs[(m - 1) * M] = xv[m - 1];
+            }
+#pragma unroll
+            for (int j = m - 2; j >= 0; --j) {
+                if (j > 0) {
+                    ldq(j - 1, fq[(j - 1) & 1]);
+                    scp[(j - 1) & 1] = scq[(j - 1) * M];
+                    bp[(j - 1) & 1] = bq[j * M];
+                }
+                const Tac gv = (Tac)bp[j & 1] * xc;
+                Tac f[16];
+                row_of(fq[j & 1], f);
+                xc = z[j] + dot16_colbcast(f, gv, (Tac)0);
+                const double d = scp[j & 1] * (double)xc;
+                xv[j] = accumulate ? xv[j] + d : d;
+                xs[j * M] = xv[j];
                 __builtin_amdgcn_sched_barrier(0);
             }
+        };
+        // Residual r = b - A x row by row (entry i; 0 on the pad): the object keeps
+        // the carried face and the prefetched node values of the next row.
+        struct resid_rows {
+            const double *ac;
+            double c, aS, cN, w;  // centre of row j, its south face, prefetched north and west nodes
+        };
+        auto resid_start = [&]() {
+            resid_rows R;
+            R.ac = ac + opaque(0);  // face coefficients are formed anew in every pass
+            R.c = R.ac[NP];
+            R.aS = hmean2(R.c, R.ac[0]);
+            R.cN = R.ac[2 * NP];
+            R.w = R.ac[NP - 1];
+            return R;
+        };
+        auto resid_row = [&](resid_rows &R, int j) {
+            const double cN = R.cN, w = R.w;
+            if (j + 1 < m) {
+                R.cN = R.ac[(j + 3) * NP];
+                R.w = R.ac[(j + 2) * NP - 1];
+            }
+            const double aw = hmean2(R.c, w), an = hmean2(R.c, cN);
+            const double ae = dpp_f64<0x101>(aw);  // the next lane's west face
+            const double xw = dpp_f64<0x111>(xv[j]), xe = dpp_f64<0x101>(xv[j]);
+            double ax = (aw + ae + R.aS + an) * xv[j];
+            ax -= i > 0 ? aw * xw : 0.0;
+            ax -= i + 1 < m ? ae * xe : 0.0;
+            if (j > 0) ax -= R.aS * xv[j - 1];
+            if (j + 1 < m) ax -= an * xv[j + 1];
+            R.c = cN;
+            R.aS = an;
+            return in ? bval - ax : 0.0;
+        };
+
+        // initial solve (fwd_done: the factorisation ran it and x holds x0)
+        if (fwd_done) {
+#pragma unroll
+            for (int j = 0; j < m; ++j) xv[j] = xs[j * M];
+        } else {
+            forward([&](int) { return in ? bval : 0.0; });
+            back(false);
         }
-        rr = rowbcast<15>(row16_total(rr));
-        bb = rowbcast<15>(row16_total(bb));
-        sx = rowbcast<15>(row16_total(sxl));
-        rel = sqrt(rr) / sqrt(bb);
-        st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
-        if (st & ST_DONE) break;
-        prev = rel;
-        {
-            resid_rows R = resid_start();
-            forward([&](int j) { return resid_row(R, j); });
+
+        uint32_t st = state[s] & ~(uint32_t)ST_DONE;
+        double prev = INFINITY, rel = INFINITY, sx = 0.0;
+        int trip = 0;
+        for (;;) {
+            double rr = 0.0, bb = 0.0, sxl = 0.0;
+            {
+                resid_rows R = resid_start();
+#pragma unroll
+                for (int j = 0; j < m; ++j) {
+                    const double rv = resid_row(R, j);
+                    rr += rv * rv;
+                    bb += in ? bval * bval : 0.0;
+                    sxl += in ? xv[j] : 0.0;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            rr = rowbcast<15>(row16_total(rr));
+            bb = rowbcast<15>(row16_total(bb));
+            sx = rowbcast<15>(row16_total(sxl));
+            rel = sqrt(rr) / sqrt(bb);
+            st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
+            if (st & ST_DONE) break;
+            prev = rel;
+            {
+                resid_rows R = resid_start();
+                forward([&](int j) { return resid_row(R, j); });
+            }
+            back(true);
+            ++trip;
         }
-        back(true);
-        ++trip;
-    }
-    if (i == 0) {
-        state[s] = st;
-        relres[s] = rel;
-        q[s] = h * h * sx;
-        if (iters) iters[s] = trip;
+        if (i == 0) {
+            state[s] = st;
+            relres[s] = rel;
+            q[s] = h * h * sx;
+            if (iters) iters[s] = trip;
+        }
+        if constexpr (!STRIDE) return;
     }
 }
 
@@ -1487,8 +1494,13 @@ hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *g
 {
     if constexpr (M == 16) {
         if (nb == 0) return hipSuccess;
-        hipLaunchKernelGGL((k_factor_rows16<Tst>), dim3((unsigned)((nb + 15) / 16)), dim3(256), 0, st, nb, a,
-                           sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
+        const unsigned grid = (unsigned)((nb + 15) / 16);
+        if (idx)
+            hipLaunchKernelGGL((k_factor_rows16<Tst, true>), dim3(grid < 1024 ? grid : 1024), dim3(256), 0, st, nb,
+                               a, sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
+        else
+            hipLaunchKernelGGL((k_factor_rows16<Tst, false>), dim3(grid), dim3(256), 0, st, nb, a, sc, beta,
+                               (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
     } else {
         hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
                            (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
@@ -1518,10 +1530,17 @@ hipError_t li(const ir_args &g, hipStream_t st)
 {
     if constexpr (M == 16) {
         if (g.nblocks == 0) return hipSuccess;
-        hipLaunchKernelGGL((k_ir_rows16<Tst>), dim3((unsigned)((g.nblocks + 15) / 16)), dim3(256), 0, st,
-                           g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
-                           g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
-                           g.fwd_done);
+        const unsigned grid = (unsigned)((g.nblocks + 15) / 16);
+        if (g.idx)
+            hipLaunchKernelGGL((k_ir_rows16<Tst, true>), dim3(grid < 1024 ? grid : 1024), dim3(256), 0, st,
+                               g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
+                               g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
+                               g.fwd_done);
+        else
+            hipLaunchKernelGGL((k_ir_rows16<Tst, false>), dim3(grid), dim3(256), 0, st,
+                               g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
+                               g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
+                               g.fwd_done);
         return hipGetLastError();
     } else {
         int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
