@@ -1422,9 +1422,10 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
 // (w / 2, w % 2) as 2 x 2 result tiles.  The contraction over the K modes
 // runs in chunks of 16; in slice kk of a chunk the lane row lr stands for
 // mode c0 + 4 lr + kk, so each lane reads four consecutive entries of a xi
-// row and four rows of Phi^T (coalesced over the 16 nodes of a lane row).
-// Modes beyond K contribute zero; rows and nodes beyond S and P are not
-// stored (their loads are clamped in bounds).
+// row (staged through LDS per chunk, read from global memory as whole
+// 16-mode rows) and four rows of Phi^T (coalesced over the 16 nodes of a
+// lane row).  Modes beyond K contribute zero; rows and nodes beyond S and P
+// are not stored (their loads are clamped in bounds).
 __global__ __launch_bounds__(256) void k_field_mfma(int S, int K, int P, const double *__restrict__ xi,
                                                     const double *__restrict__ phit,
                                                     double *__restrict__ a)
@@ -1442,7 +1443,20 @@ __global__ __launch_bounds__(256) void k_field_mfma(int S, int K, int P, const d
         rowc[q] = min(s0 + 16 * q + lc, S - 1);
         colc[q] = min(p0 + 16 * q + lc, P - 1);
     }
+    // xi[64 samples][16 modes] of the chunk, staged through LDS: the global
+    // reads are then 128-byte rows (16 consecutive modes of a sample) instead
+    // of one sample per lane
+    __shared__ double xs[64][17];
+    const int xr = t >> 2, xq = (t & 3) * 4;  // thread t stages sample row xr, modes xq .. xq + 3
+    const int xrow = min(blockIdx.y * 64 + xr, S - 1);
     for (int c0 = 0; c0 < K; c0 += 16) {
+        __syncthreads();  // the previous chunk's reads of xs are done
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = c0 + xq + e;
+            xs[xr][xq + e] = k < K ? xi[(size_t)xrow * K + k] : 0.0;
+        }
+        __syncthreads();
         double av[2][4], bv[2][4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -1451,9 +1465,8 @@ __global__ __launch_bounds__(256) void k_field_mfma(int S, int K, int P, const d
             const int kc = in ? k : K - 1;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const double x = xi[(size_t)rowc[q] * K + kc];
                 const double ph = phit[(size_t)kc * P + colc[q]];
-                av[q][kk] = in ? x : 0.0;
+                av[q][kk] = xs[32 * (w >> 1) + 16 * q + lc][4 * lr + kk];
                 bv[q][kk] = in ? ph : 0.0;
             }
         }
