@@ -223,9 +223,9 @@ def test_imax_zero_flags_samples():
 
 @pytest.mark.parametrize("n,S", [(16, 48), (32, 16), (64, 6), (128, 2)])
 def test_initial_solve_residual(n, S):
-    """Algorithm 2.1's initial solve alone (no correction): the factorisation
-    (with its fused forward sweep for the low-precision factors) and the back
-    sweep.  With the FP32 factor its relative residual is of the order of a
+    """Algorithm 2.1's initial solve alone (no correction): the forward and
+    back sweeps, wherever they run (fused into the factorisation: both at
+    n = 16, the forward one for the low-precision factors elsewhere).  With the FP32 factor its relative residual is of the order of a
     textbook FP32 band-Cholesky solve of the same systems (the oracle's; the
     block-inverse factor measures at 0.6-0.8 of it); with FP16 storage at
     n <= 32 and BF16 at n = 16 it is below 1/2, where refinement contracts."""
