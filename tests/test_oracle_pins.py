@@ -345,3 +345,142 @@ def test_adaptive_mpml_passes_deltas():
         assert df > 0
         if l > 0:
             assert dc == pytest.approx(math.sqrt(0.05) * h[l - 1] ** 2)
+
+
+# ------------------------------------------------------------- face rule
+
+def _face_case(name, n):
+    """Nodal coefficients of the hand-derived cases in golden/face_rule.txt."""
+    a = np.zeros((n + 1, n + 1))  # [iy, ix]
+    if name == "n2":
+        a[:, :] = 100.0
+        a[1, 1], a[1, 0], a[1, 2], a[0, 1], a[2, 1] = 1.0, 2.0, 3.0, 4.0, 6.0
+    elif name == "n3_checker":
+        iy, ix = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+        a = np.where((ix + iy) % 2 == 0, 1.0, 4.0)
+    elif name == "n3_xonly":
+        a[:, 0::2], a[:, 1::2] = 1.0, 4.0
+    elif name == "n3_yonly":
+        a[0::2, :], a[1::2, :] = 1.0, 4.0
+    return a.ravel()
+
+
+def test_face_rule_hand_derived():
+    """Harmonic-mean edge coefficients: Q on n = 2, 3 grids against exact
+    rationals derived by hand (golden/face_rule.txt).  An arithmetic or
+    geometric edge mean, an edge attached to the wrong node, horizontal and
+    vertical edges swapped, or a corner node entering the stencil each change
+    at least one of these values by more than 10%."""
+    rows = _rows("face_rule.txt")
+    assert len(rows) == 4
+    for name, n, num, den in rows:
+        n = int(n)
+        want = int(num) / int(den)
+        got = oracle.solve_batch(n, None, None, a_nodes=_face_case(name, n))[0]
+        assert got == pytest.approx(want, rel=1e-14), (name, got, want)
+
+
+# ------------------------------------------------------------- KL amplitude
+
+def _nystrom_cov_rank_k(n, lam, sigma2, K):
+    """Rank-K part of the covariance sigma^2 exp(-|dx|/lam) exp(-|dy|/lam)
+    on the (n+1)^2 grid nodes, from a trapezoid-weighted Nystrom
+    eigensolve of the 2D kernel itself (no 1D eigen-equation involved)."""
+    x = np.arange(n + 1) / n
+    wt = np.full(n + 1, 1.0 / n)
+    wt[0] = wt[-1] = 0.5 / n
+    X, Y = np.meshgrid(x, x)  # [iy, ix], node p = iy (n+1) + ix
+    xs, ys = X.ravel(), Y.ravel()
+    sw = np.sqrt(np.outer(wt, wt).ravel())
+    C = sigma2 * np.exp(-np.abs(xs[:, None] - xs[None, :]) / lam
+                        - np.abs(ys[:, None] - ys[None, :]) / lam)
+    ev, V = np.linalg.eigh(sw[:, None] * C * sw[None, :])
+    ev, V = ev[::-1][:K], V[:, ::-1][:, :K]
+    F = V / sw[:, None]
+    return (F * ev) @ F.T
+
+
+@pytest.mark.parametrize("lam,K", [(0.3, 64), (0.1, 30)])
+def test_kl_basis_covariance_vs_2d_nystrom(lam, K):
+    """Cov(Z_p, Z_q) = sum_k Phi[p,k] Phi[q,k] (xi iid N(0,1)) must be the
+    rank-K truncation of the kernel sigma^2 e^{-|dx|/lam} e^{-|dy|/lam}.
+    Checked against an independent 2D Nystrom eigensolve on the same nodes
+    (K chosen where the K-th and (K+1)-th eigenvalues differ, so the rank-K
+    part is unique), converging at second order in h.  sigma^2 = 2, so an
+    amplitude sigma^2 in place of sigma, or mu_i mu_j in place of
+    sqrt(mu_i mu_j), is off by more than 0.4 sigma^2."""
+    sigma2 = 2.0
+    errs = []
+    for n in (32, 48):
+        Phi = oracle.kl_basis(n, K, sigma2, lam)
+        R = Phi @ Phi.T
+        errs.append(np.max(np.abs(R - _nystrom_cov_rank_k(n, lam, sigma2, K))) / sigma2)
+        # a truncated Mercer sum never exceeds the full variance sigma^2
+        assert np.all(np.diag(R) <= sigma2 * (1 + 1e-12))
+    assert errs[1] < 0.015, errs
+    assert errs[0] / errs[1] > 1.8, errs  # (48/32)^2 = 2.25
+
+
+# ------------------------------------------------------------- xi generator
+
+def test_splitmix64_known_answers():
+    """The mixing function and the counter form against SplitMix64's
+    published outputs (golden/splitmix64_kat.txt)."""
+    from seeded_inputs.xi import splitmix64_outputs
+    rows = _rows("splitmix64_kat.txt")
+    assert len(rows) == 9
+    for seed, idx, out in rows:
+        got = splitmix64_outputs(int(seed), np.array([int(idx)], dtype=np.uint64))[0]
+        assert int(got) == int(out), (seed, idx, hex(int(got)))
+
+
+def test_normals_moments_and_distribution():
+    """2^20 draws of the xi generator: mean 0, variance 1, no skew or
+    excess kurtosis (each within 5 standard errors), Kolmogorov-Smirnov
+    against N(0,1), uncorrelated pair halves, and the pair radius^2
+    exponential with mean 2 (a Box-Muller step with a wrong factor, a
+    missing 2 pi, or one uniform used twice fails one of these)."""
+    import scipy.stats as ss
+    xi = si.splitmix64_normals(4242, 3, 0, 8192, 128)
+    v = xi.ravel()
+    N = v.size
+    assert np.all(np.isfinite(v))
+    assert abs(v.mean()) < 5 / math.sqrt(N)
+    assert abs(v.var() - 1) < 5 * math.sqrt(2 / N)
+    assert abs(ss.skew(v)) < 5 * math.sqrt(6 / N)
+    assert abs(ss.kurtosis(v)) < 5 * math.sqrt(24 / N)
+    assert ss.kstest(v, "norm").pvalue > 1e-4
+    c, s = xi[:, 0::2].ravel(), xi[:, 1::2].ravel()
+    assert abs(np.corrcoef(c, s)[0, 1]) < 5 / math.sqrt(c.size)
+    assert ss.kstest(c * c + s * s, "expon", args=(0, 2.0)).pvalue > 1e-4
+    # rows of different samples and levels are distinct streams
+    assert not np.allclose(si.splitmix64_normals(4242, 2, 0, 4, 8), xi[:4, :8])
+    assert not np.allclose(si.splitmix64_normals(4242, 3, 1, 4, 8), xi[:4, :8])
+
+
+# ------------------------------------------------------------- estimator
+
+def test_level_estimates_hand_values():
+    """Y-hat and s^2 with the 1/N normalisation of Sec. 4.1."""
+    yhat, s2 = oracle.level_estimates([1.0, 2.0, 3.0, 4.0])
+    assert yhat == 2.5 and s2 == 1.25
+    yhat, s2 = oracle.level_estimates([-3.0, 3.0])
+    assert yhat == 0.0 and s2 == 9.0
+
+
+def test_field_mirrors_with_mode_parity():
+    """phi_i(1 - x) = (-1)^(i+1) phi_i(x), so flipping xi_k of the modes whose
+    x-index i is even mirrors the field itself in x (and those with even
+    y-index j mirror it in y).  Pins that mode (i, j) puts phi_i on the x
+    coordinate and phi_j on y (Q alone cannot tell them apart)."""
+    n, K, lam = 16, 16, 0.3  # K = 16 splits a symmetric pair at the cut
+    Phi = oracle.kl_basis(n, K, 2.0, lam)
+    mi, mj = oracle.kl_modes(lam, K)
+    assert (mi != mj).any()
+    xi = si.splitmix64_normals(21, 0, 0, 2, K)
+    Z = (xi @ Phi.T).reshape(2, n + 1, n + 1)  # [s, iy, ix]
+    Zx = ((xi * np.where(mi % 2 == 0, -1.0, 1.0)) @ Phi.T).reshape(2, n + 1, n + 1)
+    Zy = ((xi * np.where(mj % 2 == 0, -1.0, 1.0)) @ Phi.T).reshape(2, n + 1, n + 1)
+    assert np.allclose(Zx, Z[:, :, ::-1], atol=1e-12)
+    assert np.allclose(Zy, Z[:, ::-1, :], atol=1e-12)
+    assert not np.allclose(Zx, Z[:, ::-1, :], atol=1e-3)
