@@ -15,7 +15,9 @@
  *
  * Conventions for every entry point:
  *   - All *_dev pointers are device pointers owned by the caller, contiguous
- *     and row-major, at least 8-byte aligned (the workspace: 256-byte aligned).
+ *     and row-major, aligned to their element size (8 bytes for double,
+ *     4 for int32; the workspace: 256 bytes); a misaligned pointer is
+ *     rejected with MLMC_EINVAL.
  *     The library never frees caller memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is enqueued asynchronously on it unless stated otherwise.
@@ -50,7 +52,11 @@ extern "C" {
 
 typedef struct mlmc_ctx mlmc_ctx;
 
-/* Storage/arithmetic precision u_f of the factor (Algorithm 2.1, Sec. 2.3). */
+/* Storage precision u_f of the factor (Algorithm 2.1, Sec. 2.3).  The
+ * factorisation and the correction solves run in FP32 arithmetic for every
+ * low-precision type (FP64 for MLMC_F64): BF16 and FP16 round the stored
+ * factor, not the arithmetic that forms it, so their u_f is the storage
+ * unit roundoff (the paper's half-precision factor computes in half). */
 typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3 } mlmc_dtype;
 
 /* Linear solver of one sample:
@@ -75,7 +81,10 @@ typedef struct {
     double corr_len;         /* correlation length lambda of exp(-|x-y|/lambda) */
     double f;                /* constant right-hand side */
     double k_p;              /* accuracy constant of Sec. 4.3 (0.05) */
-    double alpha, beta, gamma; /* MLMC rates (2, 4, cost exponent) */
+    double alpha, beta, gamma; /* MLMC rates: bias O(h^alpha), variance O(h^beta)
+                                * (2, 4 for this problem), cost per grid
+                                * (n-1)^gamma in the estimator's cost model
+                                * (4: the factorisation's flops) */
     int32_t ir_max_iter;     /* Algorithm 2.1 i_max (10) */
     int32_t minres_max_iter; /* MINRES iteration cap (e.g. 5000) */
     uint64_t seed;           /* seed of the counter-based xi generator */
@@ -108,6 +117,9 @@ typedef struct {
     double Yhat[16], s2[16], C[16], eps[16];
     double wall_s;     /* host wall time of the call */
     double gpu_ms;     /* sum of device times of the level calls */
+    int64_t n_promoted[16]; /* samples per level re-solved with an FP64 factor */
+    int64_t n_noconv[16];   /* samples per level that missed their target (any
+                             * non-zero entry ends the call with MLMC_ENOCONV) */
 } mlmc_result;
 
 /* Create a context: solves the KL eigen-equation on the host, builds Phi_l
@@ -121,8 +133,13 @@ const char *mlmc_last_error(const mlmc_ctx *ctx);
 /* Cells per side of level `level`, or -1. */
 int32_t mlmc_level_cells(const mlmc_ctx *ctx, int32_t level);
 
-/* delta_0..delta_L of the accuracy rule of Sec. 4.5 (delta_l = sqrt(k_p) h_l^2
- * for l < L, delta_L = k_p h_L^2) into eps_out[0..L] (host memory). */
+/* delta_0..delta_L of the accuracy rule of Sec. 4.3 (the equation that
+ * chooses the precisions) with the configured rates, the bias exponent of
+ * delta 1 and its variance exponent 2 (the error lemma of Sec. 4.5):
+ * delta_l = (k_p h_l^beta)^(1/2) for l < L,
+ * delta_L = min((k_p h_L^beta)^(1/2), k_p h_L^alpha); with alpha = 2,
+ * beta = 4 this is Sec. 4.5's sqrt(k_p) h_l^2 and k_p h_L^2.  Into
+ * eps_out[0..L] (host memory). */
 int mlmc_accuracy_targets(const mlmc_ctx *ctx, int32_t L, double *eps_out);
 
 /* Copy Phi_level, stored transposed as [K][(n+1)^2] FP64 (node
@@ -153,7 +170,9 @@ int mlmc_fill_xi(const mlmc_ctx *ctx, int32_t level, int64_t first_sample, int64
  * opts->solver, and Q.  Outputs: q_dev[n]; u_dev[n x (n_l-1)^2] (optional,
  * FP64 solution); status_dev[n] (optional); iters_dev[n] (optional).
  * The workspace keeps the factor, scaling, coefficient and solution for a
- * following mlmc_grad on the same samples. */
+ * following mlmc_grad on the same samples.  The call synchronises the
+ * stream before it returns (it reads the non-converged count back to return
+ * MLMC_ENOCONV). */
 int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
                const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes, double *q_dev,
                double *u_dev, uint8_t *status_dev, int32_t *iters_dev, void *stream);
@@ -205,7 +224,7 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * N_0 = N_1 = n_init; each round recomputes delta_l (Sec. 4.5), tops every
  * level up to N_l with fresh counter-based xi, updates
  * N_l = ceil(sqrt(V_l/C_l) (2/TOL^2) sum_k sqrt(V_k C_k)) with V_l = s_l^2
- * and the deterministic cost C_l = (n_l-1)^4 + (n_{l-1}-1)^4, adds a level
+ * and the deterministic cost C_l = (n_l-1)^gamma + (n_{l-1}-1)^gamma, adds a level
  * while |Y-hat_L| > (m^alpha - 1)/sqrt(2) TOL, and stops when that test and
  * sum_l s_l^2/N_l <= TOL^2/2 hold and no level needs more samples.
  * dtype_per_level[0..L_max] selects u_f per level (ignored for
@@ -218,7 +237,11 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * and results are those of starting them in the next round).  Device memory: a per-level chunk workspace
  * (8 GiB per level, up to 32 GiB for a level whose first n_init samples then
  * fit one chunk), allocated on the first call and kept by the context for
- * later calls (grown when a call needs more, freed by mlmc_destroy). */
+ * later calls (grown when a call needs more, freed by mlmc_destroy).
+ * Every Y_l must reach its accuracy (Algorithm 4.1): a round in which any
+ * sample misses its target after promotion, or whose level sums are not
+ * finite, ends the call with MLMC_ENOCONV; out then holds the state after
+ * that round (converged = 0, n_noconv per level). */
 int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
                   mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream);
 

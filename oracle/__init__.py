@@ -19,6 +19,7 @@ Functions and the passage each follows:
   grad_batch               -- adjoint dQ/dxi (not in the paper; exact
                               derivative of the discrete Q)
   accuracy_targets         -- delta_l of sec. 4.5 (sqrt(k_p) h_l^2, k_p h_L^2)
+  accuracy_targets_rates   -- the general precision choice of sec. 4.3
   level_estimates          -- Y-hat_l and s_l^2 of sec. 4.1
   adaptive_mpml            -- Algorithm 4.1 (sec. 4.3)
   cost_ratio_bound         -- bound of the cost-savings corollary, sec. 4.4
@@ -204,6 +205,21 @@ def accuracy_targets(h, L, k_p=0.05):
     return [math.sqrt(k_p) * h[l] ** 2 if l < L else k_p * h[l] ** 2 for l in range(L + 1)]
 
 
+def accuracy_targets_rates(h, L, k_p, alpha1, beta1, alpha2=1.0, beta2=2.0):
+    """delta_l, l = 0..L, from the general precision-choice equation of
+    sec. 4.3 with bias O(h^alpha1 + delta^alpha2) and variance
+    O(h^beta1 + delta^beta2):
+    delta_l = (k_p h_l^beta1)^(1/beta2) for l < L and
+    delta_L = min((k_p h_L^beta1)^(1/beta2), (k_p h_L^alpha1)^(1/alpha2)).
+    The exponents of delta default to those of the error lemma of sec. 4.5
+    (1 in the bias, 2 in the variance)."""
+    out = []
+    for l in range(L + 1):
+        ev = (k_p * h[l] ** beta1) ** (1.0 / beta2)
+        out.append(ev if l < L else min(ev, (k_p * h[l] ** alpha1) ** (1.0 / alpha2)))
+    return out
+
+
 def level_estimates(y):
     """Y-hat_l = mean and s_l^2 = (1/N_l) sum (Y - Y-hat)^2 (sec. 4.1)."""
     y = np.asarray(y, dtype=np.float64)
@@ -211,15 +227,16 @@ def level_estimates(y):
     return yhat, ((y - yhat) ** 2).sum() / y.size
 
 
-def factor_cost(n):
-    """Deterministic cost units of one grid solve: (n-1)^4 (flops of the factor)."""
-    return float((n - 1) ** 4)
+def factor_cost(n, gamma=4.0):
+    """Deterministic cost units of one grid solve: (n-1)^gamma (gamma = 4:
+    the flops of the factor)."""
+    return float(n - 1) ** gamma
 
 
-def level_cost(n0, l, m=2):
-    c = factor_cost(n0 * m ** l)
+def level_cost(n0, l, m=2, gamma=4.0):
+    c = factor_cost(n0 * m ** l, gamma)
     if l > 0:
-        c += factor_cost(n0 * m ** (l - 1))
+        c += factor_cost(n0 * m ** (l - 1), gamma)
     return c
 
 

@@ -81,6 +81,9 @@ int fail(mlmc_ctx *c, int code, const char *fmt, ...)
     } while (0)
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+// A caller pointer is usable when it is NULL (optional buffers) or aligned to
+// its element size.
+inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : 2); }
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 inline int ilog2(int v) { int l = 0; while ((1 << (l + 1)) <= v) ++l; return l; }
@@ -592,7 +595,8 @@ int mlmc_create(const mlmc_config *cfg, mlmc_ctx **out)
     const mlmc_config &c = *cfg;
     if (c.m != 2 || !is_pow2(c.n0) || c.n0 < 4 || c.L_max < 0 || (c.n0 << c.L_max) > 256 ||
         c.K < 1 || c.K > 512 || !(c.sigma2 >= 0.0) || !(c.corr_len > 0.0) || !std::isfinite(c.f) ||
-        !(c.k_p > 0.0 && c.k_p < 1.0) || c.ir_max_iter < 0 || c.L_max > 15)
+        !(c.k_p > 0.0 && c.k_p < 1.0) || c.ir_max_iter < 0 || c.L_max > 15 || !(c.alpha > 0.0) ||
+        !(c.beta > 0.0) || !(c.gamma > 0.0) || !std::isfinite(c.alpha + c.beta + c.gamma))
         return MLMC_EINVAL;
     mlmc_ctx *ctx = new mlmc_ctx();
     ctx->cfg = c;
@@ -664,9 +668,14 @@ int32_t mlmc_level_cells(const mlmc_ctx *ctx, int32_t level)
 int mlmc_accuracy_targets(const mlmc_ctx *ctx, int32_t L, double *eps_out)
 {
     if (!ctx || !eps_out || L < 0 || L > 15) return MLMC_EINVAL;
+    // Sec. 4.3's precision choice with the error lemma's exponents of delta
+    // (1 in the bias, 2 in the variance): (k_p h^beta)^(1/2) below the finest
+    // level, the smaller of that and k_p h^alpha on it.
+    const mlmc_config &c = ctx->cfg;
     for (int l = 0; l <= L; ++l) {
-        const double h = 1.0 / ((double)ctx->cfg.n0 * std::pow(2.0, l));
-        eps_out[l] = (l < L ? std::sqrt(ctx->cfg.k_p) : ctx->cfg.k_p) * h * h;
+        const double h = 1.0 / ((double)c.n0 * std::pow(2.0, l));
+        const double ev = std::sqrt(c.k_p * std::pow(h, c.beta));
+        eps_out[l] = l < L ? ev : std::min(ev, c.k_p * std::pow(h, c.alpha));
     }
     return MLMC_OK;
 }
@@ -694,7 +703,7 @@ int mlmc_fill_xi(const mlmc_ctx *cctx, int32_t level, int64_t first_sample, int6
 {
     mlmc_ctx *ctx = const_cast<mlmc_ctx *>(cctx);
     if (!ctx || level < 0 || level > 32767 || first_sample < 0 || n < 0 ||
-        first_sample + n > (int64_t)1 << 32 || (!xi_dev && n > 0))
+        first_sample + n > (int64_t)1 << 32 || (!xi_dev && n > 0) || !aligned(xi_dev, 8))
         return fail(ctx, MLMC_EINVAL, "fill_xi: bad arguments");
     HIPCHK(launch_fill_xi(ctx->cfg.seed, level, first_sample, n, ctx->cfg.K, xi_dev, (hipStream_t)stream));
     return MLMC_OK;
@@ -711,6 +720,8 @@ int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
     if (n == 0) return MLMC_OK;
     if (!xi_dev || !ws_dev || !q_dev) return fail(ctx, MLMC_EINVAL, "null pointer");
     if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    if (!aligned(xi_dev, 8) || !aligned(q_dev, 8) || !aligned(u_dev, 8) || !aligned(iters_dev, 4))
+        return fail(ctx, MLMC_EINVAL, "solve: misaligned pointer");
     const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
     if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
     hipStream_t st = (hipStream_t)stream;
@@ -740,6 +751,8 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n > 0 && (!xi_dev || !ws_dev)) return fail(ctx, MLMC_EINVAL, "null pointer");
     if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    if (!aligned(xi_dev, 8) || !aligned(q_fine_dev, 8) || !aligned(q_coarse_dev, 8) || !aligned(y_dev, 8))
+        return fail(ctx, MLMC_EINVAL, "sample_level: misaligned pointer");
     const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
     if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
     hipStream_t st = (hipStream_t)stream;
@@ -789,6 +802,8 @@ int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, c
         if ((rc = check_opts(ctx, &opts[i]))) return rc;
         if (n[i] < 0 || n[i] > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
         if (n[i] > 0 && !xi_dev[i]) return fail(ctx, MLMC_EINVAL, "null xi");
+        if (!aligned(xi_dev[i], 8) || (y_dev && !aligned(y_dev[i], 8)))
+            return fail(ctx, MLMC_EINVAL, "sample_levels: misaligned pointer");
         LL[i] = make_level_layout(ctx->cfg, levels[i], n[i], opts[i]);
         off[i] = tot;
         tot += align256(LL[i].bytes);
@@ -998,7 +1013,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     void *ws = ctx->est_buf;
     char *xi = (char *)ctx->est_buf + align256(ws_bytes);
     auto cost = [&](int l) {
-        auto f = [](int n) { const double m = n - 1; return m * m * m * m; };
+        auto f = [&](int n) { return std::pow((double)(n - 1), c.gamma); };
         return f(c.n0 << l) + (l > 0 ? f(c.n0 << (l - 1)) : 0.0);
     };
     int L = 1;
@@ -1011,6 +1026,11 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     int hcap = 0;
     int rc = MLMC_OK;
     int converged = 0;
+    // per level: samples re-solved in FP64 and samples that missed their
+    // target; the latter, or non-finite level sums, end the call (every Y_l
+    // of Algorithm 4.1 must reach its accuracy)
+    int64_t n_prom[16] = {}, n_nc[16] = {};
+    bool inexact = false;
     for (int round = 0; round < 200; ++round) {
         double eps[16];
         mlmc_accuracy_targets(ctx, L, eps);
@@ -1135,6 +1155,10 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         double next_s1 = 0.0, next_s2 = 0.0;
         for (size_t k = 0; k < recs.size(); ++k) {
             const int l = recs[k].first;
+            n_prom[l] += (int64_t)hbuf[8 * k + 4];
+            n_nc[l] += (int64_t)hbuf[8 * k + 5];
+            if (hbuf[8 * k + 5] != 0.0 || !std::isfinite(hbuf[8 * k]) || !std::isfinite(hbuf[8 * k + 1]))
+                inexact = true;
             if (l > L) {
                 next_s1 += hbuf[8 * k];
                 next_s2 += hbuf[8 * k + 1];
@@ -1153,6 +1177,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
             var[l] = std::max(s2[l] / (double)done[l] - yhat[l] * yhat[l], 0.0);
             tot += std::sqrt(var[l] * cost(l));
         }
+        if (inexact) break;  // no N_l update from inexact or non-finite sums
         for (int l = 0; l <= L; ++l)
             N[l] = std::max<int64_t>(done[l], (int64_t)std::ceil(std::sqrt(var[l] / cost(l)) * 2.0 / (tol * tol) * tot));
         if (std::fabs(yhat[L]) > bias_c && L < Lmax) {
@@ -1193,10 +1218,19 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         out->C[l] = cost(l);
         out->eps[l] = mixed ? eps[l] : 0.0;
     }
+    for (int l = 0; l <= Lmax; ++l) {
+        out->n_promoted[l] = n_prom[l];
+        out->n_noconv[l] = n_nc[l];
+    }
     out->estimate = est;
     out->var_est = v;
     out->gpu_ms = gpu_ms;
     out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (inexact) {
+        out->converged = 0;
+        fail(ctx, MLMC_ENOCONV, "estimate: samples missed their accuracy target or level sums are not finite");
+        return MLMC_ENOCONV;
+    }
     return MLMC_OK;
 }
 
@@ -1243,7 +1277,8 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, con
     if (opts->solver == MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not MINRES)");
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n == 0) return MLMC_OK;
-    if (!xi_dev || !ws_dev || !grad_xi_dev || !(eps_adjoint > 0.0))
+    if (!xi_dev || !ws_dev || !grad_xi_dev || !(eps_adjoint > 0.0) || !aligned(xi_dev, 8) ||
+        !aligned(grad_q_dev, 8) || !aligned(grad_xi_dev, 8))
         return fail(ctx, MLMC_EINVAL, "grad: bad arguments");
     if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
     const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);

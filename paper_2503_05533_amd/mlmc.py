@@ -60,7 +60,8 @@ class _Result(ctypes.Structure):
                 ("N", ctypes.c_int64 * 16), ("Yhat", ctypes.c_double * 16),
                 ("s2", ctypes.c_double * 16), ("C", ctypes.c_double * 16),
                 ("eps", ctypes.c_double * 16), ("wall_s", ctypes.c_double),
-                ("gpu_ms", ctypes.c_double)]
+                ("gpu_ms", ctypes.c_double), ("n_promoted", ctypes.c_int64 * 16),
+                ("n_noconv", ctypes.c_int64 * 16)]
 
 
 _lib = None
@@ -221,13 +222,18 @@ class MLMC:
         self._check(self.lib.mlmc_fill_xi(self.h, level, first, n, _ptr(xi), _stream()), "fill_xi")
         return xi
 
-    def solve(self, level, xi, dtype="f64", solver="direct", eps=0.0, promote=True, want_u=False):
+    def solve(self, level, xi, dtype="f64", solver="direct", eps=0.0, promote=True, want_u=False,
+              own_workspace=False):
+        """Batched solve on one grid.  own_workspace: solve in a workspace of
+        this call's own (returned as out["ws"]) instead of the context's
+        shared one, so that a later grad() can reuse its factor."""
         xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
         S = xi.shape[0]
         n = self.level_cells(level)
         o = self._opts(dtype, solver, eps, 0.0, promote)
         nb = self.lib.mlmc_workspace_bytes(self.h, level, S, ctypes.byref(o))
-        ws = self._workspace(nb)
+        ws = (torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device) if own_workspace
+              else self._workspace(nb))
         q = torch.empty(S, dtype=torch.float64, device=self.device)
         u = torch.empty((S, (n - 1) ** 2), dtype=torch.float64, device=self.device) if want_u else None
         st = torch.empty(S, dtype=torch.uint8, device=self.device)
@@ -238,6 +244,8 @@ class MLMC:
         out = dict(q=q, status=st, iters=it, rc=rc)
         if want_u:
             out["u"] = u
+        if own_workspace:
+            out["ws"] = ws
         return out
 
     def sample_level(self, level, xi, dtype="f64", solver="direct", eps_fine=0.0, eps_coarse=0.0,
@@ -280,27 +288,37 @@ class MLMC:
         L1 = self.cfg.L_max + 1
         dts = (ctypes.c_int * L1)(*[DTYPES[d] for d in (dtypes or ["f32"] * L1)])
         r = _Result()
-        self._check(self.lib.mlmc_estimate(self.h, float(tol), int(n_init), dts, SOLVERS[solver],
-                                           1 if mixed else 0, ctypes.byref(r), _stream()), "estimate")
+        rc = self._check(self.lib.mlmc_estimate(self.h, float(tol), int(n_init), dts, SOLVERS[solver],
+                                                1 if mixed else 0, ctypes.byref(r), _stream()),
+                         "estimate")
         L = r.L
         return dict(estimate=r.estimate, var_est=r.var_est, L=L, converged=bool(r.converged),
                     N=list(r.N[:L + 1]), Yhat=list(r.Yhat[:L + 1]), s2=list(r.s2[:L + 1]),
                     C=list(r.C[:L + 1]), eps=list(r.eps[:L + 1]), wall_s=r.wall_s,
-                    gpu_ms=r.gpu_ms)
+                    gpu_ms=r.gpu_ms, n_promoted=list(r.n_promoted[:L1]),
+                    n_noconv=list(r.n_noconv[:L1]), rc=rc)
 
-    def grad(self, level, xi, grad_q=None, eps_adjoint=1e-10, dtype="f32", solver="direct_ir",
-             eps=1e-10):
-        """(Q, dQ/dxi * grad_q): forward solve, then the adjoint on the same workspace."""
+    def grad_from(self, level, xi, ws, grad_q=None, eps_adjoint=1e-10, dtype="f32",
+                  solver="direct_ir", eps=1e-10):
+        """grad_q[s] * dQ/dxi[s, :] for the samples of a preceding solve() on
+        workspace ws with the same level, xi and options (its factor and
+        solution are reused by the adjoint)."""
         xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
         S = xi.shape[0]
-        fw = self.solve(level, xi, dtype=dtype, solver=solver, eps=eps, promote=True)
         o = self._opts(dtype, solver, eps, 0.0, True)
-        ws = self._ws
         g = torch.empty((S, self.cfg.K), dtype=torch.float64, device=self.device)
         gq = None if grad_q is None else grad_q.to(device=self.device, dtype=torch.float64).contiguous()
         self._check(self.lib.mlmc_grad(self.h, level, S, _ptr(xi), _ptr(gq), ctypes.byref(o),
                                        float(eps_adjoint), _ptr(ws), ws.numel(), _ptr(g), _stream()),
                     "grad")
+        return g
+
+    def grad(self, level, xi, grad_q=None, eps_adjoint=1e-10, dtype="f32", solver="direct_ir",
+             eps=1e-10):
+        """(Q, dQ/dxi * grad_q): forward solve, then the adjoint on the same workspace."""
+        xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
+        fw = self.solve(level, xi, dtype=dtype, solver=solver, eps=eps, promote=True)
+        g = self.grad_from(level, xi, self._ws, grad_q, eps_adjoint, dtype, solver, eps)
         return fw["q"], g
 
 
@@ -343,18 +361,26 @@ class LevelPlan:
 class MLMCQoI(torch.autograd.Function):
     """Q_l(xi) on one grid with the adjoint gradient as backward.
 
-    forward(ctx_obj, level, xi, dtype, eps) -> Q[S]; backward returns
-    grad_q[s] * dQ/dxi[s, :] from the library's adjoint kernel.
+    forward(ctx_obj, level, xi, dtype, eps) -> Q[S] solves only, in a
+    workspace of its own that keeps the factor and the solution; backward
+    runs the library's adjoint on that workspace with grad_q = grad_out and
+    returns grad_q[s] * dQ/dxi[s, :].  The workspace is released with the
+    autograd graph (after backward, or when no backward follows).
     """
 
     @staticmethod
     def forward(ctx, lib_ctx, level, xi, dtype="f32", eps=1e-10):
-        q, g = lib_ctx.grad(level, xi.detach(), None, eps_adjoint=eps, dtype=dtype,
-                            solver="direct_ir" if dtype != "f64" else "direct", eps=eps)
-        ctx.save_for_backward(g)
-        return q.to(xi.dtype)
+        solver = "direct_ir" if dtype != "f64" else "direct"
+        xd = xi.detach().to(device=lib_ctx.device, dtype=torch.float64).contiguous()
+        fw = lib_ctx.solve(level, xd, dtype=dtype, solver=solver, eps=eps, promote=True,
+                           own_workspace=True)
+        ctx.lib_ctx, ctx.level, ctx.dtype, ctx.solver, ctx.eps = lib_ctx, level, dtype, solver, eps
+        ctx.ws, ctx.xi = fw["ws"], xd
+        return fw["q"].to(xi.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):
-        (g,) = ctx.saved_tensors
-        return None, None, (g * grad_out.to(g.dtype)[:, None]), None, None
+        g = ctx.lib_ctx.grad_from(ctx.level, ctx.xi, ctx.ws, grad_out, eps_adjoint=ctx.eps,
+                                  dtype=ctx.dtype, solver=ctx.solver, eps=ctx.eps)
+        ctx.ws = None
+        return None, None, g, None, None

@@ -1,7 +1,8 @@
 // Host-only driver of the C ABI against the stub runtime: the multi-level
 // step (graph and eager, FP32 refinement and FP64 direct) with the four-level
 // workload shapes, three times each, then the adaptive estimator (mixed and
-// standard).  Run under AddressSanitizer by tests/test_host_logic.py.
+// standard).  Run under AddressSanitizer by tests/test_host_logic.py, once
+// as is and once with the stub reporting a non-converged sample per chunk.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -46,7 +47,8 @@ int main()
         mlmc_result res;
         for (int mixed = 1; mixed >= 0; --mixed) {
             rc = mlmc_estimate(ctx, 2e-5, 1000, dts, MLMC_DIRECT_IR, mixed, &res, nullptr);
-            printf("estimate mixed=%d rc=%d L=%d N0=%lld %s\n", mixed, rc, res.L, (long long)res.N[0], rc ? mlmc_last_error(ctx) : "");
+            printf("estimate mixed=%d rc=%d L=%d N0=%lld noconv0=%lld conv=%d %s\n", mixed, rc, res.L,
+                   (long long)res.N[0], (long long)res.n_noconv[0], res.converged, rc ? mlmc_last_error(ctx) : "");
         }
     }
     mlmc_destroy(ctx);

@@ -30,10 +30,23 @@ def test_host_scheduling_under_asan(tmp_path):
     subprocess.run(["g++", "-fsanitize=address", "-o", exe] + objs, check=True, capture_output=True,
                    timeout=120)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    env.pop("STUB_NOCONV", None)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    # the stub aborts on a capture that leaves a forked stream unjoined or
+    # waits on an event recorded outside it
     assert r.returncode == 0, r.stderr[-4000:]
     lines = r.stdout.splitlines()
     steps = [l for l in lines if l.startswith("dt=") and "rep=" in l]
     assert len(steps) == 12 and all(l.split("rc=")[1].startswith("0") for l in steps), r.stdout
     est = [l for l in lines if l.startswith("estimate")]
-    assert len(est) == 2 and all(" rc=0 " in l and " L=3 " in l for l in est), r.stdout
+    assert len(est) == 2 and all(" rc=0 " in l and " L=3 " in l and " noconv0=0 " in l for l in est), r.stdout
+    # every chunk reports a non-converged sample: the estimator stops after
+    # its first round with MLMC_ENOCONV and the counts per level
+    env["STUB_NOCONV"] = "1"
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-4000:]
+    est = [l for l in r.stdout.splitlines() if l.startswith("estimate")]
+    assert len(est) == 2, r.stdout
+    for l in est:
+        assert " rc=1 " in l and " L=1 " in l and " conv=0 " in l, l
+        assert int(l.split("noconv0=")[1].split()[0]) >= 1, l

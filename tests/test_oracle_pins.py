@@ -484,3 +484,19 @@ def test_field_mirrors_with_mode_parity():
     assert np.allclose(Zx, Z[:, :, ::-1], atol=1e-12)
     assert np.allclose(Zy, Z[:, ::-1, :], atol=1e-12)
     assert not np.allclose(Zx, Z[:, ::-1, :], atol=1e-3)
+
+
+def test_general_precision_choice_reduces_to_fem_rule():
+    """Sec. 4.3's general rule with the error lemma's exponents (alpha1 = 2,
+    alpha2 = 1, beta1 = 4, beta2 = 2) is Sec. 4.5's rule; with other rates it
+    follows the two branches of its minimum."""
+    h = [1.0 / (8 * 2 ** l) for l in range(5)]
+    for L in range(1, 5):
+        assert oracle.accuracy_targets_rates(h, L, 0.05, 2.0, 4.0) == \
+            pytest.approx(oracle.accuracy_targets(h, L, 0.05), rel=1e-14)
+    # beta1 = 3: below the finest level (k_p h^3)^(1/2); on it the bias branch
+    # k_p h^2 is the smaller one while h < k_p
+    d = oracle.accuracy_targets_rates(h, 4, 0.05, 2.0, 3.0)
+    assert d[0] == pytest.approx(math.sqrt(0.05 * h[0] ** 3), rel=1e-14)
+    assert d[4] == pytest.approx(min(math.sqrt(0.05 * h[4] ** 3), 0.05 * h[4] ** 2), rel=1e-14)
+    assert d[4] == pytest.approx(0.05 * h[4] ** 2, rel=1e-14)
