@@ -1,11 +1,13 @@
 """Builds libmlmc.so (HIP, gfx950) in-tree with hipcc."""
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmlmc.so")
-SOURCES = ["csrc/kernels.hip", "csrc/factor_mfma.hip", "csrc/minres.hip", "csrc/api.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/factor_mfma.hip", "csrc/minres.hip",
+           "csrc/api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -15,16 +17,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 def build(verbose=False):
     """Compile every source for gfx950 and link the shared library."""
-    objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(HERE, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently: one hipcc process each
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
