@@ -189,6 +189,26 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
                       double *q_fine_dev, double *q_coarse_dev, double *y_dev,
                       uint8_t *status_dev, mlmc_level_stats *stats_host, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mlmc_sample_level with the workspace taken from a fixed scratch array that
+ * the library holds on every device it runs on (MLMC_NOALLOC_SCRATCH_BYTES,
+ * kept until the process ends; its device address is taken once per device
+ * at mlmc_create).  The caller still passes xi and the outputs, with the
+ * meaning, layout and synchronisation of mlmc_sample_level.  The call
+ * allocates nothing (no hipMalloc/hipFree; kernel timing records of
+ * mlmc_profile are not taken during it).  MLMC_ENOMEM when
+ * mlmc_workspace_bytes(ctx, level, n, opts) exceeds the scratch size.
+ * Every call on a device, from any context, shares that device's array and
+ * finds the previous call's contents there (the kernels initialise what they
+ * read); calls that overlap on one device, on different streams or from
+ * different threads, race and must be serialised by the caller. */
+#define MLMC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mlmc_sample_level_noalloc(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                              const mlmc_level_opts *opts, double *q_fine_dev, double *q_coarse_dev,
+                              double *y_dev, uint8_t *status_dev, mlmc_level_stats *stats_host,
+                              void *stream);
+
 /* Several MLMC levels in one call: level levels[i] with n[i] samples and
  * xi_dev[i] ([n[i] x K]) under opts[i].  Every level's fine and coarse grids
  * run concurrently on streams forked from `stream` and joined back to it,

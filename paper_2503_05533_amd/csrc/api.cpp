@@ -49,6 +49,9 @@ struct mlmc_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uintptr_t> graph_key;
     bool capturing = false;
+    // device address of the library's fixed scratch array on this device
+    // (mlmc_sample_level_noalloc), taken at mlmc_create
+    void *scratch = nullptr;
 };
 
 namespace {
@@ -582,6 +585,40 @@ void fill_stats(mlmc_level_stats *out, int64_t n, const double *h, double ms)
     out->gpu_ms = ms;
 }
 
+// One MLMC level on the workspace ws_dev (a caller buffer, or the library's
+// scratch array for the no-allocation entry point).
+int sample_level_impl(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                      const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes,
+                      double *q_fine_dev, double *q_coarse_dev, double *y_dev,
+                      uint8_t *status_dev, mlmc_level_stats *stats_host, void *stream)
+{
+    int rc = check_level(ctx, level);
+    if (rc) return rc;
+    if ((rc = check_opts(ctx, opts))) return rc;
+    if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
+    if (n > 0 && (!xi_dev || !ws_dev)) return fail(ctx, MLMC_EINVAL, "null pointer");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
+    if (!aligned(xi_dev, 8) || !aligned(q_fine_dev, 8) || !aligned(q_coarse_dev, 8) || !aligned(y_dev, 8))
+        return fail(ctx, MLMC_EINVAL, "sample_level: misaligned pointer");
+    const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
+    if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
+    hipStream_t st = (hipStream_t)stream;
+    if (stats_host) HIPCHK(hipEventRecord(ctx->ev0, st));
+    rc = level_enqueue(ctx, level, n, xi_dev, *opts, ws_dev, LL, q_fine_dev, q_coarse_dev, y_dev, status_dev,
+                       st, st, nullptr);
+    if (rc) return rc;
+    if (stats_host) {
+        HIPCHK(hipEventRecord(ctx->ev1, st));
+        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, at<double>(ws_dev, LL.off_sums), 8 * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        fill_stats(stats_host, n, ctx->h_sums, ms);
+        return stats_host->n_noconv > 0 ? MLMC_ENOCONV : MLMC_OK;
+    }
+    return MLMC_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -600,7 +637,8 @@ int mlmc_create(const mlmc_config *cfg, mlmc_ctx **out)
         return MLMC_EINVAL;
     mlmc_ctx *ctx = new mlmc_ctx();
     ctx->cfg = c;
-    if (hipGetDevice(&ctx->device) != hipSuccess) {
+    if (hipGetDevice(&ctx->device) != hipSuccess ||
+        scratch_device_ptr(ctx->device, &ctx->scratch) != hipSuccess) {
         delete ctx;
         return MLMC_EHIP;
     }
@@ -745,31 +783,31 @@ int mlmc_sample_level(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
                       double *q_fine_dev, double *q_coarse_dev, double *y_dev,
                       uint8_t *status_dev, mlmc_level_stats *stats_host, void *stream)
 {
+    return sample_level_impl(ctx, level, n, xi_dev, opts, ws_dev, ws_bytes, q_fine_dev, q_coarse_dev, y_dev,
+                             status_dev, stats_host, stream);
+}
+
+int mlmc_sample_level_noalloc(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
+                              const mlmc_level_opts *opts, double *q_fine_dev, double *q_coarse_dev,
+                              double *y_dev, uint8_t *status_dev, mlmc_level_stats *stats_host,
+                              void *stream)
+{
     int rc = check_level(ctx, level);
     if (rc) return rc;
     if ((rc = check_opts(ctx, opts))) return rc;
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
-    if (n > 0 && (!xi_dev || !ws_dev)) return fail(ctx, MLMC_EINVAL, "null pointer");
-    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
-    if (!aligned(xi_dev, 8) || !aligned(q_fine_dev, 8) || !aligned(q_coarse_dev, 8) || !aligned(y_dev, 8))
-        return fail(ctx, MLMC_EINVAL, "sample_level: misaligned pointer");
-    const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
-    if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
-    hipStream_t st = (hipStream_t)stream;
-    if (stats_host) HIPCHK(hipEventRecord(ctx->ev0, st));
-    rc = level_enqueue(ctx, level, n, xi_dev, *opts, ws_dev, LL, q_fine_dev, q_coarse_dev, y_dev, status_dev,
-                       st, st, nullptr);
-    if (rc) return rc;
-    if (stats_host) {
-        HIPCHK(hipEventRecord(ctx->ev1, st));
-        if (n > 0) HIPCHK(hipMemcpyAsync(ctx->h_sums, at<double>(ws_dev, LL.off_sums), 8 * 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        fill_stats(stats_host, n, ctx->h_sums, ms);
-        return stats_host->n_noconv > 0 ? MLMC_ENOCONV : MLMC_OK;
-    }
-    return MLMC_OK;
+    if (!ctx->scratch) return fail(ctx, MLMC_EHIP, "no scratch address for device %d", ctx->device);
+    const size_t need = make_level_layout(ctx->cfg, level, n, *opts).bytes;
+    if (need > kNoallocScratchBytes)
+        return fail(ctx, MLMC_ENOMEM, "sample_level_noalloc: %lld samples on level %d need %zu bytes, the scratch holds %zu",
+                    (long long)n, level, need, kNoallocScratchBytes);
+    // the event-timed kernel records create events on demand: off for this call
+    const bool prof = ctx->prof_on;
+    ctx->prof_on = false;
+    rc = sample_level_impl(ctx, level, n, xi_dev, opts, ctx->scratch, kNoallocScratchBytes, q_fine_dev,
+                           q_coarse_dev, y_dev, status_dev, stats_host, stream);
+    ctx->prof_on = prof;
+    return rc;
 }
 
 size_t mlmc_levels_workspace_bytes(const mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels,

@@ -26,6 +26,12 @@ inline bool use_blk(int dtype, int n) { return n == 16 || n >= (dtype == 0 ? 64 
 
 size_t factor_entries_per_sample(int dtype, int n);
 
+// Size of the per-device scratch array behind mlmc_sample_level_noalloc.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+// Device address of that array on `device`, which must be the current
+// device; taken once per device (hipGetSymbolAddress) and kept.
+hipError_t scratch_device_ptr(int device, void **out);
+
 // Arguments of the per-sample refinement kernel (one workgroup per sample b:
 // sample idx[b] (or b), factor slot slot_base + b; b >= *count exits).
 struct ir_args {

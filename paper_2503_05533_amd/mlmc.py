@@ -24,7 +24,9 @@ ST_CONVERGED, ST_PROMOTED, ST_NONFINITE, ST_IMAX = 1, 2, 4, 8
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
            "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
            "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
-           "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune"]
+           "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune",
+           "mlmc_sample_level_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class MLMCError(RuntimeError):
@@ -91,6 +93,8 @@ def load_library():
                                vp, vp, vp, vp, vp]
     lib.mlmc_sample_level.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp,
                                       ctypes.c_size_t, vp, vp, vp, vp, ctypes.POINTER(_LevelStats), vp]
+    lib.mlmc_sample_level_noalloc.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp, vp,
+                                              vp, vp, ctypes.POINTER(_LevelStats), vp]
     lib.mlmc_estimate.argtypes = [vp, dbl, i32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, i32,
                                   ctypes.POINTER(_Result), vp]
     lib.mlmc_grad.argtypes = [vp, i32, i64, vp, vp, ctypes.POINTER(_LevelOpts), dbl, vp,
@@ -269,6 +273,29 @@ class MLMC:
         if stats:
             out["stats"] = {k: getattr(sts, k) for k, _ in _LevelStats._fields_}
         return out
+
+    def sample_level_noalloc(self, level, xi, dtype="f64", solver="direct", eps_fine=0.0,
+                             eps_coarse=0.0, promote=True, stats=True, out=None):
+        """sample_level on the library's fixed per-device scratch (no workspace
+        allocation by the library).  out: optional dict of preallocated
+        output tensors qf, qc, y, status (else they are allocated here)."""
+        xi = xi.to(device=self.device, dtype=torch.float64).contiguous()
+        S = xi.shape[0]
+        o = self._opts(dtype, solver, eps_fine, eps_coarse, promote)
+        if out is None:
+            out = dict(qf=torch.empty(S, dtype=torch.float64, device=self.device),
+                       qc=torch.empty(S, dtype=torch.float64, device=self.device) if level > 0 else None,
+                       y=torch.empty(S, dtype=torch.float64, device=self.device),
+                       status=torch.empty(S, dtype=torch.uint8, device=self.device))
+        sts = _LevelStats()
+        rc = self._check(self.lib.mlmc_sample_level_noalloc(
+            self.h, level, S, _ptr(xi), ctypes.byref(o), _ptr(out["qf"]), _ptr(out.get("qc")),
+            _ptr(out["y"]), _ptr(out["status"]), ctypes.byref(sts) if stats else None, _stream()),
+            "sample_level_noalloc")
+        res = dict(out, rc=rc)
+        if stats:
+            res["stats"] = {k: getattr(sts, k) for k, _ in _LevelStats._fields_}
+        return res
 
     def plan_levels(self, levels, xis, opts, use_graph=True):
         """A LevelPlan: opts is a list of dicts (dtype, solver, eps_fine, eps_coarse, promote)."""

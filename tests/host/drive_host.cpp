@@ -51,6 +51,23 @@ int main()
                    (long long)res.N[0], (long long)res.n_noconv[0], res.converged, rc ? mlmc_last_error(ctx) : "");
         }
     }
+    {
+        // the no-allocation entry point: a level that fits the scratch, then one that does not
+        mlmc_level_opts o{};
+        o.factor_dtype = MLMC_F32;
+        o.solver = MLMC_DIRECT_IR;
+        o.eps_fine = 1e-6;
+        o.eps_coarse = 1e-6;
+        o.promote = 1;
+        std::vector<double> xi0(1), q0(1);
+        mlmc_level_stats st;
+        const int64_t ns[2] = {64, 200000};
+        for (int k = 0; k < 2; ++k) {
+            rc = mlmc_sample_level_noalloc(ctx, 1, ns[k], xi0.data(), &o, q0.data(), q0.data(), q0.data(),
+                                           nullptr, &st, nullptr);
+            printf("noalloc n=%lld rc=%d\n", (long long)ns[k], rc);
+        }
+    }
     mlmc_destroy(ctx);
     return 0;
 }

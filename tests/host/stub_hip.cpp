@@ -167,6 +167,8 @@ size_t factor_entries_per_sample(int dtype, int n)
     int TR = n <= 16 ? 2 : (n <= 32 ? 4 : 8); const int Tn = n / TR, T = Tn * (Tn + 1) / 2;
     return (size_t)(n - 1) * T * TR * TR;
 }
+// the scratch array's device address: a fake address (the stub launchers never touch memory)
+hipError_t scratch_device_ptr(int, void **out) { *out = (void *)(uintptr_t)0x200000000ull; return hipSuccess; }
 hipError_t launch_fill_xi(uint64_t, int, int64_t, int64_t, int, double *, hipStream_t st) { return op(st); }
 hipError_t launch_field(int, int, int, const double *, const double *, double *, hipStream_t st) { return op(st); }
 hipError_t launch_grad_gemm(int, int, int, const double *, const double *, const double *, double *, hipStream_t st) { return op(st); }

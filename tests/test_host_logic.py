@@ -38,6 +38,8 @@ def test_host_scheduling_under_asan(tmp_path):
     lines = r.stdout.splitlines()
     steps = [l for l in lines if l.startswith("dt=") and "rep=" in l]
     assert len(steps) == 12 and all(l.split("rc=")[1].startswith("0") for l in steps), r.stdout
+    noalloc = [l for l in lines if l.startswith("noalloc")]
+    assert noalloc == ["noalloc n=64 rc=0", "noalloc n=200000 rc=-2"], r.stdout
     est = [l for l in lines if l.startswith("estimate")]
     assert len(est) == 2 and all(" rc=0 " in l and " L=3 " in l and " noconv0=0 " in l for l in est), r.stdout
     # every chunk reports a non-converged sample: the estimator stops after
