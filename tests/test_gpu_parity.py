@@ -318,3 +318,88 @@ def test_error_codes():
     assert rc == -2
     assert b"workspace" in ctx.lib.mlmc_last_error(ctx.h)
     ctx.close()
+
+
+# ----------------------------------------------------------------- forced conditions
+
+@pytest.mark.parametrize("n,dtype,solver", [(16, "f32", "direct_ir"), (32, "f32", "direct_ir"),
+                                            (64, "f32", "direct_ir"), (32, "f64", "direct"),
+                                            (64, "f64", "direct")])
+def test_nonfinite_xi_flags_only_its_sample(n, dtype, solver):
+    """A NaN in one xi row: that sample ends flagged non-finite and not
+    converged (after promotion, for the low-precision factor), the call
+    returns MLMC_ENOCONV, and every other sample of the batch (which shares
+    field tiles, waves and workgroups with it) still matches the oracle."""
+    torch = _torch()
+    K, s2, lam, seed = 16, 1.0, 0.3, 21
+    level = {16: 0, 32: 1, 64: 2}[n]
+    S, bad = 40, 5
+    ctx = _ctx(n0=16, L_max=2, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    xi = si.splitmix64_normals(seed, level, 0, S, K)
+    xi_bad = xi.copy()
+    xi_bad[bad, 3] = float("nan")
+    out = ctx.solve(level, torch.from_numpy(xi_bad), dtype=dtype, solver=solver, eps=1e-10, promote=True)
+    st = out["status"].cpu().numpy()
+    _say("nan xi n=%d %s: rc %d, status of the bad row %d" % (n, dtype, out["rc"], st[bad]))
+    assert out["rc"] == 1
+    assert (st[bad] & 4) and not (st[bad] & 1)
+    good = np.arange(S) != bad
+    assert np.all(st[good] & 1) and not np.any(st[good] & 4)
+    q = out["q"].cpu().numpy()
+    qref = oracle.solve_batch(n, _phi(n, K, s2, lam), xi[good])
+    assert np.all(np.abs(q[good] - qref) / qref < 1e-9)
+    # through the level call: one non-converged pair reported
+    lo = ctx.sample_level(level, torch.from_numpy(xi_bad), dtype=dtype, solver=solver, eps_fine=1e-10,
+                          eps_coarse=1e-10)
+    assert lo["rc"] == 1 and lo["stats"]["n_noconv"] == 1
+    ctx.close()
+
+
+def test_extreme_field_forces_promotion():
+    """xi_0 = 40 on some rows (coefficient contrast ~e^40): with diagonal
+    scaling the FP16-stored factor still contracts there, but needs 7-10
+    corrections to reach eps = 1e-8 against 3 for ordinary rows (measured).
+    With i_max = 5 those samples miss the target in FP16, are promoted to an
+    FP64 factor and converge; the others stay in FP16; every Q obeys the
+    residual bound against the oracle."""
+    torch = _torch()
+    K, s2, lam, seed, n, level = 16, 1.0, 0.3, 22, 32, 1
+    S = 24
+    ctx = _ctx(n0=16, L_max=1, K=K, sigma2=s2, corr_len=lam, seed=seed, ir_max_iter=5)
+    xi = si.splitmix64_normals(seed, level, 0, S, K)
+    hot = np.arange(0, S, 4)
+    xi[hot, 0] = 40.0
+    eps = 1e-8
+    out = ctx.solve(level, torch.from_numpy(xi), dtype="f16", solver="direct_ir", eps=eps, promote=True,
+                    want_u=True)
+    st = out["status"].cpu().numpy()
+    _say("xi0=40: status", st.tolist(), "iters", out["iters"].cpu().numpy().tolist())
+    assert out["rc"] == 0 and np.all(st & 1)
+    assert np.all(st[hot] & 2)
+    cold = np.setdiff1d(np.arange(S), hot)
+    assert not np.any(st[cold] & 2)
+    qref, uref = oracle.solve_batch(n, _phi(n, K, s2, lam), xi, want_u=True)
+    rr = oracle.relres_batch(n, _phi(n, K, s2, lam), xi, out["u"].cpu().numpy())
+    assert np.all(rr < eps * (1 + 1e-6))
+    dq = np.abs(out["q"].cpu().numpy() - qref) / qref
+    assert np.all(dq <= rr * _bound(n, uref, qref) * (1 + 1e-6) + 1e-14)
+    ctx.close()
+
+
+@pytest.mark.parametrize("K", [17, 63])
+def test_odd_mode_counts(K):
+    """An odd number of KL modes: the device generator fills the last column
+    from the cosine half of its pair, and the field GEMM's partial mode chunk
+    contributes exactly; FP64 Q within 1e-12 of the oracle."""
+    torch = _torch()
+    s2, lam, seed = 1.0, 0.3, 23
+    ctx = _ctx(n0=16, L_max=1, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    for level, S in ((0, 37), (1, 21)):
+        n = 16 << level
+        xg = ctx.fill_xi(level, 5, S).cpu().numpy()
+        xr = si.splitmix64_normals(seed, level, 5, S, K)
+        assert np.max(np.abs(xg - xr)) <= 1e-13 * max(1.0, np.max(np.abs(xr)))
+        out = ctx.solve(level, torch.from_numpy(xr), dtype="f64", solver="direct")
+        qref = oracle.solve_batch(n, _phi(n, K, s2, lam), xr)
+        assert np.all(np.abs(out["q"].cpu().numpy() - qref) / qref <= 1e-12), (K, level)
+    ctx.close()
