@@ -44,6 +44,34 @@ __device__ inline f64x4 mfma4(double a, double b, f64x4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// The FP16 and BF16 factors form their products in their own precision with
+// FP32 accumulation: a rank-16 product of 16 x 16 blocks is one
+// v_mfma_f32_16x16x16_{f16,bf16} whose operands are rounded to the storage
+// type (lane l = 16 lr + lc holds A[lc][4 lr .. 4 lr + 3] and
+// B[4 lr .. 4 lr + 3][lc]; the result has the layout of the FP32 16x16x4
+// product).  The FP32 factor keeps four FP32 16x16x4 products.
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+template <typename Tst> constexpr bool mfma_in_storage() { return false; }
+template <> constexpr bool mfma_in_storage<__half>() { return true; }
+template <> constexpr bool mfma_in_storage<__hip_bfloat16>() { return true; }
+
+template <typename Tst> __device__ inline f32x4 mfma16(const float a[4], const float b[4], f32x4 c);
+template <> __device__ inline f32x4 mfma16<__half>(const float a[4], const float b[4], f32x4 c)
+{
+    const f16x4 av = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+    const f16x4 bv = {(_Float16)b[0], (_Float16)b[1], (_Float16)b[2], (_Float16)b[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, c, 0, 0, 0);
+}
+template <> __device__ inline f32x4 mfma16<__hip_bfloat16>(const float a[4], const float b[4], f32x4 c)
+{
+    const bf16x4 av = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3]};
+    const bf16x4 bv = {(__bf16)b[0], (__bf16)b[1], (__bf16)b[2], (__bf16)b[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, av),
+                                                      __builtin_bit_cast(s16x4, bv), c, 0, 0, 0);
+}
+
 // Row (within a 16 x 16 block) of result register r in lane group lr = l/16:
 // FP32 16x16x4 puts D[4 lr + r][l%16] in register r, FP64 16x16x4 puts
 // D[4 r + lr][l%16] there.
@@ -381,9 +409,19 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
             for (int x = 0; x < 2; ++x) {
                 const int row = x ? NB - 1 - wk : wk;
                 V4 u = V4{0, 0, 0, 0};
+                if constexpr (mfma_in_storage<Tst>()) {
+                    float av[4], bv[4];
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc)
-                    u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
+                    for (int c = 0; c < 4; ++c) {
+                        av[c] = V[(16 * row + lc) * LD + 4 * lr + c];
+                        bv[c] = P[(4 * lr + c) * LD + lc];
+                    }
+                    u = mfma16<Tst>(av, bv, u);
+                } else {
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+                        u = mfma4(V[(16 * row + lc) * LD + 4 * kc + lr], P[(4 * kc + lr) * LD + lc], u);
+                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Uw[wk][x][drow<Tac>(lr, r) * LD + lc] = u[r];
             }
@@ -396,13 +434,22 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                 if (I != K && J != K) {
                     // C[I,J] += U_I V_J^T
                     Tac av[4], bv[4];
+                    if constexpr (mfma_in_storage<Tst>()) {
 #pragma unroll
-                    for (int kc = 0; kc < 4; ++kc) {
-                        av[kc] = U[lc * LD + 4 * kc + lr];
-                        bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
+                        for (int c = 0; c < 4; ++c) {
+                            av[c] = U[lc * LD + 4 * lr + c];
+                            bv[c] = V[(16 * J + lc) * LD + 4 * lr + c];
+                        }
+                        acc[q] = mfma16<Tst>(av, bv, acc[q]);
+                    } else {
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) {
+                            av[kc] = U[lc * LD + 4 * kc + lr];
+                            bv[kc] = V[(16 * J + lc) * LD + 4 * kc + lr];
+                        }
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
                     }
-#pragma unroll
-                    for (int kc = 0; kc < 4; ++kc) acc[q] = mfma4(av[kc], bv[kc], acc[q]);
                 } else if (I == K && J == K) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[q][r] = P[drow<Tac>(lr, r) * LD + lc];
@@ -413,9 +460,19 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                 } else {
                     // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
                     V4 z = V4{0, 0, 0, 0};
+                    if constexpr (mfma_in_storage<Tst>()) {
+                        float av[4], bv[4];
 #pragma unroll
-                    for (int kc = 0; kc < 4; ++kc)
-                        z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
+                        for (int c = 0; c < 4; ++c) {
+                            av[c] = P[(4 * lr + c) * LD + lc];
+                            bv[c] = V[(16 * J + lc) * LD + 4 * lr + c];
+                        }
+                        z = mfma16<Tst>(av, bv, z);
+                    } else {
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc)
+                            z = mfma4(P[(4 * kc + lr) * LD + lc], V[(16 * J + lc) * LD + 4 * kc + lr], z);
+                    }
                     acc[q] = -z;
                 }
                 __builtin_amdgcn_sched_barrier(0);
