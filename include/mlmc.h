@@ -9,7 +9,7 @@
  *   level l has n_l = n0 * m^l cells per side, h_l = 1/n_l; the unknowns are
  *   the (n_l - 1)^2 interior nodes, ordered P = (iy-1)(n_l-1) + (ix-1);
  *   the coefficient is nodal, a_p = exp(Z_p), Z = xi . Phi_l^T with Phi_l the
- *   separable exponential-covariance KL basis on the (n_l+1)^2 nodes; the
+ *   field basis (mlmc_config.field) on the (n_l+1)^2 nodes; the
  *   edge coefficient is the harmonic mean of its end nodes; b = h^2 f;
  *   Q = h^2 * sum_P u_P.
  *
@@ -42,7 +42,7 @@ extern "C" {
 #define MLMC_EINVAL (-1)  /* bad argument: null/misaligned pointer, level out of range, NaN */
 #define MLMC_ENOMEM (-2)  /* workspace smaller than mlmc_workspace_bytes */
 #define MLMC_EHIP (-3)    /* HIP runtime error (text via mlmc_last_error) */
-#define MLMC_ENOTIMPL (-4)
+#define MLMC_ENOTIMPL (-4) /* option not available for these arguments (e.g. a dtype on this grid) */
 
 /* Per-sample status bits (uint8). */
 #define MLMC_ST_CONVERGED 1u  /* relative residual < target */
@@ -52,12 +52,18 @@ extern "C" {
 
 typedef struct mlmc_ctx mlmc_ctx;
 
-/* Storage precision u_f of the factor (Algorithm 2.1, Sec. 2.3).  The
- * factorisation and the correction solves run in FP32 arithmetic for every
- * low-precision type (FP64 for MLMC_F64): BF16 and FP16 round the stored
- * factor, not the arithmetic that forms it, so their u_f is the storage
- * unit roundoff (the paper's half-precision factor computes in half). */
-typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3 } mlmc_dtype;
+/* Precision u_f of the factor (Algorithm 2.1, Sec. 2.3; formats of Sec. 2.1).
+ * MLMC_F64 and MLMC_F32 factorise in their own precision.  MLMC_F16 and
+ * MLMC_BF16 store the factor in 16 bits; from the 32-cell grid up (the MFMA
+ * kernels) the factorisation multiplies its 16 x 16 block operands rounded
+ * to that format with FP32 accumulation, on the 16-cell and smaller grids
+ * it forms the factor in FP32 and rounds the stored copy.  MLMC_FP8 stores
+ * the factor in FP8 E4M3 (the quarter precision q43 of Sec. 2.1, unit
+ * roundoff 2^-4), formed in FP32; it is available on grids with fewer than
+ * 16 cells per side only (a coarsest level such as the paper's h_0 = 1/4),
+ * elsewhere the calls return MLMC_ENOTIMPL.  The correction solves run in
+ * FP32 arithmetic on the stored factor for every type but MLMC_F64. */
+typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3, MLMC_FP8 = 4 } mlmc_dtype;
 
 /* Linear solver of one sample:
  *   MLMC_DIRECT    FP64 factorisation and solve, no refinement loop.
@@ -88,6 +94,13 @@ typedef struct {
     int32_t ir_max_iter;     /* Algorithm 2.1 i_max (10) */
     int32_t minres_max_iter; /* MINRES iteration cap (e.g. 5000) */
     uint64_t seed;           /* seed of the counter-based xi generator */
+    int32_t field;           /* log-coefficient Z = xi . Phi^T (xi ~ N(0,1)):
+                              * 0: separable exponential-covariance KL expansion
+                              *    (sigma2, corr_len; K modes by decreasing eigenvalue);
+                              * 1: the trigonometric expansion of Sec. 5.1,
+                              *    Z = sum_{j=1..K} xi_j sigma j^(-field_q) sin(2 pi j x1) cos(2 pi j x2)
+                              *    (the paper's s = K, q = field_q, omega_j = sigma xi_j ~ N(0, sigma2)) */
+    double field_q;          /* decay exponent q of field 1 (unused by field 0) */
 } mlmc_config;
 
 typedef struct {

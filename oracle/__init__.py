@@ -11,8 +11,8 @@ the accuracy rule of sec. 4.5 and Algorithm 4.1 of sec. 4.3).
 
 Functions and the passage each follows:
   kl_roots / kl_basis      -- KL expansion of the separable exponential
-                              covariance (field of the workloads; the paper's
-                              own field is the trigonometric one of sec. 5.1)
+                              covariance (field of the workloads)
+  trig_basis               -- the paper's own trigonometric field (sec. 5.1)
   solve_batch              -- exact discrete solution, Q = integral of u
                               (sec. 5.1 QoI)
   ir_f32_batch             -- Algorithm 2.1 with (u_f,u_s,u,u_r) = (s,s,d,d)
@@ -124,6 +124,21 @@ def kl_basis(n, K, sigma2, corr_len):
     Phi = np.zeros(((n + 1) * (n + 1), K))
     if _load().oracle_kl_basis(n, K, sigma2, corr_len, _p(Phi)):
         raise RuntimeError("KL basis failed")
+    return Phi
+
+
+def trig_basis(n, K, sigma2, q):
+    """Phi[(n+1)^2, K] of the trigonometric field of sec. 5.1 (the random
+    coefficient's exponent sum_{j<=s} omega_j j^-q sin(2 pi j x1) cos(2 pi j x2),
+    omega_j ~ N(0, sigma^2)), written for xi_j = omega_j / sigma ~ N(0, 1):
+    column j-1 is sigma j^-q sin(2 pi j x) cos(2 pi j y) on the nodes
+    (node p = iy*(n+1)+ix), j = 1..K (= s)."""
+    t = np.arange(n + 1) / n
+    x = np.tile(t, n + 1)          # ix fastest
+    y = np.repeat(t, n + 1)
+    Phi = np.empty(((n + 1) * (n + 1), K))
+    for j in range(1, K + 1):
+        Phi[:, j - 1] = math.sqrt(sigma2) * j ** (-float(q)) * np.sin(2 * math.pi * j * x) * np.cos(2 * math.pi * j * y)
     return Phi
 
 

@@ -34,7 +34,7 @@ struct mlmc_ctx {
     std::vector<prof_rec> prof;
     std::vector<hipEvent_t> ev_pool;
     // refinement-kernel variant per (factor dtype, log2 n), 0 = built-in default
-    int ir_variant[4][9] = {};
+    int ir_variant[5][9] = {};
     // concurrent multi-level launches: two streams per level, events, cached graph
     std::vector<hipStream_t> lstreams;
     std::vector<hipEvent_t> levents;
@@ -87,7 +87,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // A caller pointer is usable when it is NULL (optional buffers) or aligned to
 // its element size.
 inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
-inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : 2); }
+inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : (dt == MLMC_FP8 ? 1 : 2)); }
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 inline int ilog2(int v) { int l = 0; while ((1 << (l + 1)) <= v) ++l; return l; }
 
@@ -165,9 +165,34 @@ double kl_root(int k, double lam)
 
 struct kl_mode { double prod; int i, j; };
 
+// Trigonometric field of Sec. 5.1 (eq. of the random coefficient):
+// Phi[p, j-1] = sigma j^-q sin(2 pi j x) cos(2 pi j y), j = 1..K.
+void build_phit_trig(const mlmc_config &c, std::vector<std::vector<double>> &out)
+{
+    const double pi = 3.14159265358979323846, sigma = std::sqrt(c.sigma2);
+    out.assign(c.L_max + 1, {});
+    for (int l = 0; l <= c.L_max; ++l) {
+        const int n = c.n0 << l, P = (n + 1) * (n + 1);
+        std::vector<double> &ph = out[l];
+        ph.assign((size_t)c.K * P, 0.0);
+        for (int k = 0; k < c.K; ++k) {
+            const double jj = k + 1.0, amp = sigma * std::pow(jj, -c.field_q);
+            for (int iy = 0; iy <= n; ++iy) {
+                const double cy = std::cos(2.0 * pi * jj * iy / n);
+                for (int ix = 0; ix <= n; ++ix)
+                    ph[(size_t)k * P + iy * (n + 1) + ix] = amp * std::sin(2.0 * pi * jj * ix / n) * cy;
+            }
+        }
+    }
+}
+
 int build_phit(mlmc_ctx *ctx, std::vector<std::vector<double>> &out)
 {
     const mlmc_config &c = ctx->cfg;
+    if (c.field == 1) {
+        build_phit_trig(c, out);
+        return MLMC_OK;
+    }
     const double lam = c.corr_len;
     int R = 64;
     std::vector<double> w, mu, nu;
@@ -314,13 +339,21 @@ int check_level(mlmc_ctx *ctx, int level)
     return MLMC_OK;
 }
 
-int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o)
+// Options of a call on level `level`: the fine grid, and with `pair` also
+// the coarse partner (level - 1), must offer the factor dtype.
+int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o, int level, bool pair)
 {
     if (!o) return fail(ctx, MLMC_EINVAL, "opts is NULL");
-    if (o->factor_dtype < MLMC_F64 || o->factor_dtype > MLMC_F16)
+    if (o->factor_dtype < MLMC_F64 || o->factor_dtype > MLMC_FP8)
         return fail(ctx, MLMC_EINVAL, "bad factor dtype");
     if (o->solver < MLMC_DIRECT || o->solver > MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "bad solver");
     if (!(o->eps_fine >= 0.0) || !(o->eps_coarse >= 0.0)) return fail(ctx, MLMC_EINVAL, "bad eps");
+    if (o->solver == MLMC_DIRECT_IR) {
+        const int n = ctx->cfg.n0 << level;
+        if (!dtype_on_grid(o->factor_dtype, n) || (pair && level > 0 && !dtype_on_grid(o->factor_dtype, n / 2)))
+            return fail(ctx, MLMC_ENOTIMPL, "factor dtype %d is not available on the %d-cell grid", o->factor_dtype,
+                        n);
+    }
     return MLMC_OK;
 }
 
@@ -594,7 +627,7 @@ int sample_level_impl(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_
 {
     int rc = check_level(ctx, level);
     if (rc) return rc;
-    if ((rc = check_opts(ctx, opts))) return rc;
+    if ((rc = check_opts(ctx, opts, level, true))) return rc;
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n > 0 && (!xi_dev || !ws_dev)) return fail(ctx, MLMC_EINVAL, "null pointer");
     if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, MLMC_EINVAL, "workspace not 256-byte aligned");
@@ -631,7 +664,9 @@ int mlmc_create(const mlmc_config *cfg, mlmc_ctx **out)
     *out = nullptr;
     const mlmc_config &c = *cfg;
     if (c.m != 2 || !is_pow2(c.n0) || c.n0 < 4 || c.L_max < 0 || (c.n0 << c.L_max) > 256 ||
-        c.K < 1 || c.K > 512 || !(c.sigma2 >= 0.0) || !(c.corr_len > 0.0) || !std::isfinite(c.f) ||
+        c.K < 1 || c.K > 512 || !(c.sigma2 >= 0.0) || c.field < 0 || c.field > 1 ||
+        (c.field == 0 && !(c.corr_len > 0.0)) || (c.field == 1 && !(c.field_q >= 0.0 && c.field_q < 1e3)) ||
+        !std::isfinite(c.f) ||
         !(c.k_p > 0.0 && c.k_p < 1.0) || c.ir_max_iter < 0 || c.L_max > 15 || !(c.alpha > 0.0) ||
         !(c.beta > 0.0) || !(c.gamma > 0.0) || !std::isfinite(c.alpha + c.beta + c.gamma))
         return MLMC_EINVAL;
@@ -753,7 +788,7 @@ int mlmc_solve(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
 {
     int rc = check_level(ctx, level);
     if (rc) return rc;
-    if ((rc = check_opts(ctx, opts))) return rc;
+    if ((rc = check_opts(ctx, opts, level, false))) return rc;
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n == 0) return MLMC_OK;
     if (!xi_dev || !ws_dev || !q_dev) return fail(ctx, MLMC_EINVAL, "null pointer");
@@ -794,7 +829,7 @@ int mlmc_sample_level_noalloc(mlmc_ctx *ctx, int32_t level, int64_t n, const dou
 {
     int rc = check_level(ctx, level);
     if (rc) return rc;
-    if ((rc = check_opts(ctx, opts))) return rc;
+    if ((rc = check_opts(ctx, opts, level, true))) return rc;
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (!ctx->scratch) return fail(ctx, MLMC_EHIP, "no scratch address for device %d", ctx->device);
     const size_t need = make_level_layout(ctx->cfg, level, n, *opts).bytes;
@@ -837,7 +872,7 @@ int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, c
     for (int i = 0; i < n_levels; ++i) {
         int rc = check_level(ctx, levels[i]);
         if (rc) return rc;
-        if ((rc = check_opts(ctx, &opts[i]))) return rc;
+        if ((rc = check_opts(ctx, &opts[i], levels[i], true))) return rc;
         if (n[i] < 0 || n[i] > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
         if (n[i] > 0 && !xi_dev[i]) return fail(ctx, MLMC_EINVAL, "null xi");
         if (!aligned(xi_dev[i], 8) || (y_dev && !aligned(y_dev[i], 8)))
@@ -949,7 +984,7 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
 {
     int rc = check_level(ctx, level);
     if (rc) return rc;
-    if ((rc = check_opts(ctx, opts))) return rc;
+    if ((rc = check_opts(ctx, opts, level, true))) return rc;
     if (n < 1 || !xi_dev || !ws_dev) return fail(ctx, MLMC_EINVAL, "autotune: bad arguments");
     const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
     if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
@@ -1026,6 +1061,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
         o.solver = mixed ? solver : MLMC_DIRECT;
         o.promote = 1;
+        if (int rc_o = check_opts(ctx, &o, l, true)) return rc_o;
         int64_t ch = chunk_max;
         while (ch > 16) {
             const size_t b = make_level_layout(c, l, ch, o).bytes;
@@ -1311,7 +1347,7 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, con
 {
     int rc = check_level(ctx, level);
     if (rc) return rc;
-    if ((rc = check_opts(ctx, opts))) return rc;
+    if ((rc = check_opts(ctx, opts, level, false))) return rc;
     if (opts->solver == MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not MINRES)");
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n == 0) return MLMC_OK;

@@ -23,6 +23,9 @@ enum : uint32_t {
 // and n >= 64 (MFMA kernels), the tile kernels being faster at n = 32.  The
 // grids below 16 keep the tile kernels.
 inline bool use_blk(int dtype, int n) { return n == 16 || n >= (dtype == 0 ? 64 : 16); }
+// Grids on which a factor dtype is available: FP8 (code 4) on the grids
+// below 16 (the tile kernels) only.
+inline bool dtype_on_grid(int dtype, int n) { return dtype != 4 || n < 16; }
 
 size_t factor_entries_per_sample(int dtype, int n);
 

@@ -647,6 +647,27 @@ hipError_t launch_ir_m(const ir_args &g, hipStream_t st)
 }
 
 
+// FP8 storage: the grids below 16 only (the tile kernels)
+hipError_t launch_factor_fp8(int M, int nb, const double *beta, const double *gam, void *factor,
+                             const int *idx, const int *count, int64_t slot_base, uint32_t *state,
+                             hipStream_t st)
+{
+    switch (M) {
+    case 4: return launch_factor_t<fp8e4m3, 4>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    case 8: return launch_factor_t<fp8e4m3, 8>(nb, beta, gam, factor, idx, count, slot_base, state, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ir_fp8(const ir_args &g, hipStream_t st)
+{
+    switch (g.n) {
+    case 4: return launch_ir_t<fp8e4m3, 4>(g, st);
+    case 8: return launch_ir_t<fp8e4m3, 8>(g, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename Tst>
 hipError_t launch_factor_m(int M, int nb, const double *beta, const double *gam, void *factor,
                            const int *idx, const int *count, int64_t slot_base, uint32_t *state,
@@ -728,6 +749,7 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double 
     case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     case 2: return launch_factor_m<__hip_bfloat16>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     case 3: return launch_factor_m<__half>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
+    case 4: return launch_factor_fp8(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     }
     return hipErrorInvalidValue;
 }
@@ -741,6 +763,7 @@ hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st)
     case 1: return launch_ir_m<float>(g, st);
     case 2: return launch_ir_m<__hip_bfloat16>(g, st);
     case 3: return launch_ir_m<__half>(g, st);
+    case 4: return launch_ir_fp8(g, st);
     }
     return hipErrorInvalidValue;
 }

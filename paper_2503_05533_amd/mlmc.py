@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmlmc.so")
 
 MLMC_OK, MLMC_ENOCONV = 0, 1
 MLMC_EINVAL, MLMC_ENOMEM, MLMC_EHIP, MLMC_ENOTIMPL = -1, -2, -3, -4
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "fp8": 4}
 SOLVERS = {"direct": 0, "direct_ir": 1, "minres": 2}
 ST_CONVERGED, ST_PROMOTED, ST_NONFINITE, ST_IMAX = 1, 2, 4, 8
 
@@ -39,7 +39,7 @@ class _Config(ctypes.Structure):
                 ("f", ctypes.c_double), ("k_p", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("ir_max_iter", ctypes.c_int32), ("minres_max_iter", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("field", ctypes.c_int32), ("field_q", ctypes.c_double)]
 
 
 class _LevelOpts(ctypes.Structure):
@@ -131,6 +131,8 @@ class Config:
     ir_max_iter: int = 10
     minres_max_iter: int = 5000
     seed: int = 1
+    field: int = 0        # 0: exponential-covariance KL; 1: trigonometric field of sec. 5.1
+    field_q: float = 2.0  # decay exponent q of the trigonometric field
 
 
 def _ptr(t):

@@ -403,3 +403,59 @@ def test_odd_mode_counts(K):
         qref = oracle.solve_batch(n, _phi(n, K, s2, lam), xr)
         assert np.all(np.abs(out["q"].cpu().numpy() - qref) / qref <= 1e-12), (K, level)
     ctx.close()
+
+
+# ----------------------------------------------------------------- the paper's field, FP8 factors
+
+def test_trig_field_basis_and_fp64():
+    """field = 1 (the trigonometric field of sec. 5.1, s = 4, q = 2,
+    sigma = 2 as in the paper's first example): the library's basis equals
+    the oracle's and FP64 Q is within 1e-12 of the oracle's exact solve."""
+    torch = _torch()
+    K, s2, q, seed = 4, 4.0, 2.0, 31
+    ctx = _ctx(n0=8, L_max=3, K=K, sigma2=s2, corr_len=0.3, seed=seed, field=1, field_q=q)
+    for level, S in ((0, 50), (1, 40), (2, 30), (3, 12)):
+        n = 8 << level
+        phi = oracle.trig_basis(n, K, s2, q)
+        got = ctx.kl_basis(level).cpu().numpy().T
+        assert np.max(np.abs(got - phi)) <= 1e-14, level
+        xi = si.splitmix64_normals(seed, level, 0, S, K)
+        out = ctx.solve(level, torch.from_numpy(xi), dtype="f64", solver="direct")
+        qref = oracle.solve_batch(n, phi, xi)
+        assert np.all(np.abs(out["q"].cpu().numpy() - qref) / qref <= 1e-12), level
+    ctx.close()
+
+
+@pytest.mark.parametrize("eps", [4e-2, 1e-3, 1e-6])
+def test_fp8_factor_on_coarse_grids(eps):
+    """FP8 (E4M3) factor storage on the 4- and 8-cell grids (the paper's
+    quarter-precision coarsest level, h_0 = 1/4, trigonometric field with
+    s = 1, sigma = 1): every sample reaches eps, with promotion to an FP64
+    factor where the FP8 factor does not within i_max, and Q obeys the
+    residual bound against the oracle; the 16-cell grid refuses FP8."""
+    torch = _torch()
+    from paper_2503_05533_amd import MLMCError
+    K, s2, q, seed = 1, 1.0, 2.0, 32
+    ctx = _ctx(n0=4, L_max=2, K=K, sigma2=s2, corr_len=0.3, seed=seed, field=1, field_q=q)
+    for level, S in ((0, 300), (1, 200)):
+        n = 4 << level
+        xi = si.splitmix64_normals(seed, level, 0, S, K)
+        out = ctx.solve(level, torch.from_numpy(xi), dtype="fp8", solver="direct_ir", eps=eps,
+                        promote=True, want_u=True)
+        st = out["status"].cpu().numpy()
+        it = out["iters"].cpu().numpy()
+        _say("fp8 n=%d eps=%.0e: promoted %d, corrections %s" % (n, eps, int(np.count_nonzero(st & 2)),
+                                                                  np.bincount(it).tolist()))
+        assert out["rc"] == 0 and np.all(st & 1)
+        phi = oracle.trig_basis(n, K, s2, q)
+        qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
+        rr = oracle.relres_batch(n, phi, xi, out["u"].cpu().numpy())
+        assert np.all(rr < eps * (1 + 1e-6))
+        dq = np.abs(out["q"].cpu().numpy() - qref) / qref
+        assert np.all(dq <= rr * _bound(n, uref, qref) * (1 + 1e-6) + 1e-14)
+    lv = ctx.sample_level(1, torch.from_numpy(si.splitmix64_normals(seed, 1, 0, 64, K)), dtype="fp8",
+                          solver="direct_ir", eps_fine=eps, eps_coarse=eps)
+    assert lv["rc"] == 0 and lv["stats"]["n_noconv"] == 0
+    with pytest.raises(MLMCError, match="not available"):
+        ctx.solve(2, torch.zeros((4, K), dtype=torch.float64), dtype="fp8", solver="direct_ir", eps=eps)
+    ctx.close()

@@ -500,3 +500,36 @@ def test_general_precision_choice_reduces_to_fem_rule():
     assert d[0] == pytest.approx(math.sqrt(0.05 * h[0] ** 3), rel=1e-14)
     assert d[4] == pytest.approx(min(math.sqrt(0.05 * h[4] ** 3), 0.05 * h[4] ** 2), rel=1e-14)
     assert d[4] == pytest.approx(0.05 * h[4] ** 2, rel=1e-14)
+
+
+def test_trig_basis_hand_values():
+    """The trigonometric field of sec. 5.1 at nodes where the sines and
+    cosines are exact: (x, y) = (1/4, 0): sin(j pi/2) cos 0 = 1, 0, -1, 0;
+    (1/8, 1/8): sin(j pi/4) cos(j pi/4) = 1/2, 0, -1/2, 0; x = 1/2 or 0: 0.
+    Swapping the roles of x and y (sin on y) or dropping the j^-q decay fails."""
+    n, K, s2, q = 8, 4, 4.0, 2.0   # sigma = 2, as in the paper's first example
+    Phi = oracle.trig_basis(n, K, s2, q)
+
+    def node(ix, iy):
+        return Phi[iy * (n + 1) + ix]
+
+    sig = 2.0
+    assert np.allclose(node(2, 0), sig * np.array([1.0, 0.0, -1.0 / 9.0, 0.0]), atol=1e-15)
+    assert np.allclose(node(1, 1), sig * np.array([0.5, 0.0, -0.5 / 9.0, 0.0]), atol=1e-15)
+    assert np.allclose(node(4, 3), 0.0, atol=1e-15) and np.allclose(node(0, 5), 0.0, atol=1e-15)
+    # (x, y) = (1/8, 1/4): sin(j pi/4) cos(j pi/2) = 0, -1 * 1 ... j=2: sin(pi/2) cos(pi) = -1
+    assert np.allclose(node(1, 2), sig * np.array([0.0, -1.0 / 4.0, 0.0, 0.0]), atol=1e-15)
+
+
+def test_trig_field_sigma0_and_symmetry():
+    """sigma = 0 gives a = 1 and the closed-form Laplace value; with one term
+    the field is odd under x -> 1 - x (sin(2 pi (1-x)) = -sin(2 pi x)), so
+    flipping the sign of xi mirrors the problem and leaves Q unchanged."""
+    n = 16
+    Q0 = oracle.solve_batch(n, oracle.trig_basis(n, 1, 0.0, 2.0), np.array([[1.3]]))
+    assert abs(Q0[0] - 0.034702752313896) <= 1e-13 * 0.0347
+    Phi = oracle.trig_basis(n, 1, 1.0, 2.0)
+    xi = np.array([[0.9], [-0.9]])
+    Q = oracle.solve_batch(n, Phi, xi)
+    assert abs(Q[0] - Q[1]) <= 1e-13 * Q[0]
+    assert abs(Q[0] - Q0[0]) > 1e-4 * Q0[0]  # the field does change Q
