@@ -13,16 +13,24 @@ the timed region.
 
 Legs:
   * timed: W warm-up steps, then K steps between two device synchronisations
-    (the value);
+    (the value); a step draws every level's xi on the device (counter-based
+    generator) and runs all levels;
   * profiled: the same K steps launched eagerly with HIP events around each
     kernel launch on its own stream (per-kernel device time; the roofline of
     the dominant kernel);
   * per level: each level alone, event-timed (samples/s per level);
   * FP64: the same timed leg with the FP64 direct path;
   * time to RMSE: Algorithm 4.1 (adaptive MLMC) to an absolute tolerance,
-    mixed and FP64, wall time on the host of the second of two identical
-    runs (the first allocates the estimator's workspace);
-  * CPU: the FP64 oracle on a bounded sample of the workload, host cores.
+    mixed and FP64, over R seeds: median wall time on the host (the first
+    call allocates the estimator's workspace and is not counted) and the
+    achieved RMSE against an FP64 reference at TOL/5, with a 95% interval;
+  * other workloads (legs): the single-level FP64 workload, the per-level
+    precision sweep (FP32/BF16/FP16 and FP64 per level), all five levels in
+    one captured graph (refinement vs MINRES), the adjoint batch, and the
+    paper's quarter-precision example (FP8 factor on level 0, fixed N_l,
+    MSE against FP64 over many runs with shared xi, stored-bytes count);
+  * CPU: the FP64 oracle on a bounded sample of the workload, host cores,
+    one core, and LAPACK's banded Cholesky on the same systems.
 
 Prints one JSON line.  --gpus N > 1 is refused: the path runs on one GPU.
 """
@@ -37,7 +45,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PDE samples/s per level + MLMC time-to-RMSE, mixed+IR vs FP64 on same GPU"
 PEAK = {"f64": 78.6, "f32": 157.3, "hbm": 8000.0}  # TFLOP/s (FP64, FP32 MFMA), GB/s
-DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}  # factor storage bytes
 
 
 # HBM bytes per sample measured with FETCH_SIZE / WRITE_SIZE counters (scaled
@@ -111,6 +119,10 @@ def parse():
     p.add_argument("--ttr-tol", type=float, default=2e-5,
                    help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--ttr-runs", type=int, default=20, help="seeds of the time-to-RMSE leg")
+    p.add_argument("--legs", default="c0,c2,c3,c4,q43",
+                   help="comma-separated other-workload legs to run (empty: none)")
+    p.add_argument("--q43-runs", type=int, default=1000, help="runs of the quarter-precision leg")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run one plain streaming kernel (y = 2x, FP32) over this many MiB first; "
                         "its HBM counters calibrate the kernel traffic counters")
@@ -119,6 +131,337 @@ def parse():
 
 def log(*a):
     print("bench:", *a, flush=True)
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _ctx_for(wname, **over):
+    import seeded_inputs as si
+    from paper_2503_05533_amd import MLMC, Config
+    w = si.workload(wname)
+    kw = dict(n0=w["n0"], L_max=max(w["levels"]), K=w["K"], sigma2=w["sigma2"], corr_len=w["corr_len"],
+              seed=w["seed"], ir_max_iter=10, field=w.get("field", 0), field_q=w.get("field_q", 2.0),
+              k_p=w.get("k_p", 0.05))
+    kw.update(over)
+    return w, MLMC(Config(**kw), device="cuda:0")
+
+
+def _event_ms(fn, reps=2):
+    """Device time of fn() (one untimed call first), mean over reps."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _ci95_mse(err):
+    """MSE of the errors and a 95% bootstrap interval (2000 resamples)."""
+    import numpy as np
+    err = np.asarray(err, dtype=float)
+    mse = float(np.mean(err ** 2))
+    rng = np.random.default_rng(12345)
+    bs = np.mean(err[rng.integers(0, len(err), size=(2000, len(err)))] ** 2, axis=1)
+    return mse, [float(np.quantile(bs, 0.025)), float(np.quantile(bs, 0.975))]
+
+
+def leg_time_to_rmse(ctx, a, L, seed0):
+    """Algorithm 4.1 at TOL over R seeds, mixed and FP64 with the same seed per
+    run (shared xi); the reference is one FP64 run at TOL/5 with a seed of its
+    own.  Reports the median host wall time per run and the achieved RMSE
+    against the reference with a 95% bootstrap interval."""
+    import numpy as np
+    tol, R = a.ttr_tol, a.ttr_runs
+    out = dict(tol=tol, runs=R)
+    ctx.set_seed(seed0 + 7777)
+    ref = ctx.estimate(tol / 5, n_init=1000, dtypes=["f64"] * (L + 1), solver="direct", mixed=False)
+    out["reference"] = dict(tol=tol / 5, estimate=ref["estimate"], rmse_est=ref["var_est"] ** 0.5, N=ref["N"],
+                            L=ref["L"])
+    paths = [("mixed", [a.dtype] * (L + 1), "direct_ir", True)]
+    if not a.no_fp64:
+        paths.append(("fp64", ["f64"] * (L + 1), "direct", False))
+    for name, d, solver, mixed in paths:
+        ctx.set_seed(seed0)
+        ctx.estimate(tol, n_init=1000, dtypes=d, solver=solver, mixed=mixed)  # allocates the workspace
+        walls, ests, Ls, N0 = [], [], [], []
+        for r in range(R):
+            ctx.set_seed(seed0 + r)
+            res = ctx.estimate(tol, n_init=1000, dtypes=d, solver=solver, mixed=mixed)
+            walls.append(res["wall_s"])
+            ests.append(res["estimate"])
+            Ls.append(res["L"])
+            N0.append(res["N"][0])
+        mse, ci = _ci95_mse(np.array(ests) - ref["estimate"])
+        out[name] = dict(median_wall_s=float(np.median(walls)), min_wall_s=float(np.min(walls)),
+                         rmse=mse ** 0.5, rmse_ci95=[ci[0] ** 0.5, ci[1] ** 0.5],
+                         rmse_over_tol=mse ** 0.5 / tol, L_counts={str(k): Ls.count(k) for k in sorted(set(Ls))},
+                         mean_N0=float(np.mean(N0)))
+        log("time to RMSE %s" % name, out[name])
+    ctx.set_seed(seed0)
+    if "fp64" in out:
+        out["speedup"] = out["fp64"]["median_wall_s"] / out["mixed"]["median_wall_s"]
+    return out
+
+
+def leg_c0(a):
+    """single_n32_K16: one level, n = 32, K = 16, 1000 samples; FP64 direct
+    (and the FP32 factor with FP64 refinement to 1e-10), xi drawn in the step."""
+    w, ctx = _ctx_for("single_n32_K16")
+    N = w["N"][0]
+    xi = ctx.fill_xi(0, 0, N)
+    out = dict(workload="single_n32_K16", N=N)
+    for name, o in (("fp64", dict(dtype="f64", solver="direct")),
+                    ("mixed_f32_ir_1e-10", dict(dtype="f32", solver="direct_ir", eps_fine=1e-10))):
+        plan = ctx.plan_levels([0], [xi], [o], use_graph=False)
+
+        def run():
+            ctx.fill_xi(0, 0, N, out=xi)
+            plan.run()
+        ms = _event_ms(run, reps=5)
+        out[name] = dict(ms=ms, samples_per_s=N / (ms / 1e3))
+    ctx.close()
+    return out
+
+
+def leg_c2(a):
+    """sweep5_n16-256_K128: each level alone with each factor precision
+    (FP32, BF16, FP16 with FP64 refinement to delta_l; FP64 direct):
+    samples/s, promotions and mean corrections per level."""
+    w, ctx = _ctx_for("sweep5_n16-256_K128")
+    L = max(w["levels"])
+    eps = ctx.accuracy_targets(L)
+    out = dict(workload="sweep5_n16-256_K128", eps=eps, levels={})
+    for l, N in zip(w["levels"], w["N"]):
+        xi = ctx.fill_xi(l, 0, N)
+        row = {}
+        for dt in ("f64", "f32", "bf16", "f16"):
+            o = dict(dtype=dt, solver="direct" if dt == "f64" else "direct_ir", eps_fine=eps[l],
+                     eps_coarse=eps[l - 1] if l else 0.0)
+            plan = ctx.plan_levels([l], [xi], [o], use_graph=False)
+            ms = _event_ms(plan.run, reps=2)
+            st = plan.run(stats=True)["stats"][0]
+            row[dt] = dict(ms=ms, samples_per_s=N / (ms / 1e3), promoted=st["n_promoted"],
+                           noconv=st["n_noconv"], mean_corrections=st["mean_iters"],
+                           mean_corrections_coarse=st["mean_iters_coarse"])
+            del plan
+        best = min((d for d in ("f32", "bf16", "f16") if row[d]["noconv"] == 0), key=lambda d: row[d]["ms"])
+        row["fastest_mixed"] = best
+        row["speedup_vs_fp64"] = row["f64"]["ms"] / row[best]["ms"]
+        out["levels"][str(ctx.level_cells(l))] = row
+        del xi
+    ctx.close()
+    return out
+
+
+def leg_c3(a):
+    """batched5_n16-256_K128: all five levels (40000 ... 200 samples) as one
+    replayed HIP graph, FP32 factor + FP64 refinement against batched MINRES,
+    both to delta_l; and the eager schedule for the refinement path."""
+    w, ctx = _ctx_for("batched5_n16-256_K128", minres_max_iter=20000)
+    levels, Ns = w["levels"], w["N"]
+    L = max(levels)
+    eps = ctx.accuracy_targets(L)
+    xis = [ctx.fill_xi(l, 0, N) for l, N in zip(levels, Ns)]
+    out = dict(workload="batched5_n16-256_K128", N=Ns, eps=eps)
+    for name, solver, graph in (("direct_ir_graph", "direct_ir", True), ("direct_ir_eager", "direct_ir", False),
+                                ("minres_graph", "minres", True)):
+        o = [dict(dtype="f32", solver=solver, eps_fine=eps[l], eps_coarse=eps[l - 1] if l else 0.0)
+             for l in levels]
+        plan = ctx.plan_levels(levels, xis, o, use_graph=graph)
+        ms = _event_ms(plan.run, reps=3)
+        st = plan.run(stats=True)["stats"]
+        out[name] = dict(ms=ms, samples_per_s=sum(Ns) / (ms / 1e3),
+                         mean_iters=[x["mean_iters"] for x in st], noconv=[x["n_noconv"] for x in st])
+        del plan
+    out["direct_ir_vs_minres"] = out["minres_graph"]["ms"] / out["direct_ir_graph"]["ms"]
+    ctx.close()
+    return out
+
+
+def leg_c4(a):
+    """adjoint_n128_K128: dQ/dxi for 4096 samples at n = 128 (FP32 factor
+    reused by the adjoint, FP64 refinement): the forward solve and the
+    adjoint, at 1e-10 and at 1e-5."""
+    import torch
+    w, ctx = _ctx_for("adjoint_n128_K128")
+    N = w["N"][0]
+    xi = ctx.fill_xi(0, 0, N)
+    out = dict(workload="adjoint_n128_K128", N=N)
+    for eps in (1e-10, 1e-5):
+        fw = ctx.solve(0, xi, dtype="f32", solver="direct_ir", eps=eps, promote=True, own_workspace=True)
+        ms_f = _event_ms(lambda: ctx.solve(0, xi, dtype="f32", solver="direct_ir", eps=eps, promote=True),
+                         reps=2)
+        fw = ctx.solve(0, xi, dtype="f32", solver="direct_ir", eps=eps, promote=True, own_workspace=True)
+        ws = fw["ws"]
+        ms_g = _event_ms(lambda: ctx.grad_from(0, xi, ws, None, eps_adjoint=eps, dtype="f32",
+                                               solver="direct_ir", eps=eps), reps=2)
+        out["eps_%g" % eps] = dict(forward_ms=ms_f, adjoint_ms=ms_g,
+                                   gradients_per_s=N / ((ms_f + ms_g) / 1e3))
+        del fw, ws
+        torch.cuda.synchronize()
+    ctx.close()
+    return out
+
+
+def stored_bytes(n, dtype, trips):
+    """Bytes of the factor and the vectors one solve computes and stores
+    (the paper's memory-reference count of sec. 5.2, each entry at the
+    precision this library stores it in): the stored factor, plus the FP64
+    vectors z and x of the initial solve and r, z, x of every correction
+    (FP64 direct: z and x)."""
+    b = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[dtype]
+    m = n - 1
+    vec = m * n
+    return factor_entries(n, dtype if dtype in DT_BYTES else "f32") * b + vec * 8 * (2 + 3 * trips)
+
+
+def leg_q43(a):
+    """The paper's quarter-precision example (sec. 5.2): h0 = 1/4 (4..32
+    cells), trigonometric field s = 1, sigma = 1, k_p = 0.4; N_l from one
+    standard (FP64) adaptive run at TOL^2 = 2e-6; then R runs with those N_l,
+    each with fresh xi shared by the mixed path (FP8 factor on level 0,
+    FP16 on levels 1-3, FP64 refinement to delta_l) and the FP64 direct path;
+    MSE of both against an FP64 reference (adaptive at TOL/10), the relative
+    MSE difference, and the stored-bytes ratio."""
+    import numpy as np
+    w, ctx = _ctx_for("q43_n4-32_trig1")
+    L = max(w["levels"])
+    tol = (2e-6) ** 0.5
+    n_init = 100  # the paper does not state its initial sample count; 100 leaves N_l to the variance
+    ctx.set_seed(w["seed"] + 1)
+    ref = ctx.estimate(tol / 10, n_init=n_init, dtypes=["f64"] * (L + 1), solver="direct", mixed=False)
+    ctx.set_seed(w["seed"])
+    std = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * (L + 1), solver="direct", mixed=False)
+    Lr = std["L"]
+    N = std["N"]
+    eps = ctx.accuracy_targets(Lr)
+    dts = ["fp8"] + ["f16"] * Lr
+    R = a.q43_runs
+    est = {"mixed": [], "fp64": []}
+    trips = {"mixed": np.zeros((Lr + 1, 2)), "fp64": np.zeros((Lr + 1, 2))}
+    promoted = np.zeros(Lr + 1, dtype=np.int64)
+    noconv = {"mixed": 0, "fp64": 0}
+    gpu_ms = {"mixed": 0.0, "fp64": 0.0}
+    for r in range(R):
+        q = {"mixed": 0.0, "fp64": 0.0}
+        for l in range(Lr + 1):
+            xi = ctx.fill_xi(l, r * N[l], N[l])
+            for name, o in (("mixed", dict(dtype=dts[l], solver="direct_ir", eps_fine=eps[l],
+                                           eps_coarse=eps[l - 1] if l else 0.0)),
+                            ("fp64", dict(dtype="f64", solver="direct"))):
+                res = ctx.sample_level(l, xi, **o)
+                st = res["stats"]
+                noconv[name] += st["n_noconv"]
+                q[name] += st["sum_y"] / N[l]
+                trips[name][l] += (st["mean_iters"], st["mean_iters_coarse"])
+                gpu_ms[name] += st["gpu_ms"]
+                if name == "mixed":
+                    promoted[l] += st["n_promoted"]
+        for k in q:
+            est[k].append(q[k])
+    out = dict(workload="q43_n4-32_trig1", tol=tol, runs=R, N=N, L=Lr, eps=eps, precision=dts,
+               reference=dict(tol=tol / 10, estimate=ref["estimate"], N=ref["N"]))
+    for k in est:
+        mse, ci = _ci95_mse(np.array(est[k]) - ref["estimate"])
+        out[k] = dict(mse=mse, mse_ci95=ci, gpu_ms_per_run=gpu_ms[k] / R)
+    d = np.array(est["mixed"]) - np.array(est["fp64"])
+    out["mse_rel_diff"] = out["mixed"]["mse"] / out["fp64"]["mse"] - 1.0
+    out["rmse_rel_diff"] = (out["mixed"]["mse"] / out["fp64"]["mse"]) ** 0.5 - 1.0
+    out["max_abs_estimate_diff"] = float(np.max(np.abs(d)))
+    out["promoted_per_level"] = promoted.tolist()
+    out["noconv"] = noconv
+    mean_trips = trips["mixed"] / R
+    out["mean_corrections"] = mean_trips.tolist()
+    # stored bytes per level (fine + coarse solve of every Y_l sample)
+    by_m, by_d = [], []
+    for l in range(Lr + 1):
+        nf = w["n0"] << l
+        bm = stored_bytes(nf, dts[l], mean_trips[l][0]) + (stored_bytes(nf // 2, dts[l], mean_trips[l][1]) if l else 0)
+        bd = stored_bytes(nf, "f64", 0) + (stored_bytes(nf // 2, "f64", 0) if l else 0)
+        by_m.append(N[l] * bm)
+        by_d.append(N[l] * bd)
+    # the same count with the vectors at the paper's precisions for this example
+    # (level 0 qhhh: u = u_r = half; levels 1-3 hhss: u = u_r = single; the
+    # FP64 reference: double), on the same correction counts
+    vb = [2] + [4] * Lr
+    by_p = []
+    for l in range(Lr + 1):
+        nf = w["n0"] << l
+        fb = {"fp8": 1, "f16": 2}[dts[l]]
+        per = 0.0
+        for nn, t in ([(nf, mean_trips[l][0])] + ([(nf // 2, mean_trips[l][1])] if l else [])):
+            per += factor_entries(nn, "f32") * fb + (nn - 1) * nn * vb[l] * (2 + 3 * t)
+        by_p.append(N[l] * per)
+    out["stored_bytes_ratio_paper_precisions"] = sum(by_d) / sum(by_p)
+    out["stored_bytes_ratio_per_level"] = [x / y for x, y in zip(by_d, by_m)]
+    out["stored_bytes_ratio_total"] = sum(by_d) / sum(by_m)
+    out["factor_bytes_ratio_total"] = sum(
+        N[l] * (factor_entries(w["n0"] << l, "f64") * 8 + (factor_entries((w["n0"] << l) // 2, "f64") * 8 if l else 0))
+        for l in range(Lr + 1)) / sum(
+        N[l] * (factor_entries(w["n0"] << l, "f32") * {"fp8": 1, "f16": 2}[dts[l]]
+                + (factor_entries((w["n0"] << l) // 2, "f32") * {"fp8": 1, "f16": 2}[dts[l]] if l else 0))
+        for l in range(Lr + 1))
+    ctx.close()
+    return out
+
+
+def cpu_single_and_lapack(oracle, si, w, ctx, levels, Ns, phis, budget):
+    """One-core oracle time and LAPACK's banded Cholesky (dpbtrf/dpbtrs via
+    SciPy, on the band matrices the oracle assembles; the assembly is not
+    timed) on bounded samples, scaled to the workload like the main line."""
+    import numpy as np
+    import scipy.linalg as sl
+    nthr = oracle.num_threads()
+    K = w["K"]
+    t1, tl, desc = [], [], []
+    per = budget / len(levels)
+    for l, N in zip(levels, Ns):
+        nf = ctx.level_cells(l)
+        grids = [nf, nf // 2] if l > 0 else [nf]
+        # one core
+        oracle.set_threads(1)
+        xi = si.splitmix64_normals(w["seed"], l, 0, 1, K)
+        t0 = time.perf_counter()
+        for nn in grids:
+            oracle.solve_batch(nn, phis[nn], xi)
+        dt = time.perf_counter() - t0
+        s = int(max(1, min(N, per / 2 / max(dt, 1e-9))))
+        xi = si.splitmix64_normals(w["seed"], l, 0, s, K)
+        t0 = time.perf_counter()
+        for nn in grids:
+            oracle.solve_batch(nn, phis[nn], xi)
+        t1.append((time.perf_counter() - t0) / s)
+        oracle.set_threads(nthr)
+        # LAPACK banded Cholesky, one process
+        s2 = max(1, min(s, 64))
+        tt = 0.0
+        for k in range(s2):
+            for nn in grids:
+                ab = oracle.band_matrix(nn, phis[nn], xi[k:k + 1])
+                b = np.full(ab.shape[1], 1.0 / nn ** 2)
+                t0 = time.perf_counter()
+                sl.solveh_banded(ab, b, lower=True, check_finite=False)
+                tt += time.perf_counter() - t0
+        tl.append(tt / s2)
+        desc.append("%d/%d" % (s, N))
+    total = float(sum(Ns))
+    return dict(single_core_value=total / sum(t * N for t, N in zip(t1, Ns)),
+                lapack_band_value=total / sum(t * N for t, N in zip(tl, Ns)),
+                lapack_band_kind="scipy.linalg.solveh_banded (LAPACK dpbtrf/dpbtrs), one process",
+                single_core_sample="oracle with one thread on the first %s samples per level" % ",".join(desc))
 
 
 def main():
@@ -166,13 +509,20 @@ def main():
         log("autotuned refinement variants", tuned)
     total = float(sum(Ns))
 
+    def step(plan):
+        # a step draws every level's xi into the plan's input buffers, then
+        # runs all levels (both on the current stream's order)
+        for i, l in enumerate(plan.levels):
+            ctx.fill_xi(l, 0, plan.xis[i].shape[0], out=plan.xis[i])
+        plan.run()
+
     def timed(plan, steps, warmup):
         for _ in range(warmup):
-            plan.run()
+            step(plan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            plan.run()
+            step(plan)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
@@ -185,12 +535,12 @@ def main():
 
     # ---- profiled leg: the same concurrent step launched eagerly
     eager = ctx.plan_levels(levels, xis, om, use_graph=False)
-    eager.run()
+    step(eager)
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        eager.run()
+        step(eager)
     torch.cuda.synchronize()
     ms_eager = (time.perf_counter() - t0) * 1e3 / a.steps
     prof = {}
@@ -282,26 +632,10 @@ def main():
                     per_level_samples_per_s=None if a.no_per_level else per_level(o64))
         del plan_d
 
-    # ---- time to RMSE: Algorithm 4.1 at an absolute tolerance
+    # ---- time to RMSE: Algorithm 4.1 at an absolute tolerance, R seeds
     ttr = None
     if a.ttr_tol > 0:
-        dts = [a.dtype] * (L + 1)
-        ttr = dict(tol=a.ttr_tol)
-        runs = [("mixed", dts, "direct_ir", True)]
-        if not a.no_fp64:
-            runs.append(("fp64", ["f64"] * (L + 1), "direct", False))
-        for name, d, solver, mixed in runs:
-            # one untimed run first: the estimator's workspace (tens of GB)
-            # is allocated on the first call and kept by the context
-            ctx.estimate(a.ttr_tol, n_init=1000, dtypes=d, solver=solver, mixed=mixed)
-            res = ctx.estimate(a.ttr_tol, n_init=1000, dtypes=d, solver=solver, mixed=mixed)
-            ttr[name] = dict(wall_s=res["wall_s"], gpu_ms=res["gpu_ms"], estimate=res["estimate"],
-                             rmse_est=res["var_est"] ** 0.5, L=res["L"], N=res["N"],
-                             converged=res["converged"])
-            log("time to RMSE %s" % name, ttr[name])
-        if "fp64" in ttr:
-            ttr["speedup"] = ttr["fp64"]["wall_s"] / ttr["mixed"]["wall_s"]
-
+        ttr = leg_time_to_rmse(ctx, a, L, w["seed"])
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not a.no_cpu:
@@ -334,8 +668,23 @@ def main():
         cpu_time = sum(t * N for t, N in zip(t_per, Ns))
         cpu = dict(value=total / cpu_time, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
                    sample="FP64 banded Cholesky on the first %s samples of each level (fine+coarse), "
-                          "per-sample time scaled to the full workload" % ",".join(samples_desc))
+                          "per-sample time scaled to the full workload" % ",".join(samples_desc),
+                   cpu_model=cpu_model())
+        cpu.update(cpu_single_and_lapack(oracle, si, w, ctx, levels, Ns, phis, a.cpu_seconds / 3))
         log("cpu oracle", cpu)
+
+    # ---- other workloads
+    legs = {}
+    sel = [x for x in a.legs.split(",") if x]
+    ctx_main = ctx
+    for name in sel:
+        fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43}[name]
+        t0 = time.perf_counter()
+        legs[name] = fn(a)
+        legs[name]["leg_wall_s"] = time.perf_counter() - t0
+        log("leg %s" % name, legs[name])
+        torch.cuda.empty_cache()
+    ctx = ctx_main
 
     line = {
         "metric": METRIC,
@@ -350,6 +699,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
+        "xi_in_step": True,
         "config": {"workload": a.workload, "cells": cells, "N_l": Ns, "K": K,
                    "sigma2": w["sigma2"], "corr_len": w["corr_len"], "eps_l": eps,
                    "path": "%s factor + FP64 residual/refinement/sums, all levels concurrent, "
@@ -364,6 +714,7 @@ def main():
         "eager_ms_per_step": ms_eager,
         "kernel_ms_per_step": {"%s_n%d" % k: v["ms"] / a.steps for k, v in sorted(prof.items())},
         "autotuned": tuned,
+        "legs": legs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

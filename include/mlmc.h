@@ -178,6 +178,11 @@ size_t mlmc_workspace_bytes(const mlmc_ctx *ctx, int32_t level, int64_t n_sample
 int mlmc_fill_xi(const mlmc_ctx *ctx, int32_t level, int64_t first_sample, int64_t n,
                  double *xi_dev, void *stream);
 
+/* Replace the seed of the counter-based generator (mlmc_fill_xi and the xi
+ * that mlmc_estimate draws), e.g. for independent repetitions of Algorithm
+ * 4.1 on one context; nothing else changes. */
+int mlmc_set_seed(mlmc_ctx *ctx, uint64_t seed);
+
 /* Batched solve of n samples on the grid of level `level` (no pairing):
  * field GEMM, assembly, factorisation, solve to opts->eps_fine with
  * opts->solver, and Q.  Outputs: q_dev[n]; u_dev[n x (n_l-1)^2] (optional,

@@ -70,6 +70,9 @@ def _load():
         lib.oracle_energy.argtypes = [c_int, c_int, D, D, D]
         lib.oracle_energy.restype = c_double
         lib.oracle_dense_matrix.argtypes = [c_int, c_int, D, D, D]
+        lib.oracle_band_matrix.argtypes = [c_int, c_int, D, D, D]
+        lib.oracle_set_threads.argtypes = [c_int]
+        lib.oracle_set_threads.restype = None
         lib.oracle_num_threads.restype = c_int
         _lib = lib
     return _lib
@@ -203,6 +206,23 @@ def grad_batch(n, Phi, xi, f=1.0, want_gz=False, want_lambda=False):
 
 def energy(n, Phi, xi, u):
     return _load().oracle_energy(n, Phi.shape[1], _p(_f64(Phi)), _p(_f64(xi)), _p(_f64(u)))
+
+
+def band_matrix(n, Phi, xi):
+    """A of one sample in LAPACK lower band form ab[d, j] = A[j+d, j], d = 0..n-1."""
+    m = n - 1
+    N, bw = m * m, m
+    Ab = np.zeros((N, bw + 1))
+    _load().oracle_band_matrix(n, Phi.shape[1], _p(_f64(Phi)), _p(_f64(np.atleast_2d(xi)[0])), _p(Ab))
+    ab = np.zeros((bw + 1, N))
+    for d in range(bw + 1):
+        ab[d, :N - d] = Ab[d:, d]
+    return ab
+
+
+def set_threads(k):
+    """Threads of the oracle's later OpenMP regions."""
+    _load().oracle_set_threads(int(k))
 
 
 def dense_matrix(n, Phi, xi):

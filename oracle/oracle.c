@@ -553,6 +553,30 @@ int oracle_dense_matrix(int n, int K, const double *Phi, const double *xi, doubl
     return 0;
 }
 
+/* Band of one sample's matrix in the lower storage of assemble_band
+ * (Ab[P*(bw+1) + d] = A[P, P-d], bw = n-2), for the LAPACK banded CPU line. */
+int oracle_band_matrix(int n, int K, const double *Phi, const double *xi, double *Ab)
+{
+    int m = n - 1, N = m * m, np = (n + 1) * (n + 1);
+    double *a = (double *)malloc(sizeof(double) * np);
+    double *aE = (double *)malloc(sizeof(double) * (n + 1) * n);
+    double *aN = (double *)malloc(sizeof(double) * (n + 1) * n);
+    double *b = (double *)malloc(sizeof(double) * N);
+    build_system(n, K, Phi, xi, NULL, 1.0, NULL, a, aE, aN, Ab, b);
+    free(a); free(aE); free(aN); free(b);
+    return 0;
+}
+
+/* Set the number of OpenMP threads of later parallel regions. */
+void oracle_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* Threads an OpenMP parallel region of this library uses. */
 int oracle_num_threads(void)
 {

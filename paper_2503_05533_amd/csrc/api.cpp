@@ -771,6 +771,13 @@ size_t mlmc_workspace_bytes(const mlmc_ctx *ctx, int32_t level, int64_t n_sample
     return make_level_layout(ctx->cfg, level, n_samples, *opts).bytes;
 }
 
+int mlmc_set_seed(mlmc_ctx *ctx, uint64_t seed)
+{
+    if (!ctx) return MLMC_EINVAL;
+    ctx->cfg.seed = seed;
+    return MLMC_OK;
+}
+
 int mlmc_fill_xi(const mlmc_ctx *cctx, int32_t level, int64_t first_sample, int64_t n,
                  double *xi_dev, void *stream)
 {

@@ -25,7 +25,7 @@ EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
            "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
            "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
            "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune",
-           "mlmc_sample_level_noalloc"]
+           "mlmc_sample_level_noalloc", "mlmc_set_seed"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -89,6 +89,7 @@ def load_library():
     lib.mlmc_workspace_bytes.argtypes = [vp, i32, i64, ctypes.POINTER(_LevelOpts)]
     lib.mlmc_workspace_bytes.restype = ctypes.c_size_t
     lib.mlmc_fill_xi.argtypes = [vp, i32, i64, i64, vp, vp]
+    lib.mlmc_set_seed.argtypes = [vp, ctypes.c_uint64]
     lib.mlmc_solve.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp, ctypes.c_size_t,
                                vp, vp, vp, vp, vp]
     lib.mlmc_sample_level.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp,
@@ -223,10 +224,16 @@ class MLMC:
         return dict(ms=ms.value, launches=cnt.value, samples=smp.value)
 
     # -------------------------------------------------------------- entry points
-    def fill_xi(self, level, first, n):
-        xi = torch.empty((n, self.cfg.K), dtype=torch.float64, device=self.device)
+    def fill_xi(self, level, first, n, out=None):
+        """xi[n, K] of samples first .. first+n-1 of `level` (into `out` if given)."""
+        xi = out if out is not None else torch.empty((n, self.cfg.K), dtype=torch.float64,
+                                                      device=self.device)
         self._check(self.lib.mlmc_fill_xi(self.h, level, first, n, _ptr(xi), _stream()), "fill_xi")
         return xi
+
+    def set_seed(self, seed):
+        self._check(self.lib.mlmc_set_seed(self.h, int(seed) & 0xFFFFFFFFFFFFFFFF), "set_seed")
+        self.cfg.seed = int(seed)
 
     def solve(self, level, xi, dtype="f64", solver="direct", eps=0.0, promote=True, want_u=False,
               own_workspace=False):

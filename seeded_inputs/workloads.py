@@ -1,7 +1,8 @@
 """The synthetic workloads (grid sizes, field parameters, sample counts, seeds).
 
 Domain (0,1)^2, f = 1, u = 0 on the boundary, nodal lognormal coefficient
-a = exp(Z) with Z a truncated separable exponential-covariance KL expansion.
+a = exp(Z) with Z a truncated separable exponential-covariance KL expansion
+(field 0) or the trigonometric expansion of the paper's sec. 5.1 (field 1).
 Level l has n_l = n0 * 2**l cells per side.  Seeds are 1000 + workload id.
 """
 
@@ -18,6 +19,10 @@ WORKLOADS = {
     # all five levels batched together, geometric sample counts
     "batched5_n16-256_K128": dict(id=3, n0=16, levels=[0, 1, 2, 3, 4], K=128, sigma2=2.0,
                                   corr_len=0.1, N=[40000, 10637, 2828, 752, 200], seed=1003),
+    # the paper's quarter-precision example (sec. 5.2): h0 = 1/4, trigonometric
+    # field with s = 1, sigma = 1, k_p = 0.4; N_l from standard MLMC at TOL^2 = 2e-6
+    "q43_n4-32_trig1": dict(id=5, n0=4, levels=[0, 1, 2, 3], K=1, sigma2=1.0, corr_len=0.3,
+                            field=1, field_q=2.0, k_p=0.4, N=None, seed=1005),
     # adjoint gradient at n=128, 4096 samples
     "adjoint_n128_K128": dict(id=4, n0=128, levels=[0], K=128, sigma2=2.0, corr_len=0.1,
                               N=[4096], seed=1004),
