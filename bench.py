@@ -268,8 +268,9 @@ def leg_c2(a):
 
 def leg_c3(a):
     """batched5_n16-256_K128: all five levels (40000 ... 200 samples) as one
-    replayed HIP graph, FP32 factor + FP64 refinement against batched MINRES,
-    both to delta_l; and the eager schedule for the refinement path."""
+    replayed HIP graph, FP32 factor + FP64 refinement against batched MINRES
+    (FP64) and MINRES-IR (FP32 inner vectors), all to delta_l; and the eager
+    schedule for the refinement path."""
     w, ctx = _ctx_for("batched5_n16-256_K128", minres_max_iter=20000)
     levels, Ns = w["levels"], w["N"]
     L = max(levels)
@@ -277,16 +278,18 @@ def leg_c3(a):
     xis = [ctx.fill_xi(l, 0, N) for l, N in zip(levels, Ns)]
     out = dict(workload="batched5_n16-256_K128", N=Ns, eps=eps)
     for name, solver, graph in (("direct_ir_graph", "direct_ir", True), ("direct_ir_eager", "direct_ir", False),
-                                ("minres_graph", "minres", True)):
+                                ("minres_graph", "minres", True), ("minres_ir_graph", "minres_ir", True)):
         o = [dict(dtype="f32", solver=solver, eps_fine=eps[l], eps_coarse=eps[l - 1] if l else 0.0)
              for l in levels]
         plan = ctx.plan_levels(levels, xis, o, use_graph=graph)
         ms = _event_ms(plan.run, reps=3)
         st = plan.run(stats=True)["stats"]
         out[name] = dict(ms=ms, samples_per_s=sum(Ns) / (ms / 1e3),
-                         mean_iters=[x["mean_iters"] for x in st], noconv=[x["n_noconv"] for x in st])
+                         mean_iters=[x["mean_iters"] for x in st], noconv=[x["n_noconv"] for x in st],
+                         promoted=[x["n_promoted"] for x in st])
         del plan
     out["direct_ir_vs_minres"] = out["minres_graph"]["ms"] / out["direct_ir_graph"]["ms"]
+    out["minres_ir_vs_minres"] = out["minres_graph"]["ms"] / out["minres_ir_graph"]["ms"]
     ctx.close()
     return out
 

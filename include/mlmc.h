@@ -72,11 +72,20 @@ typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3, MLMC_FP8
  *                  (FP32 arithmetic), FP64 update, stop when
  *                  ||b - A x||_2 / ||b||_2 < eps (strict), at most
  *                  ir_max_iter corrections (Sec. 2.3).
- *   MLMC_MINRES    Jacobi-scaled MINRES in FP64 (Sec. 2.2) stopped when the
+ *   MLMC_MINRES    Jacobi-scaled MINRES in FP64 (Sec. 2.2), run until its
  *                  recurrence estimate of the scaled relative residual is
- *                  below eps and the true unscaled FP64 relative residual
- *                  ||b - A x||/||b|| < eps, at most minres_max_iter steps. */
-typedef enum { MLMC_DIRECT = 0, MLMC_DIRECT_IR = 1, MLMC_MINRES = 2 } mlmc_solver;
+ *                  below 0.9 eps; the sample has converged when the true
+ *                  unscaled FP64 relative residual ||b - A x||/||b|| < eps,
+ *                  otherwise MINRES restarts from that residual (at most 8
+ *                  restarts, minres_max_iter iterations in all).
+ *   MLMC_MINRES_IR MINRES as the inner solver of iterative refinement
+ *                  (Sec. 2.3 with a Krylov correction solve): each inner
+ *                  MINRES stores its vectors in FP32 and reduces the scaled
+ *                  correction residual by max(eps / (2 rel), 1e-5); FP64
+ *                  residual and update, the same stop test, at most
+ *                  ir_max_iter refinements and minres_max_iter inner
+ *                  iterations in all.  factor_dtype is ignored by both. */
+typedef enum { MLMC_DIRECT = 0, MLMC_DIRECT_IR = 1, MLMC_MINRES = 2, MLMC_MINRES_IR = 3 } mlmc_solver;
 
 typedef struct {
     int32_t n0;              /* cells per side on level 0 (power of two, >= 4) */

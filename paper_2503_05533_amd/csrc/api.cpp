@@ -89,6 +89,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : (dt == MLMC_FP8 ? 1 : 2)); }
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+inline bool is_minres(int solver) { return solver == MLMC_MINRES || solver == MLMC_MINRES_IR; }
 inline int ilog2(int v) { int l = 0; while ((1 << (l + 1)) <= v) ++l; return l; }
 
 // ---------------------------------------------------------------- kernel timing
@@ -257,7 +258,7 @@ struct grid_layout {
     size_t vec;  // padded vector length per sample
     size_t off_a, off_sc, off_gam, off_beta, off_x, off_r, off_z, off_lam, off_gz;
     size_t off_factor, off_promo, off_state, off_relres, off_q, off_iters, off_idx;
-    size_t off_mr;  // MINRES vectors (7 per sample)
+    size_t off_mr;  // MINRES vectors (7 per sample, FP64 or FP32)
     size_t off_cnt; // device counters (promotion)
     int64_t promo_slots;
     size_t bytes;
@@ -283,13 +284,14 @@ grid_layout make_layout(int n, int64_t S, const mlmc_level_opts &o)
     L.off_r = take(vb);
     L.off_z = take(vb);
     L.off_lam = take(vb);
-    const bool direct = o.solver != MLMC_MINRES;
+    const bool direct = !is_minres(o.solver);
     const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
     L.off_factor = take(direct ? S * factor_entries_per_sample(dt, n) * dtype_bytes(dt) : 0);
     // every sample can be re-solved with an FP64 factor without a host round trip
     L.promo_slots = (direct && dt != MLMC_F64 && o.promote) ? S : 0;
     L.off_promo = take(L.promo_slots * factor_entries_per_sample(MLMC_F64, n) * 8);
-    L.off_mr = take(o.solver == MLMC_MINRES ? 7 * S * L.vec * 8 : 0);
+    // 7 FP64 vectors per sample: also room for the FP64 re-solve of MINRES-IR samples
+    L.off_mr = take(is_minres(o.solver) ? 7 * S * L.vec * 8 : 0);
     L.off_state = take(S * 4);
     L.off_relres = take(S * 8);
     L.off_q = take(S * 8);
@@ -346,7 +348,7 @@ int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o, int level, bool pair)
     if (!o) return fail(ctx, MLMC_EINVAL, "opts is NULL");
     if (o->factor_dtype < MLMC_F64 || o->factor_dtype > MLMC_FP8)
         return fail(ctx, MLMC_EINVAL, "bad factor dtype");
-    if (o->solver < MLMC_DIRECT || o->solver > MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "bad solver");
+    if (o->solver < MLMC_DIRECT || o->solver > MLMC_MINRES_IR) return fail(ctx, MLMC_EINVAL, "bad solver");
     if (!(o->eps_fine >= 0.0) || !(o->eps_coarse >= 0.0)) return fail(ctx, MLMC_EINVAL, "bad eps");
     if (o->solver == MLMC_DIRECT_IR) {
         const int n = ctx->cfg.n0 << level;
@@ -432,12 +434,28 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     double *relres = at<double>(ws, L.off_relres);
     PROF(0, n, S, launch_field(S, K, P, xi, ctx->phit[level], a, st));
     // the n = 16 factorisation forms the scaled operator itself
-    if (o.solver == MLMC_MINRES || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, st));
+    if (is_minres(o.solver) || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, st));
     HIPCHK(launch_init_state(S, state, relres, st));
-    if (o.solver == MLMC_MINRES) {
+    if (is_minres(o.solver)) {
+        // MINRES: FP64 vectors, a restart from the true residual at most 8
+        // times; MINRES-IR: FP32 inner vectors, up to ir_max_iter refinements
+        const bool low = o.solver == MLMC_MINRES_IR;
         PROF(5, n, S, launch_minres(n, S, ctx->cfg.f, a, sc, gam, beta, at<double>(ws, L.off_x),
-                                    at<double>(ws, L.off_r), at<double>(ws, L.off_mr), eps,
-                                    ctx->cfg.minres_max_iter, state, relres, q, iters, st));
+                                    at<double>(ws, L.off_r), at<void>(ws, L.off_mr), low ? 1 : 0, eps,
+                                    ctx->cfg.minres_max_iter, low ? ctx->cfg.ir_max_iter : 8, nullptr, nullptr,
+                                    state, relres, q, iters, st));
+        if (low && o.promote) {
+            // samples whose FP32-vector refinement did not converge: FP64 MINRES,
+            // compacted on the device (workgroups beyond the count exit)
+            int *idx = at<int>(ws, L.off_idx);
+            int *cnt = at<int>(ws, L.off_cnt);
+            HIPCHK(launch_zero_int(cnt, 1, st));
+            HIPCHK(launch_collect(S, state, idx, cnt, st));
+            HIPCHK(launch_reset_subset(S, idx, cnt, state, relres, st));
+            PROF(5, n, S, launch_minres(n, S, ctx->cfg.f, a, sc, gam, beta, at<double>(ws, L.off_x),
+                                        at<double>(ws, L.off_r), at<void>(ws, L.off_mr), 0, eps,
+                                        ctx->cfg.minres_max_iter, 8, idx, cnt, state, relres, q, iters, st));
+        }
         return MLMC_OK;
     }
     const bool direct = o.solver == MLMC_DIRECT;
@@ -995,7 +1013,7 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
     if (n < 1 || !xi_dev || !ws_dev) return fail(ctx, MLMC_EINVAL, "autotune: bad arguments");
     const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
     if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
-    if (opts->solver == MLMC_MINRES) return MLMC_OK;
+    if (is_minres(opts->solver)) return MLMC_OK;
     hipStream_t st = (hipStream_t)stream;
     const int dt = opts->solver == MLMC_DIRECT ? MLMC_F64 : opts->factor_dtype;
     const bool was = ctx->prof_on;
@@ -1037,7 +1055,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
 {
     if (!ctx || !out || !(tol > 0.0) || n_init < 2 || ctx->cfg.L_max < 1)
         return fail(ctx, MLMC_EINVAL, "estimate: bad arguments");
-    if (solver != MLMC_MINRES && !dtype_per_level && solver == MLMC_DIRECT_IR)
+    if (!dtype_per_level && solver == MLMC_DIRECT_IR)
         return fail(ctx, MLMC_EINVAL, "estimate: dtype_per_level is NULL");
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
@@ -1355,7 +1373,7 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, con
     int rc = check_level(ctx, level);
     if (rc) return rc;
     if ((rc = check_opts(ctx, opts, level, false))) return rc;
-    if (opts->solver == MLMC_MINRES) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not MINRES)");
+    if (is_minres(opts->solver)) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not MINRES)");
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n == 0) return MLMC_OK;
     if (!xi_dev || !ws_dev || !grad_xi_dev || !(eps_adjoint > 0.0) || !aligned(xi_dev, 8) ||

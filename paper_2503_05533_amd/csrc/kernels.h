@@ -91,10 +91,14 @@ hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, dou
                              int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
                              hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
+// MINRES (low = 0: FP64 inner vectors) or MINRES with FP64 iterative
+// refinement around an inner solve with FP32 vectors (low = 1); vecs holds
+// 7 vectors per workgroup of the inner precision.  Workgroup b solves sample
+// idx[b] (or b); with count != NULL, workgroups b >= *count exit.
 hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
-                         const double *gam, const double *beta, double *x, double *r, double *vecs,
-                         double eps, int maxit, uint32_t *state, double *relres, double *q,
-                         int32_t *iters, hipStream_t st);
+                         const double *gam, const double *beta, double *x, double *r, void *vecs,
+                         int low, double eps, int maxit, int max_outer, const int *idx, const int *count,
+                         uint32_t *state, double *relres, double *q, int32_t *iters, hipStream_t st);
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
                              double *gz, hipStream_t st);
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);

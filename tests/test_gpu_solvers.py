@@ -29,18 +29,21 @@ def _say(*a):
 
 # ----------------------------------------------------------------- MINRES
 
-@pytest.mark.parametrize("n,S", [(16, 40), (32, 20), (64, 6)])
-def test_minres_reaches_eps(n, S):
+@pytest.mark.parametrize("solver", ["minres", "minres_ir"])
+@pytest.mark.parametrize("n,S", [(16, 40), (32, 20), (64, 6), (128, 3)])
+def test_minres_reaches_eps(n, S, solver):
+    """MINRES (FP64) and MINRES-IR (FP32 inner vectors, FP64 refinement) reach
+    eps in the true unscaled residual, with Q within the residual bound."""
     torch = _torch()
-    level = {16: 0, 32: 1, 64: 2}[n]
+    level = {16: 0, 32: 1, 64: 2, 128: 3}[n]
     K, s2, lam, seed = 64, 1.0, 0.3, 1001
     ctx = _ctx(n0=16, L_max=level, K=K, sigma2=s2, corr_len=lam, seed=seed, minres_max_iter=4000)
     xi = si.splitmix64_normals(seed, level, 0, S, K)
     phi = oracle.kl_basis(n, K, s2, lam)
     qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
     for eps in (8.7e-4, 1e-8):
-        _say("minres n=%d S=%d eps=%g" % (n, S, eps))
-        out = ctx.solve(level, torch.from_numpy(xi), solver="minres", eps=eps, want_u=True)
+        out = ctx.solve(level, torch.from_numpy(xi), solver=solver, eps=eps, want_u=True)
+        _say("%s n=%d S=%d eps=%g: iterations %s" % (solver, n, S, eps, out["iters"].cpu().numpy().tolist()))
         st = out["status"].cpu().numpy()
         assert np.all(st & 1), st
         rr = oracle.relres_batch(n, phi, xi, out["u"].cpu().numpy())
@@ -54,21 +57,23 @@ def test_minres_reaches_eps(n, S):
     ctx.close()
 
 
-def test_minres_iterations_grow_with_accuracy():
+@pytest.mark.parametrize("solver", ["minres", "minres_ir"])
+def test_minres_iterations_grow_with_accuracy(solver):
     torch = _torch()
     ctx = _ctx(n0=16, L_max=1, K=16, minres_max_iter=4000)
     xi = torch.from_numpy(si.splitmix64_normals(3, 1, 0, 8, 16))
-    loose = ctx.solve(1, xi, solver="minres", eps=1e-3)["iters"].cpu().numpy()
-    tight = ctx.solve(1, xi, solver="minres", eps=1e-9)["iters"].cpu().numpy()
+    loose = ctx.solve(1, xi, solver=solver, eps=1e-3)["iters"].cpu().numpy()
+    tight = ctx.solve(1, xi, solver=solver, eps=1e-9)["iters"].cpu().numpy()
     assert np.all(tight > loose)
     ctx.close()
 
 
-def test_minres_iteration_cap_flags():
+@pytest.mark.parametrize("solver", ["minres", "minres_ir"])
+def test_minres_iteration_cap_flags(solver):
     torch = _torch()
     ctx = _ctx(n0=16, L_max=1, K=16, minres_max_iter=3)
     xi = torch.from_numpy(si.splitmix64_normals(3, 1, 0, 4, 16))
-    out = ctx.solve(1, xi, solver="minres", eps=1e-12)
+    out = ctx.solve(1, xi, solver=solver, eps=1e-12)
     st = out["status"].cpu().numpy()
     assert np.all(st & 8) and not np.any(st & 1)
     ctx.close()
