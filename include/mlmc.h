@@ -10,7 +10,8 @@
  *   the (n_l - 1)^2 interior nodes, ordered P = (iy-1)(n_l-1) + (ix-1);
  *   the coefficient is nodal, a_p = exp(Z_p), Z = xi . Phi_l^T with Phi_l the
  *   field basis (mlmc_config.field) on the (n_l+1)^2 nodes; the
- *   edge coefficient is the harmonic mean of its end nodes; b = h^2 f;
+ *   edge coefficient is the harmonic mean of its end nodes (or the P1
+ *   element rule, mlmc_config.disc); b = h^2 f;
  *   Q = h^2 * sum_P u_P.
  *
  * Conventions for every entry point:
@@ -110,6 +111,16 @@ typedef struct {
                               *    Z = sum_{j=1..K} xi_j sigma j^(-field_q) sin(2 pi j x1) cos(2 pi j x2)
                               *    (the paper's s = K, q = field_q, omega_j = sigma xi_j ~ N(0, sigma2)) */
     double field_q;          /* decay exponent q of field 1 (unused by field 0) */
+    int32_t disc;            /* edge coefficients of the 5-point operator:
+                              * 0: vertex-centred finite volumes, the harmonic mean of
+                              *    the edge's end nodes;
+                              * 1: P1 finite elements (Sec. 3; the discretisation of the
+                              *    paper's experiments, Sec. 5.1) on the right triangles of
+                              *    the cells cut along (x, y)-(x+h, y+h), the coefficient
+                              *    interpolated linearly: edge (x,y)-(x+h,y) gets
+                              *    (2a(x,y) + 2a(x+h,y) + a(x+h,y+h) + a(x,y-h)) / 6 and edge
+                              *    (x,y)-(x,y+h) gets (2a(x,y) + 2a(x,y+h) + a(x+h,y+h) + a(x-h,y)) / 6;
+                              *    b = h^2 f and Q = h^2 sum u are the same for both. */
 } mlmc_config;
 
 typedef struct {

@@ -73,6 +73,8 @@ def _load():
         lib.oracle_band_matrix.argtypes = [c_int, c_int, D, D, D]
         lib.oracle_set_threads.argtypes = [c_int]
         lib.oracle_set_threads.restype = None
+        lib.oracle_set_disc.argtypes = [c_int]
+        lib.oracle_set_disc.restype = None
         lib.oracle_num_threads.restype = c_int
         _lib = lib
     return _lib
@@ -218,6 +220,29 @@ def band_matrix(n, Phi, xi):
     for d in range(bw + 1):
         ab[d, :N - d] = Ab[d:, d]
     return ab
+
+
+def set_disc(d):
+    """Edge rule of every later assembly: 0 finite volumes (harmonic mean of
+    the edge's end nodes), 1 P1 elements on right triangles (sec. 3)."""
+    if d not in (0, 1):
+        raise ValueError("disc is 0 or 1")
+    _load().oracle_set_disc(int(d))
+
+
+class disc_rule:
+    """Context manager: assemble with edge rule d inside the block."""
+
+    def __init__(self, d):
+        self.d = d
+
+    def __enter__(self):
+        set_disc(self.d)
+        return self
+
+    def __exit__(self, *exc):
+        set_disc(0)
+        return False
 
 
 def set_threads(k):

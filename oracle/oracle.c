@@ -168,16 +168,44 @@ static void field(int n, int K, const double *Phi, const double *xi, double *a)
 
 static double hmean(double x, double y) { return 2.0 * x * y / (x + y); }
 
+/* Discretisation of the edge coefficients (oracle_set_disc):
+ * 0: vertex-centred finite volumes, the harmonic mean of the edge's end nodes;
+ * 1: P1 finite elements (Sec. 3) on the mesh whose cells are cut along the
+ *    diagonal (x,y)-(x+h,y+h), with the coefficient interpolated linearly.
+ *    For a right triangle with legs h the element matrix couples the right
+ *    angle's vertex with each acute vertex by -(mean of a over T)/2 and the
+ *    two acute vertices by 0, so an axis edge, a leg of both its triangles,
+ *    gets half the sum of their vertex means:
+ *      edge (x,y)-(x+h,y):  its triangles' third vertices are (x+h,y+h) and (x,y-h);
+ *      edge (x,y)-(x,y+h):  their third vertices are (x+h,y+h) and (x-h,y). */
+static int g_disc = 0;
+void oracle_set_disc(int d) { g_disc = d; }
+
+/* a at node (ix, iy), 0 outside the node grid (only edges with both ends on
+ * the boundary reach outside; they enter no equation). */
+static double anode(int n, const double *a, int ix, int iy)
+{
+    return (ix < 0 || ix > n || iy < 0 || iy > n) ? 0.0 : a[iy * (n + 1) + ix];
+}
+
 /* Edge coefficients: aE[iy*n + ix] joins (ix,iy)-(ix+1,iy), ix<n, iy<=n;
  * aN[iy*(n+1) + ix] joins (ix,iy)-(ix,iy+1), iy<n, ix<=n. */
 static void faces(int n, const double *a, double *aE, double *aN)
 {
     for (int iy = 0; iy <= n; ++iy)
-        for (int ix = 0; ix < n; ++ix)
-            aE[iy * n + ix] = hmean(a[iy * (n + 1) + ix], a[iy * (n + 1) + ix + 1]);
+        for (int ix = 0; ix < n; ++ix) {
+            double l = anode(n, a, ix, iy), r = anode(n, a, ix + 1, iy);
+            double t1 = (l + r + anode(n, a, ix + 1, iy + 1)) / 3.0; /* triangle above */
+            double t2 = (l + r + anode(n, a, ix, iy - 1)) / 3.0;     /* triangle below */
+            aE[iy * n + ix] = g_disc ? 0.5 * (t1 + t2) : hmean(l, r);
+        }
     for (int iy = 0; iy < n; ++iy)
-        for (int ix = 0; ix <= n; ++ix)
-            aN[iy * (n + 1) + ix] = hmean(a[iy * (n + 1) + ix], a[(iy + 1) * (n + 1) + ix]);
+        for (int ix = 0; ix <= n; ++ix) {
+            double b = anode(n, a, ix, iy), t = anode(n, a, ix, iy + 1);
+            double t1 = (b + t + anode(n, a, ix + 1, iy + 1)) / 3.0; /* triangle to the right */
+            double t2 = (b + t + anode(n, a, ix - 1, iy)) / 3.0;     /* triangle to the left */
+            aN[iy * (n + 1) + ix] = g_disc ? 0.5 * (t1 + t2) : hmean(b, t);
+        }
 }
 
 /* Banded lower storage: Ab[P*(bw+1) + d] = A[P, P-d], d = 0..bw. */
@@ -480,6 +508,14 @@ int oracle_grad_batch(int n, int K, const double *Phi, int S, const double *xi, 
                 for (int ix = 0; ix < n; ++ix) {
                     int p = iy * (n + 1) + ix, q = p + 1;
                     double prod = (Lm[p] - Lm[q]) * (U[p] - U[q]);
+                    if (g_disc) {
+                        /* d/dZ of (2a_p + 2a_q + a_t1 + a_t2)/6, a = exp(Z) */
+                        gZ[p] -= prod * 2.0 * a[p] / 6.0;
+                        gZ[q] -= prod * 2.0 * a[q] / 6.0;
+                        if (iy + 1 <= n) gZ[p + (n + 1) + 1] -= prod * a[p + (n + 1) + 1] / 6.0;
+                        if (iy - 1 >= 0) gZ[p - (n + 1)] -= prod * a[p - (n + 1)] / 6.0;
+                        continue;
+                    }
                     double den = (a[p] + a[q]) * (a[p] + a[q]);
                     gZ[p] -= prod * 2.0 * a[q] * a[q] * a[p] / den;
                     gZ[q] -= prod * 2.0 * a[p] * a[p] * a[q] / den;
@@ -489,6 +525,13 @@ int oracle_grad_batch(int n, int K, const double *Phi, int S, const double *xi, 
                 for (int ix = 0; ix <= n; ++ix) {
                     int p = iy * (n + 1) + ix, q = p + (n + 1);
                     double prod = (Lm[p] - Lm[q]) * (U[p] - U[q]);
+                    if (g_disc) {
+                        gZ[p] -= prod * 2.0 * a[p] / 6.0;
+                        gZ[q] -= prod * 2.0 * a[q] / 6.0;
+                        if (ix + 1 <= n) gZ[q + 1] -= prod * a[q + 1] / 6.0;
+                        if (ix - 1 >= 0) gZ[p - 1] -= prod * a[p - 1] / 6.0;
+                        continue;
+                    }
                     double den = (a[p] + a[q]) * (a[p] + a[q]);
                     gZ[p] -= prod * 2.0 * a[q] * a[q] * a[p] / den;
                     gZ[q] -= prod * 2.0 * a[p] * a[p] * a[q] / den;

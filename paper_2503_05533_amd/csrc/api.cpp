@@ -389,6 +389,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
     g.iters = iters;
     g.variant = ctx->ir_variant[dt][ilog2(n)];
     g.fwd_done = fwd_done ? 1 : 0;
+    g.disc = ctx->cfg.disc;
     PROF(3, n, S, launch_ir(dt, g, st));
     if (L.promo_slots > 0 && dt != MLMC_F64) {
         int *idx = at<int>(ws, L.off_idx);
@@ -400,7 +401,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
         PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_a), at<double>(ws, L.off_sc),
                                      at<double>(ws, L.off_beta), at<double>(ws, L.off_gam), pf, idx, cnt, 0,
-                                     state, 0.0, nullptr, nullptr, st));
+                                     state, 0.0, nullptr, nullptr, ctx->cfg.disc, st));
         ir_args p = g;
         p.nblocks = np;
         p.factor = pf;
@@ -434,7 +435,7 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     double *relres = at<double>(ws, L.off_relres);
     PROF(0, n, S, launch_field(S, K, P, xi, ctx->phit[level], a, st));
     // the n = 16 factorisation forms the scaled operator itself
-    if (is_minres(o.solver) || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, st));
+    if (is_minres(o.solver) || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, ctx->cfg.disc, st));
     HIPCHK(launch_init_state(S, state, relres, st));
     if (is_minres(o.solver)) {
         // MINRES: FP64 vectors, a restart from the true residual at most 8
@@ -443,7 +444,7 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
         PROF(5, n, S, launch_minres(n, S, ctx->cfg.f, a, sc, gam, beta, at<double>(ws, L.off_x),
                                     at<double>(ws, L.off_r), at<void>(ws, L.off_mr), low ? 1 : 0, eps,
                                     ctx->cfg.minres_max_iter, low ? ctx->cfg.ir_max_iter : 8, nullptr, nullptr,
-                                    state, relres, q, iters, st));
+                                    state, relres, q, iters, ctx->cfg.disc, st));
         if (low && o.promote) {
             // samples whose FP32-vector refinement did not converge: FP64 MINRES,
             // compacted on the device (workgroups beyond the count exit)
@@ -454,7 +455,8 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
             HIPCHK(launch_reset_subset(S, idx, cnt, state, relres, st));
             PROF(5, n, S, launch_minres(n, S, ctx->cfg.f, a, sc, gam, beta, at<double>(ws, L.off_x),
                                         at<double>(ws, L.off_r), at<void>(ws, L.off_mr), 0, eps,
-                                        ctx->cfg.minres_max_iter, 8, idx, cnt, state, relres, q, iters, st));
+                                        ctx->cfg.minres_max_iter, 8, idx, cnt, state, relres, q, iters,
+                                        ctx->cfg.disc, st));
         }
         return MLMC_OK;
     }
@@ -468,7 +470,7 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     double *x = at<double>(ws, L.off_x);
     PROF(2, n, S, launch_factor(dt, n, S, a, sc, beta, gam, factor, nullptr, nullptr, 0, state, h * h * ctx->cfg.f,
                                 fwd ? at<double>(ws, L.off_z) : nullptr,
-                                fwd && factor_solves_initial(n) ? x : nullptr, st));
+                                fwd && factor_solves_initial(n) ? x : nullptr, ctx->cfg.disc, st));
     return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, x, q, iters, st, fwd);
 }
 
@@ -682,7 +684,7 @@ int mlmc_create(const mlmc_config *cfg, mlmc_ctx **out)
     *out = nullptr;
     const mlmc_config &c = *cfg;
     if (c.m != 2 || !is_pow2(c.n0) || c.n0 < 4 || c.L_max < 0 || (c.n0 << c.L_max) > 256 ||
-        c.K < 1 || c.K > 512 || !(c.sigma2 >= 0.0) || c.field < 0 || c.field > 1 ||
+        c.K < 1 || c.K > 512 || !(c.sigma2 >= 0.0) || c.field < 0 || c.field > 1 || c.disc < 0 || c.disc > 1 ||
         (c.field == 0 && !(c.corr_len > 0.0)) || (c.field == 1 && !(c.field_q >= 0.0 && c.field_q < 1e3)) ||
         !std::isfinite(c.f) ||
         !(c.k_p > 0.0 && c.k_p < 1.0) || c.ir_max_iter < 0 || c.L_max > 15 || !(c.alpha > 0.0) ||
@@ -1394,7 +1396,8 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, con
     rc = refine(ctx, L, ws, dt, false, 1.0, eps_adjoint, lam, at<double>(ws, L.off_q), nullptr, st);
     if (rc) return rc;
     double *gz = at<double>(ws, L.off_gz);
-    HIPCHK(launch_adjoint_gz(nn, S, at<double>(ws, L.off_a), at<double>(ws, L.off_x), lam, gz, st));
+    HIPCHK(launch_adjoint_gz(nn, S, at<double>(ws, L.off_a), at<double>(ws, L.off_x), lam, gz, ctx->cfg.disc,
+                             st));
     HIPCHK(launch_grad_gemm(S, K, P, gz, ctx->phit[level], grad_q_dev, grad_xi_dev, st));
     return MLMC_OK;
 }

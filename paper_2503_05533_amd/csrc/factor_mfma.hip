@@ -841,7 +841,7 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
                                                        const int *__restrict__ count,
                                                        int64_t slot_base, uint32_t *__restrict__ state,
                                                        double frhs, double *__restrict__ fz,
-                                                       double *__restrict__ x0)
+                                                       double *__restrict__ x0, int disc)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
@@ -873,15 +873,24 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
         // beta to the row below; 0 in the pad.  Row j + 1's values are formed
         // while row j is swept (independent work for the sweep's latency gaps),
         // and the nodes they need were requested one row before that.
-        double c = ac[NP], cN = ac[2 * NP], w = ac[NP - 1];
-        double aS = hmean2(c, ac[0]), sS = 0.0;
+        // (disc 1, P1 faces: also the node south of the west node, carried in
+        // wS, and the node east of the north node, the next lane's cN)
+        double c = ac[NP], cN = ac[2 * NP], w = ac[NP - 1], wS = ac[-1];
+        double aS = disc ? face_y(1, ac[0], c, dpp_f64<0x101>(c), ac[-1]) : hmean2(c, ac[0]), sS = 0.0;
         auto coeffs = [&](int j, double &sj, double &bj, double &gj) {
             double cNN = 0.0, wN = 0.0;
             if (j + 1 < m) {
                 cNN = ac[(j + 3) * NP];
                 wN = ac[(j + 2) * NP - 1];
             }
-            const double aw = hmean2(c, w), an = hmean2(c, cN);
+            double aw, an;
+            if (disc) {
+                aw = face_x(1, w, c, cN, wS);
+                an = face_y(1, c, cN, dpp_f64<0x101>(cN), w);
+            } else {
+                aw = hmean2(c, w);
+                an = hmean2(c, cN);
+            }
             const double ae = dpp_f64<0x101>(aw);
             sj = in ? 1.0 / sqrt(aw + ae + aS + an) : 0.0;
             const double sE = dpp_f64<0x101>(sj);
@@ -895,6 +904,7 @@ __global__ __launch_bounds__(256) void k_factor_rows16(int S, const double *__re
             sS = sj;
             c = cN;
             cN = cNN;
+            wS = w;
             w = wN;
         };
         double sjn, bjn, gjn;
@@ -991,7 +1001,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_wav
     const double *__restrict__ beta, const Tst *__restrict__ factor, double *__restrict__ x,
     const double *__restrict__ zbuf, double eps, int imax, int direct, const int *__restrict__ idx,
     const int *__restrict__ count, int64_t slot_base, uint32_t *__restrict__ state,
-    double *__restrict__ relres, double *__restrict__ q, int32_t *__restrict__ iters, int fwd_done)
+    double *__restrict__ relres, double *__restrict__ q, int32_t *__restrict__ iters, int fwd_done, int disc)
 {
     using Tac = typename store_traits<Tst>::acc;
     constexpr int M = 16, m = M - 1, NP = M + 1;
@@ -1096,14 +1106,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_wav
         struct resid_rows {
             const double *ac;
             double c, aS, cN, w;  // centre of row j, its south face, prefetched north and west nodes
+            double wS;            // the node south of the west node (P1 faces)
         };
         auto resid_start = [&]() {
             resid_rows R;
             R.ac = ac + opaque(0);  // face coefficients are formed anew in every pass
             R.c = R.ac[NP];
-            R.aS = hmean2(R.c, R.ac[0]);
+            R.aS = disc ? face_y(1, R.ac[0], R.c, dpp_f64<0x101>(R.c), R.ac[-1]) : hmean2(R.c, R.ac[0]);
             R.cN = R.ac[2 * NP];
             R.w = R.ac[NP - 1];
+            R.wS = R.ac[-1];
             return R;
         };
         auto resid_row = [&](resid_rows &R, int j) {
@@ -1112,7 +1124,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_wav
                 R.cN = R.ac[(j + 3) * NP];
                 R.w = R.ac[(j + 2) * NP - 1];
             }
-            const double aw = hmean2(R.c, w), an = hmean2(R.c, cN);
+            double aw, an;
+            if (disc) {
+                aw = face_x(1, w, R.c, cN, R.wS);
+                an = face_y(1, R.c, cN, dpp_f64<0x101>(cN), w);
+            } else {
+                aw = hmean2(R.c, w);
+                an = hmean2(R.c, cN);
+            }
+            R.wS = w;
             const double ae = dpp_f64<0x101>(aw);  // the next lane's west face
             const double xw = dpp_f64<0x111>(xv[j]), xe = dpp_f64<0x101>(xv[j]);
             double ax = (aw + ae + R.aS + an) * xv[j];
@@ -1434,7 +1454,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
     const int *__restrict__ idx, const int *__restrict__ count, int64_t slot_base,
     uint32_t *__restrict__ state, double *__restrict__ relres, double *__restrict__ q,
-    int32_t *__restrict__ iters, int fwd_done)
+    int32_t *__restrict__ iters, int fwd_done, int disc)
 {
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, m = M - 1, NT = 64 * blk_waves<M, G>();
     __shared__ double red[3 * NT];
@@ -1453,7 +1473,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     int trip = 0;
     for (;;) {
         __syncthreads();
-        const resid_out o = residual_pass_m<NT, M>(fconst, as, xs, rsb, red);
+        const resid_out o = residual_pass_m<NT, M>(fconst, as, xs, rsb, red, disc);
         rel = sqrt(o.rr) / sqrt(o.bb);
         sx = o.sx;
         st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
@@ -1560,17 +1580,17 @@ template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static c
 template <typename Tst, int M>
 hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
               const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
-              double *fz, double *x0, hipStream_t st)
+              double *fz, double *x0, int disc, hipStream_t st)
 {
     if constexpr (M == 16) {
         if (nb == 0) return hipSuccess;
         const unsigned grid = (unsigned)((nb + 15) / 16);
         if (idx)
             hipLaunchKernelGGL((k_factor_rows16<Tst, true>), dim3(grid < 1024 ? grid : 1024), dim3(256), 0, st, nb,
-                               a, sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
+                               a, sc, beta, (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0, disc);
         else
             hipLaunchKernelGGL((k_factor_rows16<Tst, false>), dim3(grid), dim3(256), 0, st, nb, a, sc, beta,
-                               (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
+                               (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0, disc);
     } else {
         hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
                            (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
@@ -1591,7 +1611,7 @@ hipError_t li_g(const ir_args &g, hipStream_t st)
     hipLaunchKernelGGL((k_ir_blk<Tst, M, G, PREF>), dim3(g.nblocks), dim3(64 * blk_waves<M, G>()), 0, st, g.n,
                        g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps,
                        g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
-                       g.fwd_done);
+                       g.fwd_done, g.disc);
     return hipGetLastError();
 }
 
@@ -1605,12 +1625,12 @@ hipError_t li(const ir_args &g, hipStream_t st)
             hipLaunchKernelGGL((k_ir_rows16<Tst, true>), dim3(grid < 1024 ? grid : 1024), dim3(256), 0, st,
                                g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
                                g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
-                               g.fwd_done);
+                               g.fwd_done, g.disc);
         else
             hipLaunchKernelGGL((k_ir_rows16<Tst, false>), dim3(grid), dim3(256), 0, st,
                                g.nblocks, g.fconst, g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.z, g.eps,
                                g.imax, g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters,
-                               g.fwd_done);
+                               g.fwd_done, g.disc);
         return hipGetLastError();
     } else {
         int G = g.variant > 0 ? g.variant : solve_cfg<Tst, M>::G;
@@ -1634,14 +1654,14 @@ hipError_t li_m(const ir_args &g, hipStream_t st)
 template <typename Tst>
 hipError_t lf_m(int M, int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
                 const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
-                double *fz, double *x0, hipStream_t st)
+                double *fz, double *x0, int disc, hipStream_t st)
 {
     switch (M) {
-    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1660,13 +1680,13 @@ hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,
                              int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                             hipStream_t st)
+                             int disc, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
-    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, st);
+    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
     }
     return hipErrorInvalidValue;
 }

@@ -11,6 +11,36 @@ namespace mlmc {
 
 __device__ inline double hmean2(double p, double q) { return 2.0 * p * q / (p + q); }
 
+// Edge coefficients of the 5-point operator from the nodal coefficient.
+// disc 0 (vertex-centred finite volumes): the harmonic mean of the edge's
+// end nodes.  disc 1 (P1 elements, Sec. 3, on the right triangles of cells
+// cut along the diagonal (x, y)-(x+h, y+h), the coefficient interpolated
+// linearly, so a triangle weighs its vertex mean): every mesh edge parallel
+// to an axis is a leg of its two triangles, each contributing half its
+// weight, and the diagonals couple nothing:
+//   edge L = (x, y) - R = (x+h, y): (2 a_L + 2 a_R + a(x+h, y+h) + a(x, y-h)) / 6,
+//   edge B = (x, y) - T = (x, y+h): (2 a_B + 2 a_T + a(x+h, y+h) + a(x-h, y)) / 6.
+__device__ inline double face_x(int disc, double aL, double aR, double aRN, double aLS)
+{
+    return disc ? (2.0 * (aL + aR) + aRN + aLS) / 6.0 : hmean2(aL, aR);
+}
+__device__ inline double face_y(int disc, double aB, double aT, double aTE, double aBW)
+{
+    return disc ? (2.0 * (aB + aT) + aTE + aBW) / 6.0 : hmean2(aB, aT);
+}
+
+// The four edge coefficients around node p of the (n+1)^2 node array (row
+// length np); the diagonal neighbours are read for disc 1 only.
+struct faces4 { double w, e, s, n; };
+__device__ inline faces4 node_faces(int disc, const double *__restrict__ as, int p, int np)
+{
+    const double c = as[p], w = as[p - 1], e = as[p + 1], sv = as[p - np], nv = as[p + np];
+    if (!disc) return faces4{hmean2(c, w), hmean2(c, e), hmean2(c, sv), hmean2(c, nv)};
+    const double ne = as[p + np + 1], sw = as[p - np - 1];
+    return faces4{face_x(1, w, c, nv, sw), face_x(1, c, e, ne, sv), face_y(1, sv, c, e, sw),
+                  face_y(1, c, nv, ne, w)};
+}
+
 // Fixed-order tree sum over the NT threads of a workgroup (deterministic).
 template <int NT>
 __device__ inline double wg_sum(double v, double *red)
@@ -35,7 +65,7 @@ struct resid_out { double rr, bb, sx; };
 template <int NT>
 __device__ inline resid_out residual_pass(int n, double fconst, const double *__restrict__ as,
                                           const double *__restrict__ xs, double *__restrict__ rs,
-                                          double *red)
+                                          double *red, int disc)
 {
     const int m = n - 1, M = n, np = n + 1;
     const double h = 1.0 / n, bval = h * h * fconst;
@@ -47,9 +77,8 @@ __device__ inline resid_out residual_pass(int n, double fconst, const double *__
             continue;
         }
         const int p = (j + 1) * np + (i + 1);
-        const double c = as[p];
-        const double aw = hmean2(c, as[p - 1]), ae = hmean2(c, as[p + 1]);
-        const double asu = hmean2(c, as[p - np]), an = hmean2(c, as[p + np]);
+        const faces4 f = node_faces(disc, as, p, np);
+        const double aw = f.w, ae = f.e, asu = f.s, an = f.n;
         const double xv = xs[e];
         double ax = (aw + ae + asu + an) * xv;
         if (i > 0) ax -= aw * xs[e - 1];
@@ -106,7 +135,7 @@ __device__ inline resid_out wg_sum3(double a, double b, double c, double *red)
 template <int NT, int M>
 __device__ inline resid_out residual_pass_m(double fconst, const double *__restrict__ as,
                                             const double *__restrict__ xs, double *__restrict__ rs,
-                                            double *red)
+                                            double *red, int disc)
 {
     constexpr int m = M - 1, np = M + 1, TOT = m * M, IT = (TOT + NT - 1) / NT;
     const double h = 1.0 / M, bval = h * h * fconst;
@@ -120,10 +149,11 @@ __device__ inline resid_out residual_pass_m(double fconst, const double *__restr
         const bool in = live && i < m;
         // node of the unknown; for the pad entry (i = m) it is a boundary node
         // whose neighbours are still inside the node array (values unused)
+        // (the pad's node stands for an interior one: its diagonal neighbours
+        // are outside the node array)
         const int p = (j + 1) * np + (i + 1);
-        const double c = as[p];
-        const double aw = hmean2(c, as[p - 1]), ae = hmean2(c, as[p + 1]);
-        const double asu = hmean2(c, as[p - np]), an = hmean2(c, as[p + np]);
+        const faces4 f = node_faces(disc, as, in ? p : p - 1, np);
+        const double aw = f.w, ae = f.e, asu = f.s, an = f.n;
         const double xv = xs[ec];
         const double xw = xs[ec > 0 ? ec - 1 : 0], xe = xs[ec + 1 < TOT ? ec + 1 : TOT - 1];
         const double xsn = xs[ec >= M ? ec - M : 0], xn = xs[ec + M < TOT ? ec + M : TOT - 1];

@@ -52,6 +52,7 @@ struct ir_args {
     int32_t *iters;
     int variant;  // refinement-kernel variant (0: built-in default; n >= 64: waves per row pair)
     int fwd_done;  // the factorisation wrote the forward sweep of the initial solve to z
+    int disc;      // edge coefficients: 0 harmonic means (finite volumes), 1 P1 elements
 };
 
 hipError_t launch_fill_xi(uint64_t seed, int level, int64_t first, int64_t n, int K, double *xi,
@@ -63,7 +64,9 @@ hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double
                              hipStream_t st);
 hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double *phit,
                             const double *gq, double *grad, hipStream_t st);
-hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
+// disc: edge coefficients, 0 harmonic means (finite volumes), 1 P1 elements
+// on right triangles (node_faces in ir_common.h).
+hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta, int disc,
                          hipStream_t st);
 // Factorisation of the scaled operator.  It reads the couplings beta, gam,
 // except where factor_forms_coeffs(n): there it reads the nodal coefficient a
@@ -77,7 +80,7 @@ hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam,
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                          const double *gam, void *factor, const int *idx, const int *count,
                          int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                         hipStream_t st);
+                         int disc, hipStream_t st);
 bool factor_fuses_forward(int dtype, int n);
 inline bool factor_forms_coeffs(int n) { return n == 16; }
 inline bool factor_solves_initial(int n) { return n == 16; }
@@ -89,7 +92,7 @@ hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,
                              int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                             hipStream_t st);
+                             int disc, hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 // MINRES (low = 0: FP64 inner vectors) or MINRES with FP64 iterative
 // refinement around an inner solve with FP32 vectors (low = 1); vecs holds
@@ -98,9 +101,9 @@ hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
                          const double *gam, const double *beta, double *x, double *r, void *vecs,
                          int low, double eps, int maxit, int max_outer, const int *idx, const int *count,
-                         uint32_t *state, double *relres, double *q, int32_t *iters, hipStream_t st);
+                         uint32_t *state, double *relres, double *q, int32_t *iters, int disc, hipStream_t st);
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
-                             double *gz, hipStream_t st);
+                             double *gz, int disc, hipStream_t st);
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);
 hipError_t launch_init_state(int S, uint32_t *state, double *relres, hipStream_t st);
 hipError_t launch_reset_subset(int P, const int *idx, const int *count, uint32_t *state,

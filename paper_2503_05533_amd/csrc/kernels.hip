@@ -27,7 +27,6 @@ namespace mlmc {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ inline double hmean(double p, double q) { return 2.0 * p * q / (p + q); }
 
 // Tile t of the lower block triangle, enumerated row by row: t = I(I+1)/2 + J.
 __device__ inline void tile_of(int t, int &I, int &J)
@@ -155,8 +154,9 @@ __global__ __launch_bounds__(256) void k_gemm64(int R, int Cn, int L, const doub
 // sc = diag(A)^(-1/2), gam (to the right neighbour), beta (to the row below).
 // Diagonal scaling S = diag(A)^(-1/2) of the 5-point operator, one thread per
 // padded unknown (x = sample, y = block of unknowns): A_PP is the sum of the
-// four harmonic-mean edge coefficients around node P.
-__global__ void k_scale(int n, const double *__restrict__ a, double *__restrict__ sc)
+// four edge coefficients around node P (harmonic means, or the P1 rule for
+// disc 1: node_faces).
+__global__ void k_scale(int n, const double *__restrict__ a, double *__restrict__ sc, int disc)
 {
     const int m = n - 1, M = n, np = n + 1;
     const int s = blockIdx.x, e = blockIdx.y * blockDim.x + threadIdx.x;
@@ -169,15 +169,14 @@ __global__ void k_scale(int n, const double *__restrict__ a, double *__restrict_
     }
     const double *as = a + (size_t)s * np * np;
     const int p = (j + 1) * np + (i + 1);
-    const double c = as[p];
-    const double d = hmean(c, as[p - 1]) + hmean(c, as[p + 1]) + hmean(c, as[p - np]) + hmean(c, as[p + np]);
-    sc[o] = 1.0 / sqrt(d);
+    const faces4 f = node_faces(disc, as, p, np);
+    sc[o] = 1.0 / sqrt(f.w + f.e + f.s + f.n);
 }
 
 // Scaled couplings of S A S: gam to the right neighbour (same grid row), beta
 // to the neighbour in the row below; 0 at the grid edge and in the pad.
 __global__ void k_coeffs(int n, const double *__restrict__ a, const double *__restrict__ sc,
-                         double *__restrict__ gam, double *__restrict__ beta)
+                         double *__restrict__ gam, double *__restrict__ beta, int disc)
 {
     const int m = n - 1, M = n, np = n + 1;
     const int s = blockIdx.x, e = blockIdx.y * blockDim.x + threadIdx.x;
@@ -192,8 +191,9 @@ __global__ void k_coeffs(int n, const double *__restrict__ a, const double *__re
     const double *as = a + (size_t)s * np * np;
     const int p = (j + 1) * np + (i + 1);
     const double sP = sc[o];
-    gam[o] = (i + 1 < m) ? -hmean(as[p], as[p + 1]) * sP * sc[o + 1] : 0.0;
-    beta[o] = (j > 0) ? -hmean(as[p], as[p - np]) * sP * sc[o - M] : 0.0;
+    const faces4 f = node_faces(disc, as, p, np);
+    gam[o] = (i + 1 < m) ? -f.e * sP * sc[o + 1] : 0.0;
+    beta[o] = (j > 0) ? -f.s * sP * sc[o - M] : 0.0;
 }
 
 // ------------------------------------------------------------------ factor
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_ir_tile(
     double *__restrict__ r, double *__restrict__ zbuf, double eps, int imax, int direct,
     const int *__restrict__ idx, const int *__restrict__ count, int64_t slot_base,
     uint32_t *__restrict__ state, double *__restrict__ relres, double *__restrict__ q,
-    int32_t *__restrict__ iters)
+    int32_t *__restrict__ iters, int disc)
 {
     constexpr int Tn = M / TR, T = Tn * (Tn + 1) / 2, E = TR * TR, m = M - 1;
     __shared__ double red[NT];
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_ir_tile(
     int trip = 0;
     for (;;) {
         __syncthreads();
-        const resid_out o = residual_pass<NT>(n, fconst, as, xs, rsb, red);
+        const resid_out o = residual_pass<NT>(n, fconst, as, xs, rsb, red, disc);
         rel = sqrt(o.rr) / sqrt(o.bb);
         sx = o.sx;
         st = ir_decide(st, rel, prev, sx, eps, trip, imax, direct);
@@ -457,11 +457,14 @@ __global__ __launch_bounds__(NT) void k_ir_tile(
 
 // dQ/dZ at every node for the adjoint gradient: with u and lambda the
 // (padded) primal and adjoint solutions (0 on the boundary),
-//   gz_e = -sum_{edges (e,o)} (lambda_e - lambda_o)(u_e - u_o) 2 a_o^2 a_e / (a_e + a_o)^2,
-// the derivative of the harmonic-mean edge coefficient with respect to
-// Z_e = log a_e.  One thread per node.
+//   gz_e = -sum_{edges f} (lambda_P - lambda_Q)(u_P - u_Q) d w_f / d Z_e,
+// Z_e = log a_e, over the edges f = (P, Q) whose coefficient w_f depends on
+// a_e.  disc 0: the four edges at e, d w_f / d Z_e = 2 a_o^2 a_e / (a_e + a_o)^2
+// (a_o the other end); disc 1: the four edges at e (weight 2/6) and the four
+// whose adjacent triangles have e as third vertex (weight 1/6),
+// d w_f / d Z_e = weight * a_e.  One thread per node.
 __global__ void k_adjoint_gz(int n, int S, const double *__restrict__ a, const double *__restrict__ u,
-                             const double *__restrict__ lam, double *__restrict__ gz)
+                             const double *__restrict__ lam, double *__restrict__ gz, int disc)
 {
     const int m = n - 1, M = n, np = n + 1;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -474,17 +477,36 @@ __global__ void k_adjoint_gz(int n, int S, const double *__restrict__ a, const d
     auto val = [&](const double *v, int jx, int jy) {
         return (jx >= 1 && jx <= m && jy >= 1 && jy <= m) ? v[(jy - 1) * M + (jx - 1)] : 0.0;
     };
-    const double ae = as[p], ue = val(us, ix, iy), le = val(ls, ix, iy);
+    auto inside = [&](int jx, int jy) { return jx >= 0 && jx <= n && jy >= 0 && jy <= n; };
+    // (lambda_P - lambda_Q)(u_P - u_Q) of the edge (px, py) - (qx, qy)
+    auto edge = [&](int px, int py, int qx, int qy) {
+        if (!inside(px, py) || !inside(qx, qy)) return 0.0;
+        return (val(ls, px, py) - val(ls, qx, qy)) * (val(us, px, py) - val(us, qx, qy));
+    };
+    const double ae = as[p];
     double acc = 0.0;
-    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+    if (!disc) {
+        const double ue = val(us, ix, iy), le = val(ls, ix, iy);
+        const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int jx = ix + dx[k], jy = iy + dy[k];
-        if (jx < 0 || jx > n || jy < 0 || jy > n) continue;
-        const double ao = as[jy * np + jx];
-        const double du = ue - val(us, jx, jy), dl = le - val(ls, jx, jy);
-        const double den = ae + ao;
-        acc -= dl * du * 2.0 * ao * ao * ae / (den * den);
+        for (int k = 0; k < 4; ++k) {
+            const int jx = ix + dx[k], jy = iy + dy[k];
+            if (!inside(jx, jy)) continue;
+            const double ao = as[jy * np + jx];
+            const double du = ue - val(us, jx, jy), dl = le - val(ls, jx, jy);
+            const double den = ae + ao;
+            acc -= dl * du * 2.0 * ao * ao * ae / (den * den);
+        }
+    } else {
+        // edges with e as an end node
+        double s2 = edge(ix, iy, ix + 1, iy) + edge(ix - 1, iy, ix, iy) + edge(ix, iy, ix, iy + 1) +
+                    edge(ix, iy - 1, ix, iy);
+        // edges whose triangles have e as third vertex: e north of the right
+        // node or south of the left node of an x-edge; east of the top node or
+        // west of the bottom node of a y-edge
+        double s1 = edge(ix - 1, iy - 1, ix, iy - 1) + edge(ix, iy + 1, ix + 1, iy + 1) +
+                    edge(ix - 1, iy - 1, ix - 1, iy) + edge(ix + 1, iy, ix + 1, iy + 1);
+        acc = -ae * (2.0 * s2 + s1) / 6.0;
     }
     gz[g] = acc;
 }
@@ -630,7 +652,7 @@ hipError_t launch_ir_t(const ir_args &g, hipStream_t st)
     constexpr int TR = tile_cfg<M>::TR, NT = nthreads<Tst, M, TR>();
     hipLaunchKernelGGL((k_ir_tile<Tst, M, TR, NT>), dim3(g.nblocks), dim3(NT), 0, st, g.n, g.fconst,
                        g.a, g.sc, g.beta, (const Tst *)g.factor, g.x, g.r, g.z, g.eps, g.imax,
-                       g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters);
+                       g.direct, g.idx, g.count, g.slot_base, g.state, g.relres, g.q, g.iters, g.disc);
     return hipGetLastError();
 }
 
@@ -723,27 +745,27 @@ hipError_t launch_grad_gemm(int S, int K, int P, const double *gz, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta,
+hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam, double *beta, int disc,
                          hipStream_t st)
 {
     if (S == 0) return hipSuccess;
     const dim3 grid((unsigned)S, (unsigned)(((n - 1) * n + 255) / 256));
-    hipLaunchKernelGGL(k_scale, grid, dim3(256), 0, st, n, a, sc);
-    hipLaunchKernelGGL(k_coeffs, grid, dim3(256), 0, st, n, a, sc, gam, beta);
+    hipLaunchKernelGGL(k_scale, grid, dim3(256), 0, st, n, a, sc, disc);
+    hipLaunchKernelGGL(k_coeffs, grid, dim3(256), 0, st, n, a, sc, gam, beta, disc);
     return hipGetLastError();
 }
 
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                          const double *gam, void *factor, const int *idx, const int *count,
                          int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                         hipStream_t st)
+                         int disc, hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
     if (fz && !factor_fuses_forward(dtype, n)) return hipErrorInvalidValue;
     if (x0 && (!fz || idx || !factor_solves_initial(n))) return hipErrorInvalidValue;
     if (use_blk(dtype, n))
         return launch_factor_blk(dtype, n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state,
-                                 frhs, fz, x0, st);
+                                 frhs, fz, x0, disc, st);
     switch (dtype) {
     case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
@@ -770,11 +792,11 @@ hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st)
 
 
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
-                             double *gz, hipStream_t st)
+                             double *gz, int disc, hipStream_t st)
 {
     const int64_t tot = (int64_t)S * (n + 1) * (n + 1);
     hipLaunchKernelGGL(k_adjoint_gz, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, S, a, u,
-                       lam, gz);
+                       lam, gz, disc);
     return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_minres_ir(int n, double fconst, const do
                                                   const int *__restrict__ idx, const int *__restrict__ count,
                                                   uint32_t *__restrict__ state,
                                                   double *__restrict__ relres,
-                                                  double *__restrict__ q, int32_t *__restrict__ iters)
+                                                  double *__restrict__ q, int32_t *__restrict__ iters, int disc)
 {
     constexpr bool LOW = sizeof(T) == 4;
     __shared__ double slots[2][NT / 64][2];
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(NT) void k_minres_ir(int n, double fconst, const do
     const bool zero_rhs = !(bval != 0.0);
     for (int outer = 0; !zero_rhs; ++outer) {
         if (outer > 0) {
-            const resid_out o = residual_pass<NT>(n, fconst, as, xs, rs, red);
+            const resid_out o = residual_pass<NT>(n, fconst, as, xs, rs, red, disc);
             rel = sqrt(o.rr) / sqrt(o.bb);
             sx = o.sx;
             if (!isfinite(rel)) {
@@ -248,27 +248,27 @@ template <typename T>
 hipError_t launch_minres_t(int n, int S, double fconst, const double *a, const double *sc, const double *gam,
                            const double *beta, double *x, double *r, void *vecs, double eps, int maxit,
                            int max_outer, const int *idx, const int *count, uint32_t *state, double *relres,
-                           double *q, int32_t *iters, hipStream_t st)
+                           double *q, int32_t *iters, int disc, hipStream_t st)
 {
     if (n >= 64)
         hipLaunchKernelGGL((k_minres_ir<T, 1024>), dim3(S), dim3(1024), 0, st, n, fconst, a, sc, gam, beta, x, r,
-                           (T *)vecs, eps, maxit, max_outer, idx, count, state, relres, q, iters);
+                           (T *)vecs, eps, maxit, max_outer, idx, count, state, relres, q, iters, disc);
     else
         hipLaunchKernelGGL((k_minres_ir<T, 256>), dim3(S), dim3(256), 0, st, n, fconst, a, sc, gam, beta, x, r,
-                           (T *)vecs, eps, maxit, max_outer, idx, count, state, relres, q, iters);
+                           (T *)vecs, eps, maxit, max_outer, idx, count, state, relres, q, iters, disc);
     return hipGetLastError();
 }
 
 hipError_t launch_minres(int n, int S, double fconst, const double *a, const double *sc,
                          const double *gam, const double *beta, double *x, double *r, void *vecs,
                          int low, double eps, int maxit, int max_outer, const int *idx, const int *count,
-                         uint32_t *state, double *relres, double *q, int32_t *iters, hipStream_t st)
+                         uint32_t *state, double *relres, double *q, int32_t *iters, int disc, hipStream_t st)
 {
     if (S == 0) return hipSuccess;
     return low ? launch_minres_t<float>(n, S, fconst, a, sc, gam, beta, x, r, vecs, eps, maxit, max_outer, idx,
-                                        count, state, relres, q, iters, st)
+                                        count, state, relres, q, iters, disc, st)
                : launch_minres_t<double>(n, S, fconst, a, sc, gam, beta, x, r, vecs, eps, maxit, max_outer, idx,
-                                         count, state, relres, q, iters, st);
+                                         count, state, relres, q, iters, disc, st);
 }
 
 }  // namespace mlmc

@@ -39,7 +39,8 @@ class _Config(ctypes.Structure):
                 ("f", ctypes.c_double), ("k_p", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("ir_max_iter", ctypes.c_int32), ("minres_max_iter", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("field", ctypes.c_int32), ("field_q", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("field", ctypes.c_int32), ("field_q", ctypes.c_double),
+                ("disc", ctypes.c_int32)]
 
 
 class _LevelOpts(ctypes.Structure):
@@ -134,6 +135,7 @@ class Config:
     seed: int = 1
     field: int = 0        # 0: exponential-covariance KL; 1: trigonometric field of sec. 5.1
     field_q: float = 2.0  # decay exponent q of the trigonometric field
+    disc: int = 0         # 0: finite volumes (harmonic faces); 1: P1 elements on right triangles
 
 
 def _ptr(t):

@@ -459,3 +459,51 @@ def test_fp8_factor_on_coarse_grids(eps):
     with pytest.raises(MLMCError, match="not available"):
         ctx.solve(2, torch.zeros((4, K), dtype=torch.float64), dtype="fp8", solver="direct_ir", eps=eps)
     ctx.close()
+
+
+# ----------------------------------------------------------------- P1 elements (the paper's discretisation)
+
+@pytest.mark.parametrize("level,S", [(0, 40), (1, 30), (2, 20), (3, 8), (4, 3)])
+def test_p1_elements_fp64_and_mixed(level, S):
+    """disc = 1 (P1 elements on right triangles) with the paper's first field
+    (s = 4, q = 2, sigma = 2), grids 8..128 (tile, row and MFMA kernels):
+    FP64 within 1e-12 of the oracle; FP32 and FP16 factors with refinement
+    and MINRES-IR reach eps, Q within the residual bound."""
+    torch = _torch()
+    K, s2, q, seed, n0 = 4, 4.0, 2.0, 41, 8
+    n = n0 << level
+    ctx = _ctx(n0=n0, L_max=level, K=K, sigma2=s2, corr_len=0.3, seed=seed, field=1, field_q=q, disc=1,
+               minres_max_iter=20000)
+    xi = si.splitmix64_normals(seed, level, 0, S, K)
+    phi = oracle.trig_basis(n, K, s2, q)
+    with oracle.disc_rule(1):
+        qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
+    out = ctx.solve(level, torch.from_numpy(xi), dtype="f64", solver="direct")
+    assert np.all(np.abs(out["q"].cpu().numpy() - qref) / qref <= 1e-12), level
+    eps = 1e-6
+    for dtype, solver in (("f32", "direct_ir"), ("f16", "direct_ir"), ("f32", "minres_ir")):
+        o = ctx.solve(level, torch.from_numpy(xi), dtype=dtype, solver=solver, eps=eps, want_u=True)
+        assert np.all(o["status"].cpu().numpy() & 1), (dtype, solver)
+        with oracle.disc_rule(1):
+            rr = oracle.relres_batch(n, phi, xi, o["u"].cpu().numpy())
+        assert np.all(rr < eps * (1 + 1e-6)), (dtype, solver, rr.max())
+        dq = np.abs(o["q"].cpu().numpy() - qref) / qref
+        assert np.all(dq <= rr * _bound(n, uref, qref) * (1 + 1e-6) + 1e-14), (dtype, solver)
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_p1_elements_adjoint(n):
+    """The adjoint under the P1 edge rule against the oracle's gradient."""
+    torch = _torch()
+    K, s2, q, seed = 4, 4.0, 2.0, 42
+    level = {16: 1, 64: 3}[n]
+    ctx = _ctx(n0=8, L_max=level, K=K, sigma2=s2, corr_len=0.3, seed=seed, field=1, field_q=q, disc=1)
+    xi = si.splitmix64_normals(seed, level, 0, 6, K)
+    qg, g = ctx.grad(level, torch.from_numpy(xi), None, eps_adjoint=1e-11, dtype="f64", solver="direct")
+    with oracle.disc_rule(1):
+        ref = oracle.grad_batch(n, oracle.trig_basis(n, K, s2, q), xi)
+    g = g.cpu().numpy()
+    for k in range(xi.shape[0]):
+        assert np.linalg.norm(g[k] - ref[k]) <= 1e-9 * np.linalg.norm(ref[k]), k
+    ctx.close()

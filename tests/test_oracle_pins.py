@@ -533,3 +533,81 @@ def test_trig_field_sigma0_and_symmetry():
     Q = oracle.solve_batch(n, Phi, xi)
     assert abs(Q[0] - Q[1]) <= 1e-13 * Q[0]
     assert abs(Q[0] - Q0[0]) > 1e-4 * Q0[0]  # the field does change Q
+
+
+def _p1_matrix_by_elements(n, a_nodes):
+    """Stiffness matrix of P1 elements on the unit square, assembled element
+    by element from the textbook formula K_T[i, j] = a_T |T| grad(phi_i) .
+    grad(phi_j) (gradients from the vertex coordinates), the cells cut along
+    (x, y)-(x+h, y+h), a_T the mean of the nodal coefficient over T's three
+    vertices; restricted to the interior nodes (x fastest)."""
+    h = 1.0 / n
+    m = n - 1
+    A = np.zeros((m * m, m * m))
+
+    def unk(ix, iy):
+        return (iy - 1) * m + (ix - 1) if 1 <= ix <= m and 1 <= iy <= m else -1
+
+    for cy in range(n):
+        for cx in range(n):
+            for tri in (((cx, cy), (cx + 1, cy), (cx + 1, cy + 1)), ((cx, cy), (cx + 1, cy + 1), (cx, cy + 1))):
+                P = np.array([[vx * h, vy * h] for vx, vy in tri])
+                B = np.array([[1.0, P[k, 0], P[k, 1]] for k in range(3)])
+                G = np.linalg.inv(B)[1:, :]           # column k: gradient of phi_k
+                area = 0.5 * abs(np.linalg.det(B))
+                aT = np.mean([a_nodes[vy * (n + 1) + vx] for vx, vy in tri])
+                KT = aT * area * (G.T @ G)
+                for i in range(3):
+                    for j in range(3):
+                        ui, uj = unk(*tri[i]), unk(*tri[j])
+                        if ui >= 0 and uj >= 0:
+                            A[ui, uj] += KT[i, j]
+    return A
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_p1_rule_equals_element_assembly(n):
+    """The oracle's P1 edge rule (disc 1) equals an element-by-element P1
+    assembly from the textbook element matrix: the harmonic (finite-volume)
+    rule, or an edge rule with its third vertices mirrored, does not."""
+    K = 3
+    Phi = oracle.trig_basis(n, K, 2.0, 1.0)
+    xi = np.array([[0.9, -1.3, 0.4]])
+    a = np.exp(Phi @ xi[0])
+    ref = _p1_matrix_by_elements(n, a)
+    with oracle.disc_rule(1):
+        A = oracle.dense_matrix(n, Phi, xi)
+    assert np.max(np.abs(A - ref)) <= 1e-13 * np.max(np.abs(ref))
+    A0 = oracle.dense_matrix(n, Phi, xi)
+    assert np.max(np.abs(A0 - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
+def test_p1_rule_hand_values_n2():
+    """n = 2: one unknown at (1/2, 1/2).  With the P1 rule its four edges are
+    west (2 a01 + 2 a11 + a12 + a00)/6, east (2 a11 + 2 a21 + a22 + a10)/6,
+    south (2 a10 + 2 a11 + a21 + a00)/6, north (2 a11 + 2 a12 + a22 + a01)/6
+    (a_ij at node (i/2, j/2)); A = their sum, u = h^2 / A, Q = h^2 u.  With
+    a_ij = 1 + i + 3 j: a00 1, a10 2, a20 3, a01 4, a11 5, a21 6, a02 7,
+    a12 8, a22 9: west (8 + 10 + 8 + 1)/6 = 27/6, east (10 + 12 + 9 + 2)/6 =
+    33/6, south (4 + 10 + 6 + 1)/6 = 21/6, north (10 + 16 + 9 + 4)/6 = 39/6:
+    A = 120/6 = 20, Q = (1/16)/20 = 1/320."""
+    n = 2
+    a = np.array([1.0 + i + 3 * j for j in range(3) for i in range(3)])
+    with oracle.disc_rule(1):
+        q = oracle.solve_batch(n, None, np.zeros((1, 1)), a_nodes=a[None, :])
+    assert abs(q[0] - 1.0 / 320.0) <= 1e-15
+
+
+def test_p1_adjoint_vs_central_differences():
+    """The oracle's adjoint under the P1 rule against central differences."""
+    n, K = 8, 3
+    Phi = oracle.trig_basis(n, K, 1.0, 1.5)
+    xi = np.array([[0.5, -0.8, 1.1]])
+    with oracle.disc_rule(1):
+        g = oracle.grad_batch(n, Phi, xi)[0]
+        fd = np.zeros(K)
+        for k in range(K):
+            e = np.zeros((1, K))
+            e[0, k] = 1e-6
+            fd[k] = (oracle.solve_batch(n, Phi, xi + e)[0] - oracle.solve_batch(n, Phi, xi - e)[0]) / 2e-6
+    assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
