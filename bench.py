@@ -26,9 +26,12 @@ Legs:
     achieved RMSE against an FP64 reference at TOL/5, with a 95% interval;
   * other workloads (legs): the single-level FP64 workload, the per-level
     precision sweep (FP32/BF16/FP16 and FP64 per level), all five levels in
-    one captured graph (refinement vs MINRES), the adjoint batch, and the
-    paper's quarter-precision example (FP8 factor on level 0, fixed N_l,
-    MSE against FP64 over many runs with shared xi, stored-bytes count);
+    one captured graph (refinement vs MINRES and MINRES-IR), the adjoint
+    batch, and the paper's two direct-solver examples on its own
+    discretisation and field (P1 elements, trigonometric field): the Table 1
+    precisions and the quarter-precision example (FP8 factor on level 0),
+    each at fixed N_l, MSE against FP64 over many runs with shared xi, and
+    the stored-bytes count;
   * CPU: the FP64 oracle on a bounded sample of the workload, host cores,
     one core, and LAPACK's banded Cholesky on the same systems.
 
@@ -120,9 +123,10 @@ def parse():
                    help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--ttr-runs", type=int, default=20, help="seeds of the time-to-RMSE leg")
-    p.add_argument("--legs", default="c0,c2,c3,c4,q43",
+    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5",
                    help="comma-separated other-workload legs to run (empty: none)")
     p.add_argument("--q43-runs", type=int, default=1000, help="runs of the quarter-precision leg")
+    p.add_argument("--paper5-runs", type=int, default=300, help="runs of the Table 1 precision leg")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run one plain streaming kernel (y = 2x, FP32) over this many MiB first; "
                         "its HBM counters calibrate the kernel traffic counters")
@@ -149,7 +153,7 @@ def _ctx_for(wname, **over):
     w = si.workload(wname)
     kw = dict(n0=w["n0"], L_max=max(w["levels"]), K=w["K"], sigma2=w["sigma2"], corr_len=w["corr_len"],
               seed=w["seed"], ir_max_iter=10, field=w.get("field", 0), field_q=w.get("field_q", 2.0),
-              k_p=w.get("k_p", 0.05))
+              k_p=w.get("k_p", 0.05), disc=w.get("disc", 0))
     kw.update(over)
     return w, MLMC(Config(**kw), device="cuda:0")
 
@@ -331,94 +335,97 @@ def stored_bytes(n, dtype, trips):
     return factor_entries(n, dtype if dtype in DT_BYTES else "f32") * b + vec * 8 * (2 + 3 * trips)
 
 
-def leg_q43(a):
-    """The paper's quarter-precision example (sec. 5.2): h0 = 1/4 (4..32
-    cells), trigonometric field s = 1, sigma = 1, k_p = 0.4; N_l from one
-    standard (FP64) adaptive run at TOL^2 = 2e-6; then R runs with those N_l,
-    each with fresh xi shared by the mixed path (FP8 factor on level 0,
-    FP16 on levels 1-3, FP64 refinement to delta_l) and the FP64 direct path;
-    MSE of both against an FP64 reference (adaptive at TOL/10), the relative
-    MSE difference, and the stored-bytes ratio."""
+def _paper_leg(a, wname, dts_of, vec_bytes_of, tol2, n_init, runs):
+    """The paper's fixed-sample comparison (sec. 5.2): N_l from one standard
+    (FP64) adaptive run at TOL^2 = tol2; then `runs` runs with those N_l, run r
+    drawing samples r*N_l ... of each level, shared by the mixed path (factor
+    precision dts_of(L)[l], FP64 refinement to delta_l) and the FP64 direct
+    path; the MSE of both against an FP64 reference (adaptive at TOL/10,
+    seed of its own), their relative difference, and the stored-bytes count
+    (stored_bytes) with this library's vector precisions and with the
+    paper's (vec_bytes_of(L)[l] bytes per vector entry)."""
     import numpy as np
-    w, ctx = _ctx_for("q43_n4-32_trig1")
-    L = max(w["levels"])
-    tol = (2e-6) ** 0.5
-    n_init = 100  # the paper does not state its initial sample count; 100 leaves N_l to the variance
+    w, ctx = _ctx_for(wname)
+    Lm = max(w["levels"])
+    tol = tol2 ** 0.5
     ctx.set_seed(w["seed"] + 1)
-    ref = ctx.estimate(tol / 10, n_init=n_init, dtypes=["f64"] * (L + 1), solver="direct", mixed=False)
+    ref = ctx.estimate(tol / 10, n_init=n_init, dtypes=["f64"] * (Lm + 1), solver="direct", mixed=False)
     ctx.set_seed(w["seed"])
-    std = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * (L + 1), solver="direct", mixed=False)
-    Lr = std["L"]
-    N = std["N"]
+    std = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * (Lm + 1), solver="direct", mixed=False)
+    Lr, N = std["L"], std["N"]
     eps = ctx.accuracy_targets(Lr)
-    dts = ["fp8"] + ["f16"] * Lr
-    R = a.q43_runs
+    dts = dts_of(Lr)
     est = {"mixed": [], "fp64": []}
-    trips = {"mixed": np.zeros((Lr + 1, 2)), "fp64": np.zeros((Lr + 1, 2))}
+    trips = np.zeros((Lr + 1, 2))
     promoted = np.zeros(Lr + 1, dtype=np.int64)
     noconv = {"mixed": 0, "fp64": 0}
     gpu_ms = {"mixed": 0.0, "fp64": 0.0}
-    for r in range(R):
+    for r in range(runs):
         q = {"mixed": 0.0, "fp64": 0.0}
         for l in range(Lr + 1):
             xi = ctx.fill_xi(l, r * N[l], N[l])
             for name, o in (("mixed", dict(dtype=dts[l], solver="direct_ir", eps_fine=eps[l],
                                            eps_coarse=eps[l - 1] if l else 0.0)),
                             ("fp64", dict(dtype="f64", solver="direct"))):
-                res = ctx.sample_level(l, xi, **o)
-                st = res["stats"]
+                st = ctx.sample_level(l, xi, **o)["stats"]
                 noconv[name] += st["n_noconv"]
                 q[name] += st["sum_y"] / N[l]
-                trips[name][l] += (st["mean_iters"], st["mean_iters_coarse"])
                 gpu_ms[name] += st["gpu_ms"]
                 if name == "mixed":
+                    trips[l] += (st["mean_iters"], st["mean_iters_coarse"])
                     promoted[l] += st["n_promoted"]
         for k in q:
             est[k].append(q[k])
-    out = dict(workload="q43_n4-32_trig1", tol=tol, runs=R, N=N, L=Lr, eps=eps, precision=dts,
-               reference=dict(tol=tol / 10, estimate=ref["estimate"], N=ref["N"]))
+    out = dict(workload=wname, disc=w.get("disc", 0), tol2=tol2, runs=runs, n_init=n_init, N=N, L=Lr,
+               eps=eps, precision=dts, reference=dict(tol=tol / 10, estimate=ref["estimate"], N=ref["N"]))
     for k in est:
         mse, ci = _ci95_mse(np.array(est[k]) - ref["estimate"])
-        out[k] = dict(mse=mse, mse_ci95=ci, gpu_ms_per_run=gpu_ms[k] / R)
+        out[k] = dict(mse=mse, mse_ci95=ci, gpu_ms_per_run=gpu_ms[k] / runs)
     d = np.array(est["mixed"]) - np.array(est["fp64"])
     out["mse_rel_diff"] = out["mixed"]["mse"] / out["fp64"]["mse"] - 1.0
-    out["rmse_rel_diff"] = (out["mixed"]["mse"] / out["fp64"]["mse"]) ** 0.5 - 1.0
     out["max_abs_estimate_diff"] = float(np.max(np.abs(d)))
     out["promoted_per_level"] = promoted.tolist()
     out["noconv"] = noconv
-    mean_trips = trips["mixed"] / R
+    mean_trips = trips / runs
     out["mean_corrections"] = mean_trips.tolist()
-    # stored bytes per level (fine + coarse solve of every Y_l sample)
-    by_m, by_d = [], []
+    # stored bytes per level: the fine and the coarse solve of every Y_l sample
+    vb = vec_bytes_of(Lr)
+    fbytes = {"fp8": 1, "f16": 2, "bf16": 2, "f32": 4}
+    by_m, by_d, by_p = [], [], []
     for l in range(Lr + 1):
         nf = w["n0"] << l
-        bm = stored_bytes(nf, dts[l], mean_trips[l][0]) + (stored_bytes(nf // 2, dts[l], mean_trips[l][1]) if l else 0)
-        bd = stored_bytes(nf, "f64", 0) + (stored_bytes(nf // 2, "f64", 0) if l else 0)
+        grids = [(nf, mean_trips[l][0])] + ([(nf // 2, mean_trips[l][1])] if l else [])
+        bm = sum(stored_bytes(nn, dts[l], t) for nn, t in grids)
+        bd = sum(stored_bytes(nn, "f64", 0) for nn, _ in grids)
+        bp = sum(factor_entries(nn, "f32") * fbytes[dts[l]] + (nn - 1) * nn * vb[l] * (2 + 3 * t) for nn, t in grids)
         by_m.append(N[l] * bm)
         by_d.append(N[l] * bd)
-    # the same count with the vectors at the paper's precisions for this example
-    # (level 0 qhhh: u = u_r = half; levels 1-3 hhss: u = u_r = single; the
-    # FP64 reference: double), on the same correction counts
-    vb = [2] + [4] * Lr
-    by_p = []
-    for l in range(Lr + 1):
-        nf = w["n0"] << l
-        fb = {"fp8": 1, "f16": 2}[dts[l]]
-        per = 0.0
-        for nn, t in ([(nf, mean_trips[l][0])] + ([(nf // 2, mean_trips[l][1])] if l else [])):
-            per += factor_entries(nn, "f32") * fb + (nn - 1) * nn * vb[l] * (2 + 3 * t)
-        by_p.append(N[l] * per)
-    out["stored_bytes_ratio_paper_precisions"] = sum(by_d) / sum(by_p)
+        by_p.append(N[l] * bp)
     out["stored_bytes_ratio_per_level"] = [x / y for x, y in zip(by_d, by_m)]
     out["stored_bytes_ratio_total"] = sum(by_d) / sum(by_m)
-    out["factor_bytes_ratio_total"] = sum(
-        N[l] * (factor_entries(w["n0"] << l, "f64") * 8 + (factor_entries((w["n0"] << l) // 2, "f64") * 8 if l else 0))
-        for l in range(Lr + 1)) / sum(
-        N[l] * (factor_entries(w["n0"] << l, "f32") * {"fp8": 1, "f16": 2}[dts[l]]
-                + (factor_entries((w["n0"] << l) // 2, "f32") * {"fp8": 1, "f16": 2}[dts[l]] if l else 0))
-        for l in range(Lr + 1))
+    out["stored_bytes_ratio_paper_precisions_per_level"] = [x / y for x, y in zip(by_d, by_p)]
+    out["stored_bytes_ratio_paper_precisions"] = sum(by_d) / sum(by_p)
     ctx.close()
     return out
+
+
+def leg_q43(a):
+    """The paper's quarter-precision example (sec. 5.2, last paragraph): P1
+    elements, h0 = 1/4 (4..32 cells), trigonometric field s = 1, sigma = 1,
+    k_p = 0.4, TOL^2 = 2e-6; level 0 `qhhh` -> FP8 factor, levels 1-3 `hhss`
+    -> FP16 factor; the paper's vectors: half on level 0, single above."""
+    return _paper_leg(a, "q43_n4-32_trig1", lambda L: ["fp8"] + ["f16"] * L, lambda L: [2] + [4] * L,
+                      2e-6, 100, a.q43_runs)
+
+
+def leg_paper5(a):
+    """The paper's direct-solver example (sec. 5.2): P1 elements, h0 = 1/8,
+    trigonometric field s = 4, q = 2, sigma = 2, k_p = 0.05, TOL^2 = 2e-6; the
+    precisions of Table 1 (right): level 0 `hhss` -> FP16 factor, level 1
+    `ssss` -> FP32, levels 2+ `ssdd` -> FP32; the paper's vectors: single on
+    levels 0-1, double from level 2."""
+    return _paper_leg(a, "paper5_n8-128_trig4", lambda L: ["f16", "f32"] + ["f32"] * (L - 1),
+                      lambda L: [4, 4] + [8] * (L - 1), 2e-6, 100, a.paper5_runs)
 
 
 def cpu_single_and_lapack(oracle, si, w, ctx, levels, Ns, phis, budget):
@@ -681,7 +688,7 @@ def main():
     sel = [x for x in a.legs.split(",") if x]
     ctx_main = ctx
     for name in sel:
-        fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43}[name]
+        fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43, "paper5": leg_paper5}[name]
         t0 = time.perf_counter()
         legs[name] = fn(a)
         legs[name]["leg_wall_s"] = time.perf_counter() - t0
