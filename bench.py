@@ -118,7 +118,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-per-level", action="store_true")
-    p.add_argument("--autotune", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="skip the autotuner (refinement waves per row pair, FP16/BF16 product precision)")
     p.add_argument("--ttr-tol", type=float, default=2e-5,
                    help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -254,12 +255,13 @@ def leg_c2(a):
         for dt in ("f64", "f32", "bf16", "f16"):
             o = dict(dtype=dt, solver="direct" if dt == "f64" else "direct_ir", eps_fine=eps[l],
                      eps_coarse=eps[l - 1] if l else 0.0)
+            tuned = None if (a.no_autotune or dt == "f64") else ctx.autotune(l, xi, **o)
             plan = ctx.plan_levels([l], [xi], [o], use_graph=False)
             ms = _event_ms(plan.run, reps=2)
             st = plan.run(stats=True)["stats"][0]
             row[dt] = dict(ms=ms, samples_per_s=N / (ms / 1e3), promoted=st["n_promoted"],
                            noconv=st["n_noconv"], mean_corrections=st["mean_iters"],
-                           mean_corrections_coarse=st["mean_iters_coarse"])
+                           mean_corrections_coarse=st["mean_iters_coarse"], autotuned=tuned)
             del plan
         best = min((d for d in ("f32", "bf16", "f16") if row[d]["noconv"] == 0), key=lambda d: row[d]["ms"])
         row["fastest_mixed"] = best
@@ -273,8 +275,9 @@ def leg_c2(a):
 def leg_c3(a):
     """batched5_n16-256_K128: all five levels (40000 ... 200 samples) as one
     replayed HIP graph, FP32 factor + FP64 refinement against batched MINRES
-    (FP64) and MINRES-IR (FP32 inner vectors), all to delta_l; and the eager
-    schedule for the refinement path."""
+    (FP64), MINRES-IR (FP32 inner vectors) and multigrid-preconditioned CG
+    (the gamma = 2 solver), all to delta_l; and the eager schedule for the
+    refinement path."""
     w, ctx = _ctx_for("batched5_n16-256_K128", minres_max_iter=20000)
     levels, Ns = w["levels"], w["N"]
     L = max(levels)
@@ -282,7 +285,8 @@ def leg_c3(a):
     xis = [ctx.fill_xi(l, 0, N) for l, N in zip(levels, Ns)]
     out = dict(workload="batched5_n16-256_K128", N=Ns, eps=eps)
     for name, solver, graph in (("direct_ir_graph", "direct_ir", True), ("direct_ir_eager", "direct_ir", False),
-                                ("minres_graph", "minres", True), ("minres_ir_graph", "minres_ir", True)):
+                                ("minres_graph", "minres", True), ("minres_ir_graph", "minres_ir", True),
+                                ("mgcg_graph", "mgcg", True)):
         o = [dict(dtype="f32", solver=solver, eps_fine=eps[l], eps_coarse=eps[l - 1] if l else 0.0)
              for l in levels]
         plan = ctx.plan_levels(levels, xis, o, use_graph=graph)
@@ -294,6 +298,7 @@ def leg_c3(a):
         del plan
     out["direct_ir_vs_minres"] = out["minres_graph"]["ms"] / out["direct_ir_graph"]["ms"]
     out["minres_ir_vs_minres"] = out["minres_graph"]["ms"] / out["minres_ir_graph"]["ms"]
+    out["mgcg_vs_direct_ir"] = out["direct_ir_graph"]["ms"] / out["mgcg_graph"]["ms"]
     ctx.close()
     return out
 
@@ -513,10 +518,10 @@ def main():
 
     om, o64 = opts(a.dtype, "direct_ir"), opts("f64", "direct")
     tuned = None
-    if a.autotune:
+    if not a.no_autotune:
         tuned = {cells[i]: ctx.autotune(l, xis[i], **{k: v for k, v in om[i].items() if k != "promote"})
                  for i, l in enumerate(levels)}
-        log("autotuned refinement variants", tuned)
+        log("autotuned (fine, coarse): waves per row pair | fp32 products << 4", tuned)
     total = float(sum(Ns))
 
     def step(plan):

@@ -85,8 +85,17 @@ typedef enum { MLMC_F64 = 0, MLMC_F32 = 1, MLMC_BF16 = 2, MLMC_F16 = 3, MLMC_FP8
  *                  correction residual by max(eps / (2 rel), 1e-5); FP64
  *                  residual and update, the same stop test, at most
  *                  ir_max_iter refinements and minres_max_iter inner
- *                  iterations in all.  factor_dtype is ignored by both. */
-typedef enum { MLMC_DIRECT = 0, MLMC_DIRECT_IR = 1, MLMC_MINRES = 2, MLMC_MINRES_IR = 3 } mlmc_solver;
+ *                  iterations in all.  factor_dtype is ignored by both.
+ *   MLMC_MGCG      conjugate gradients in FP64 preconditioned by one
+ *                  geometric multigrid V-cycle in FP32 (red-black
+ *                  Gauss-Seidel smoothing, edge coefficients coarsened by
+ *                  series averaging, grids down to 2 cells), a solver whose
+ *                  cost grows like the number of unknowns (gamma = 2 of the
+ *                  cost model of Sec. 4.4); stops on the true FP64 relative
+ *                  residual < eps, at most minres_max_iter iterations.
+ *                  factor_dtype is ignored. */
+typedef enum { MLMC_DIRECT = 0, MLMC_DIRECT_IR = 1, MLMC_MINRES = 2, MLMC_MINRES_IR = 3,
+               MLMC_MGCG = 4 } mlmc_solver;
 
 typedef struct {
     int32_t n0;              /* cells per side on level 0 (power of two, >= 4) */
@@ -268,11 +277,16 @@ int mlmc_sample_levels(mlmc_ctx *ctx, int32_t n_levels, const int32_t *levels, c
                        size_t ws_bytes, double *const *y_dev, mlmc_level_stats *stats_host,
                        int32_t use_graph, void *stream);
 
-/* Autotuner: times the candidate refinement-kernel configurations (waves
- * per block-row pair, grids with n >= 64) on the given level and samples
- * (xi_dev [n x K], the workspace of mlmc_sample_level) and keeps the fastest
- * for the factor dtype of opts in the context; chosen[0] (fine grid) and
- * chosen[1] (coarse grid) receive the choice (0 = single configuration).
+/* Autotuner: on the given level and samples (xi_dev [n x K], the workspace
+ * of mlmc_sample_level) times every candidate configuration of each of the
+ * level's grids as the whole solve of that grid (factorisation and
+ * refinement) and keeps the fastest in the context for the factor dtype of
+ * opts and that grid, for every later call.  Candidates: the refinement
+ * kernel's waves per block-row pair (1 or 2, grids with n >= 64) and, for
+ * the FP16/BF16 factors on grids with n >= 32, the factorisation's block
+ * products in the storage format (faster, a less accurate factor) or in
+ * FP32.  chosen[0] (fine grid) and chosen[1] (coarse grid) receive
+ * waves | (fp32_products << 4) (0 = a single configuration).
  * Synchronises the stream. */
 int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
                   const mlmc_level_opts *opts, void *ws_dev, size_t ws_bytes, int32_t *chosen,

@@ -35,6 +35,9 @@ struct mlmc_ctx {
     std::vector<hipEvent_t> ev_pool;
     // refinement-kernel variant per (factor dtype, log2 n), 0 = built-in default
     int ir_variant[5][9] = {};
+    // factorisation variant per (factor dtype, log2 n): 0 default, 1 FP32 MFMA
+    // products for the FP16/BF16 factors (autotuner)
+    int factor_variant[5][9] = {};
     // concurrent multi-level launches: two streams per level, events, cached graph
     std::vector<hipStream_t> lstreams;
     std::vector<hipEvent_t> levents;
@@ -90,6 +93,8 @@ inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p & (a - 1)) =
 inline size_t dtype_bytes(int dt) { return dt == MLMC_F64 ? 8 : (dt == MLMC_F32 ? 4 : (dt == MLMC_FP8 ? 1 : 2)); }
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 inline bool is_minres(int solver) { return solver == MLMC_MINRES || solver == MLMC_MINRES_IR; }
+// solvers without a factorisation
+inline bool is_iterative(int solver) { return is_minres(solver) || solver == MLMC_MGCG; }
 inline int ilog2(int v) { int l = 0; while ((1 << (l + 1)) <= v) ++l; return l; }
 
 // ---------------------------------------------------------------- kernel timing
@@ -259,6 +264,7 @@ struct grid_layout {
     size_t off_a, off_sc, off_gam, off_beta, off_x, off_r, off_z, off_lam, off_gz;
     size_t off_factor, off_promo, off_state, off_relres, off_q, off_iters, off_idx;
     size_t off_mr;  // MINRES vectors (7 per sample, FP64 or FP32)
+    size_t off_mgv, off_mgh;  // multigrid CG: 5 FP64 node vectors, the FP32 hierarchy
     size_t off_cnt; // device counters (promotion)
     int64_t promo_slots;
     size_t bytes;
@@ -284,7 +290,7 @@ grid_layout make_layout(int n, int64_t S, const mlmc_level_opts &o)
     L.off_r = take(vb);
     L.off_z = take(vb);
     L.off_lam = take(vb);
-    const bool direct = !is_minres(o.solver);
+    const bool direct = !is_iterative(o.solver);
     const int dt = o.solver == MLMC_DIRECT ? MLMC_F64 : o.factor_dtype;
     L.off_factor = take(direct ? S * factor_entries_per_sample(dt, n) * dtype_bytes(dt) : 0);
     // every sample can be re-solved with an FP64 factor without a host round trip
@@ -292,6 +298,9 @@ grid_layout make_layout(int n, int64_t S, const mlmc_level_opts &o)
     L.off_promo = take(L.promo_slots * factor_entries_per_sample(MLMC_F64, n) * 8);
     // 7 FP64 vectors per sample: also room for the FP64 re-solve of MINRES-IR samples
     L.off_mr = take(is_minres(o.solver) ? 7 * S * L.vec * 8 : 0);
+    const bool mg = o.solver == MLMC_MGCG;
+    L.off_mgv = take(mg ? 5 * S * (size_t)(n + 1) * (n + 1) * 8 : 0);
+    L.off_mgh = take(mg ? S * mgcg_floats_per_sample(n) * 4 : 0);
     L.off_state = take(S * 4);
     L.off_relres = take(S * 8);
     L.off_q = take(S * 8);
@@ -348,7 +357,7 @@ int check_opts(mlmc_ctx *ctx, const mlmc_level_opts *o, int level, bool pair)
     if (!o) return fail(ctx, MLMC_EINVAL, "opts is NULL");
     if (o->factor_dtype < MLMC_F64 || o->factor_dtype > MLMC_FP8)
         return fail(ctx, MLMC_EINVAL, "bad factor dtype");
-    if (o->solver < MLMC_DIRECT || o->solver > MLMC_MINRES_IR) return fail(ctx, MLMC_EINVAL, "bad solver");
+    if (o->solver < MLMC_DIRECT || o->solver > MLMC_MGCG) return fail(ctx, MLMC_EINVAL, "bad solver");
     if (!(o->eps_fine >= 0.0) || !(o->eps_coarse >= 0.0)) return fail(ctx, MLMC_EINVAL, "bad eps");
     if (o->solver == MLMC_DIRECT_IR) {
         const int n = ctx->cfg.n0 << level;
@@ -401,7 +410,7 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
         HIPCHK(launch_reset_subset(np, idx, cnt, state, relres, st));
         PROF(6, n, np, launch_factor(MLMC_F64, n, np, at<double>(ws, L.off_a), at<double>(ws, L.off_sc),
                                      at<double>(ws, L.off_beta), at<double>(ws, L.off_gam), pf, idx, cnt, 0,
-                                     state, 0.0, nullptr, nullptr, ctx->cfg.disc, st));
+                                     state, 0.0, nullptr, nullptr, ctx->cfg.disc, 0, st));
         ir_args p = g;
         p.nblocks = np;
         p.factor = pf;
@@ -435,6 +444,13 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     double *relres = at<double>(ws, L.off_relres);
     PROF(0, n, S, launch_field(S, K, P, xi, ctx->phit[level], a, st));
     // the n = 16 factorisation forms the scaled operator itself
+    if (o.solver == MLMC_MGCG) {
+        HIPCHK(launch_init_state(S, state, relres, st));
+        PROF(5, n, S, launch_mgcg(n, S, ctx->cfg.f, a, at<double>(ws, L.off_x), at<double>(ws, L.off_mgv),
+                                  at<float>(ws, L.off_mgh), eps, ctx->cfg.minres_max_iter, state, relres, q, iters,
+                                  ctx->cfg.disc, st));
+        return MLMC_OK;
+    }
     if (is_minres(o.solver) || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, ctx->cfg.disc, st));
     HIPCHK(launch_init_state(S, state, relres, st));
     if (is_minres(o.solver)) {
@@ -470,7 +486,8 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     double *x = at<double>(ws, L.off_x);
     PROF(2, n, S, launch_factor(dt, n, S, a, sc, beta, gam, factor, nullptr, nullptr, 0, state, h * h * ctx->cfg.f,
                                 fwd ? at<double>(ws, L.off_z) : nullptr,
-                                fwd && factor_solves_initial(n) ? x : nullptr, ctx->cfg.disc, st));
+                                fwd && factor_solves_initial(n) ? x : nullptr, ctx->cfg.disc,
+                                ctx->factor_variant[dt][ilog2(n)], st));
     return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, x, q, iters, st, fwd);
 }
 
@@ -1015,7 +1032,7 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
     if (n < 1 || !xi_dev || !ws_dev) return fail(ctx, MLMC_EINVAL, "autotune: bad arguments");
     const level_layout LL = make_level_layout(ctx->cfg, level, n, *opts);
     if (ws_bytes < LL.bytes) return fail(ctx, MLMC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, LL.bytes);
-    if (is_minres(opts->solver)) return MLMC_OK;
+    if (is_iterative(opts->solver)) return MLMC_OK;
     hipStream_t st = (hipStream_t)stream;
     const int dt = opts->solver == MLMC_DIRECT ? MLMC_F64 : opts->factor_dtype;
     const bool was = ctx->prof_on;
@@ -1024,27 +1041,40 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
         const int lv = level - g, nn = ctx->cfg.n0 << lv;
         const grid_layout &L = g ? LL.coarse : LL.fine;
         void *w = at<void>(ws_dev, g ? LL.off_coarse : LL.off_fine);
+        // candidates: the refinement kernel's waves per row pair (grids from
+        // n = 64) and, for the FP16/BF16 factors on the MFMA grids (n >= 32),
+        // products in the storage format or in FP32; each timed as the whole
+        // solve of the grid (factor and refinement: a faster factorisation
+        // may cost corrections)
+        const int nir = (use_blk(dt, nn) && nn >= 64) ? 2 : 0;
+        const int nfv = ((dt == MLMC_F16 || dt == MLMC_BF16) && nn >= 32) ? 2 : 1;
         int best = 0;
-        if (use_blk(dt, nn) && nn >= 64) {
+        if (nir > 0 || nfv > 1) {
             float best_ms = 1e30f;
-            for (int var = 1; var <= 2; ++var) {
-                ctx->ir_variant[dt][ilog2(nn)] = var;
-                for (int rep = 0; rep < 3; ++rep) {
-                    if (rep == 1) HIPCHK(hipEventRecord(ctx->ev0, st));
-                    rc = solve_grid(ctx, L, lv, xi_dev, *opts, g ? opts->eps_coarse : opts->eps_fine, w,
-                                    at<double>(ws_dev, g ? LL.off_qc : LL.off_qf), nullptr, st);
-                    if (rc) return rc;
+            int best_ir = 0, best_fv = 0;
+            for (int fv = 0; fv < nfv; ++fv)
+                for (int var = (nir ? 1 : 0); var <= nir; ++var) {
+                    ctx->ir_variant[dt][ilog2(nn)] = var;
+                    ctx->factor_variant[dt][ilog2(nn)] = fv;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        if (rep == 1) HIPCHK(hipEventRecord(ctx->ev0, st));
+                        rc = solve_grid(ctx, L, lv, xi_dev, *opts, g ? opts->eps_coarse : opts->eps_fine, w,
+                                        at<double>(ws_dev, g ? LL.off_qc : LL.off_qf), nullptr, st);
+                        if (rc) return rc;
+                    }
+                    HIPCHK(hipEventRecord(ctx->ev1, st));
+                    HIPCHK(hipEventSynchronize(ctx->ev1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best_ir = var;
+                        best_fv = fv;
+                    }
                 }
-                HIPCHK(hipEventRecord(ctx->ev1, st));
-                HIPCHK(hipEventSynchronize(ctx->ev1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = var;
-                }
-            }
-            ctx->ir_variant[dt][ilog2(nn)] = best;
+            ctx->ir_variant[dt][ilog2(nn)] = best_ir;
+            ctx->factor_variant[dt][ilog2(nn)] = best_fv;
+            best = best_ir | (best_fv << 4);
         }
         if (chosen) chosen[g] = best;
     }
@@ -1375,7 +1405,7 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev, con
     int rc = check_level(ctx, level);
     if (rc) return rc;
     if ((rc = check_opts(ctx, opts, level, false))) return rc;
-    if (is_minres(opts->solver)) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not MINRES)");
+    if (is_iterative(opts->solver)) return fail(ctx, MLMC_EINVAL, "grad needs a factorisation (not an iterative solver)");
     if (n < 0 || n > 4000000) return fail(ctx, MLMC_EINVAL, "bad sample count (0..4e6)");
     if (n == 0) return MLMC_OK;
     if (!xi_dev || !ws_dev || !grad_xi_dev || !(eps_adjoint > 0.0) || !aligned(xi_dev, 8) ||

@@ -281,7 +281,11 @@ __device__ inline void wave_lds_sync()
 // its CU in the multi-level step (measured: slower and erratic steps).
 template <typename Tac, int M> constexpr bool factor_fwd_ok() { return sizeof(Tac) == 4; }
 
-template <typename Tst, int M>
+// H16: for the FP16/BF16 factors, form the products in the storage format
+// (one 16x16x16 MFMA per block product); false: four FP32 16x16x4 products
+// (the autotuner chooses per grid, as the faster factorisation can cost more
+// corrections).
+template <typename Tst, int M, bool H16 = true>
 __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S, const double *__restrict__ beta,
                                                              const double *__restrict__ gam,
                                                              Tst *__restrict__ factor,
@@ -409,7 +413,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
             for (int x = 0; x < 2; ++x) {
                 const int row = x ? NB - 1 - wk : wk;
                 V4 u = V4{0, 0, 0, 0};
-                if constexpr (mfma_in_storage<Tst>()) {
+                if constexpr (H16 && mfma_in_storage<Tst>()) {
                     float av[4], bv[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
@@ -434,7 +438,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                 if (I != K && J != K) {
                     // C[I,J] += U_I V_J^T
                     Tac av[4], bv[4];
-                    if constexpr (mfma_in_storage<Tst>()) {
+                    if constexpr (H16 && mfma_in_storage<Tst>()) {
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
                             av[c] = U[lc * LD + 4 * lr + c];
@@ -460,7 +464,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                 } else {
                     // C[K,J] = (V_J P^{-1})^T = P^{-1} V_J^T = -((-P^{-1}) V_J^T)
                     V4 z = V4{0, 0, 0, 0};
-                    if constexpr (mfma_in_storage<Tst>()) {
+                    if constexpr (H16 && mfma_in_storage<Tst>()) {
                         float av[4], bv[4];
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
@@ -1580,7 +1584,7 @@ template <> struct solve_cfg<double, 256> { static constexpr int G = 1; static c
 template <typename Tst, int M>
 hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
               const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
-              double *fz, double *x0, int disc, hipStream_t st)
+              double *fz, double *x0, int disc, int variant, hipStream_t st)
 {
     if constexpr (M == 16) {
         if (nb == 0) return hipSuccess;
@@ -1591,6 +1595,9 @@ hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *g
         else
             hipLaunchKernelGGL((k_factor_rows16<Tst, false>), dim3(grid), dim3(256), 0, st, nb, a, sc, beta,
                                (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0, disc);
+    } else if (variant == 1 && mfma_in_storage<Tst>()) {
+        hipLaunchKernelGGL((k_factor_mfma<Tst, M, false>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta,
+                           gam, (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
     } else {
         hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
                            (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
@@ -1654,14 +1661,14 @@ hipError_t li_m(const ir_args &g, hipStream_t st)
 template <typename Tst>
 hipError_t lf_m(int M, int nb, const double *a, double *sc, double *beta, const double *gam, void *factor,
                 const int *idx, const int *count, int64_t slot_base, uint32_t *state, double frhs,
-                double *fz, double *x0, int disc, hipStream_t st)
+                double *fz, double *x0, int disc, int variant, hipStream_t st)
 {
     switch (M) {
-    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 16: return lf<Tst, 16>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 32: return lf<Tst, 32>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 64: return lf<Tst, 64>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 128: return lf<Tst, 128>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 256: return lf<Tst, 256>(nb, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1680,13 +1687,13 @@ hipError_t launch_field_mfma(int S, int K, int P, const double *xi, const double
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,
                              int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                             int disc, hipStream_t st)
+                             int disc, int variant, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
-    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, st);
+    case 0: return lf_m<double>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 1: return lf_m<float>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 2: return lf_m<__hip_bfloat16>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
+    case 3: return lf_m<__half>(n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state, frhs, fz, x0, disc, variant, st);
     }
     return hipErrorInvalidValue;
 }

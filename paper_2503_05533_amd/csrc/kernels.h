@@ -76,11 +76,12 @@ hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam,
 // forward sweep of the solve for the right-hand side frhs (constant, interior
 // unknowns) scaled by sc, writing z to fz (the refinement's z buffer); where
 // factor_solves_initial(n), with x0 != NULL, the back sweep as well, writing
-// the initial solve to x0.
+// the initial solve to x0.  variant (the autotuner's choice, 0 default): 1
+// forms the FP16/BF16 factors' MFMA products in FP32 instead of their format.
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                          const double *gam, void *factor, const int *idx, const int *count,
                          int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                         int disc, hipStream_t st);
+                         int disc, int variant, hipStream_t st);
 bool factor_fuses_forward(int dtype, int n);
 inline bool factor_forms_coeffs(int n) { return n == 16; }
 inline bool factor_solves_initial(int n) { return n == 16; }
@@ -92,7 +93,7 @@ hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,
                              int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                             int disc, hipStream_t st);
+                             int disc, int variant, hipStream_t st);
 hipError_t launch_ir_blk(int dtype, const ir_args &g, hipStream_t st);
 // MINRES (low = 0: FP64 inner vectors) or MINRES with FP64 iterative
 // refinement around an inner solve with FP32 vectors (low = 1); vecs holds
@@ -102,6 +103,14 @@ hipError_t launch_minres(int n, int S, double fconst, const double *a, const dou
                          const double *gam, const double *beta, double *x, double *r, void *vecs,
                          int low, double eps, int maxit, int max_outer, const int *idx, const int *count,
                          uint32_t *state, double *relres, double *q, int32_t *iters, int disc, hipStream_t st);
+// Conjugate gradients in FP64 preconditioned by an FP32 geometric multigrid
+// V-cycle (gamma = 2 solver), one workgroup per sample: the solution into the
+// padded layout x; vecs holds 5 (n+1)^2 doubles and mg
+// mgcg_floats_per_sample(n) floats per sample.
+size_t mgcg_floats_per_sample(int n);
+hipError_t launch_mgcg(int n, int S, double fconst, const double *a, double *x, double *vecs, float *mg,
+                       double eps, int maxit, uint32_t *state, double *relres, double *q, int32_t *iters, int disc,
+                       hipStream_t st);
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
                              double *gz, int disc, hipStream_t st);
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);

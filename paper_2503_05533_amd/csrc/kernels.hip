@@ -758,14 +758,14 @@ hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam,
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                          const double *gam, void *factor, const int *idx, const int *count,
                          int64_t slot_base, uint32_t *state, double frhs, double *fz, double *x0,
-                         int disc, hipStream_t st)
+                         int disc, int variant, hipStream_t st)
 {
     if (nblocks == 0) return hipSuccess;
     if (fz && !factor_fuses_forward(dtype, n)) return hipErrorInvalidValue;
     if (x0 && (!fz || idx || !factor_solves_initial(n))) return hipErrorInvalidValue;
     if (use_blk(dtype, n))
         return launch_factor_blk(dtype, n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state,
-                                 frhs, fz, x0, disc, st);
+                                 frhs, fz, x0, disc, variant, st);
     switch (dtype) {
     case 0: return launch_factor_m<double>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);
     case 1: return launch_factor_m<float>(n, nblocks, beta, gam, factor, idx, count, slot_base, state, st);

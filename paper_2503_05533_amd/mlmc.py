@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmlmc.so")
 MLMC_OK, MLMC_ENOCONV = 0, 1
 MLMC_EINVAL, MLMC_ENOMEM, MLMC_EHIP, MLMC_ENOTIMPL = -1, -2, -3, -4
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "fp8": 4}
-SOLVERS = {"direct": 0, "direct_ir": 1, "minres": 2, "minres_ir": 3}
+SOLVERS = {"direct": 0, "direct_ir": 1, "minres": 2, "minres_ir": 3, "mgcg": 4}
 ST_CONVERGED, ST_PROMOTED, ST_NONFINITE, ST_IMAX = 1, 2, 4, 8
 
 EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",

@@ -173,11 +173,13 @@ hipError_t launch_fill_xi(uint64_t, int, int64_t, int64_t, int, double *, hipStr
 hipError_t launch_field(int, int, int, const double *, const double *, double *, hipStream_t st) { return op(st); }
 hipError_t launch_grad_gemm(int, int, int, const double *, const double *, const double *, double *, hipStream_t st) { return op(st); }
 hipError_t launch_coeffs(int, int, const double *, double *, double *, double *, int, hipStream_t st) { return op(st); }
-hipError_t launch_factor(int, int, int, const double *, double *, double *, const double *, void *, const int *, const int *, int64_t, uint32_t *, double, double *, double *, int, hipStream_t st) { return op(st); }
+hipError_t launch_factor(int, int, int, const double *, double *, double *, const double *, void *, const int *, const int *, int64_t, uint32_t *, double, double *, double *, int, int, hipStream_t st) { return op(st); }
 bool factor_fuses_forward(int dtype, int n) { return use_blk(dtype, n) && (dtype != 0 || n == 16); }
 hipError_t launch_ir(int, const ir_args &, hipStream_t st) { return op(st); }
 hipError_t launch_minres(int, int, double, const double *, const double *, const double *, const double *, double *, double *, void *, int, double, int, int, const int *, const int *, uint32_t *, double *, double *, int32_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_adjoint_gz(int, int, const double *, const double *, const double *, double *, int, hipStream_t st) { return op(st); }
+size_t mgcg_floats_per_sample(int n) { size_t t = 0; for (int l = 0; (n >> l) >= 2; ++l) { const size_t nl = n >> l, np = nl + 1; t += 2 * np * nl + 3 * np * np; } return (t + 63) & ~(size_t)63; }
+hipError_t launch_mgcg(int, int, double, const double *, double *, double *, float *, double, int, uint32_t *, double *, double *, int32_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_unpad(int, int, const double *, double *, hipStream_t st) { return op(st); }
 hipError_t launch_init_state(int, uint32_t *, double *, hipStream_t st) { return op(st); }
 hipError_t launch_reset_subset(int, const int *, const int *, uint32_t *, double *, hipStream_t st) { return op(st); }

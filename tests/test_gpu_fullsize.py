@@ -273,7 +273,7 @@ def test_precision_sweep_fullsize(dtype):
             assert row["promoted_frac"] <= ceil, row
 
 
-@pytest.mark.parametrize("solver", ["direct_ir", "minres", "minres_ir"])
+@pytest.mark.parametrize("solver", ["direct_ir", "minres", "minres_ir", "mgcg"])
 def test_all_levels_one_graph_fullsize(solver):
     """batched5_n16-256_K128: the five levels (40000 ... 200 samples) in one graph."""
     torch = _torch()

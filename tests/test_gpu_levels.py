@@ -110,3 +110,29 @@ def test_autotune_choices_and_parity():
     # a different kernel variant may change rounding, never the accuracy target
     assert np.all(np.abs(after - before) <= 1e-4 * qscale)
     ctx.close()
+
+
+def test_autotune_half_factor_products():
+    """FP16 factors: the autotuner may choose FP32 block products per grid;
+    either choice keeps the accuracy target (residual bound against the
+    oracle) and the choice persists for later calls."""
+    torch = _torch()
+    from paper_2503_05533_amd import MLMC, Config
+    K, s2, lam, seed = 64, 1.0, 0.3, 1001
+    ctx = MLMC(Config(n0=16, L_max=3, K=K, sigma2=s2, corr_len=lam, seed=seed), device="cuda:0")
+    eps = ctx.accuracy_targets(3)
+    for level, S in ((2, 40), (3, 12)):
+        xi = ctx.fill_xi(level, 0, S)
+        o = dict(dtype="f16", solver="direct_ir", eps_fine=eps[level], eps_coarse=eps[level - 1])
+        ch = ctx.autotune(level, xi, **o)
+        _say("f16 autotune level", level, ch)
+        assert all((c & 15) in (0, 1, 2) and (c >> 4) in (0, 1) for c in ch)
+        out = ctx.sample_level(level, xi, **o)
+        assert out["stats"]["n_noconv"] == 0
+        xr = si.splitmix64_normals(seed, level, 0, S, K)
+        nf = 16 << level
+        for nn, qg, e in ((nf, out["qf"], eps[level]), (nf // 2, out["qc"], eps[level - 1])):
+            q, u = oracle.solve_batch(nn, oracle.kl_basis(nn, K, s2, lam), xr, want_u=True)
+            c = np.linalg.norm(u, axis=1) * np.sqrt(u.shape[1]) / u.sum(axis=1)
+            assert np.all(np.abs(qg.cpu().numpy() - q) <= e * c * np.abs(q) * (1 + 1e-6)), (level, nn)
+    ctx.close()

@@ -208,3 +208,41 @@ def test_estimate_mixed_matches_fp64(case):
     assert mix["converged"] and sum(mix["n_noconv"]) == 0
     assert all(e > 0 for e in mix["eps"])
     ctx.close()
+
+
+# ----------------------------------------------------------------- multigrid-preconditioned CG
+
+@pytest.mark.parametrize("disc", [0, 1])
+def test_mgcg_reaches_eps_with_grid_independent_iterations(disc):
+    """CG with an FP32 multigrid V-cycle (gamma = 2 solver) on the precision
+    sweep's field (sigma^2 = 2, lambda = 0.1), 16..256 cells: every sample
+    reaches eps in the true FP64 residual with Q within the residual bound,
+    and the iteration count grows far slower than MINRES's (roughly constant
+    in n)."""
+    torch = _torch()
+    K, s2, lam, seed = 128, 2.0, 0.1, 51
+    ctx = _ctx(n0=16, L_max=4, K=K, sigma2=s2, corr_len=lam, seed=seed, minres_max_iter=500, disc=disc)
+    mean_it = []
+    for level, S in ((0, 24), (1, 16), (2, 8), (3, 4), (4, 2)):
+        n = 16 << level
+        xi = si.splitmix64_normals(seed, level, 0, S, K)
+        phi = oracle.kl_basis(n, K, s2, lam)
+        with oracle.disc_rule(disc):
+            qref, uref = oracle.solve_batch(n, phi, xi, want_u=True)
+        for eps in (1e-4, 1e-9):
+            out = ctx.solve(level, torch.from_numpy(xi), solver="mgcg", eps=eps, want_u=True)
+            st = out["status"].cpu().numpy()
+            it = out["iters"].cpu().numpy()
+            _say("mgcg disc=%d n=%d eps=%g: iterations %s" % (disc, n, eps, it.tolist()))
+            assert np.all(st & 1), st
+            with oracle.disc_rule(disc):
+                rr = oracle.relres_batch(n, phi, xi, out["u"].cpu().numpy())
+            assert np.all(rr < eps * (1 + 1e-6)), rr.max()
+            bound = np.linalg.norm(uref, axis=1) * (math.sqrt(uref.shape[1]) / n ** 2) / qref
+            dq = np.abs(out["q"].cpu().numpy() - qref) / qref
+            assert np.all(dq <= rr * bound * (1 + 1e-6) + 1e-14)
+            if eps == 1e-9:
+                mean_it.append(float(it.mean()))
+    # 16 -> 256 cells: MINRES needs ~25x the iterations; the V-cycle keeps CG within a small factor
+    assert mean_it[-1] <= 3.0 * mean_it[0] + 5, mean_it
+    ctx.close()
