@@ -31,7 +31,8 @@ Legs:
     discretisation and field (P1 elements, trigonometric field): the Table 1
     precisions and the quarter-precision example (FP8 factor on level 0),
     each at fixed N_l, MSE against FP64 over many runs with shared xi, and
-    the stored-bytes count;
+    the stored-bytes count; and its iterative-solver comparison (adaptive
+    MPML against standard MLMC at a fixed 1e-6, MINRES and multigrid CG);
   * CPU: the FP64 oracle on a bounded sample of the workload, host cores,
     one core, and LAPACK's banded Cholesky on the same systems.
 
@@ -124,7 +125,7 @@ def parse():
                    help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--ttr-runs", type=int, default=20, help="seeds of the time-to-RMSE leg")
-    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5",
+    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5,paper_iterative",
                    help="comma-separated other-workload legs to run (empty: none)")
     p.add_argument("--q43-runs", type=int, default=1000, help="runs of the quarter-precision leg")
     p.add_argument("--paper5-runs", type=int, default=300, help="runs of the Table 1 precision leg")
@@ -433,6 +434,51 @@ def leg_paper5(a):
                       lambda L: [4, 4] + [8] * (L - 1), 2e-6, 100, a.paper5_runs)
 
 
+def leg_paper_iterative(a):
+    """The paper's iterative-solver comparison (sec. 5.1): adaptive MPML
+    (Algorithm 4.1 with its accuracy targets delta_l) against standard MLMC
+    (every solve to a fixed relative residual 1e-6) with the same iterative
+    solver, on the paper's first example (P1 elements, trigonometric field
+    s = 4, q = 2, sigma = 2, h0 = 1/8, k_p = 0.05), at TOL^2 = 8e-6 and 2e-6,
+    10 seeds each (MPML and MLMC share each seed's xi): median host wall
+    time, mean device time, the cost ratio MLMC / MPML (the paper reports
+    ~1.5x in FLOPs with MINRES), and the RMSE of both against an FP64 direct
+    reference at TOL/10; for FP64 MINRES and for multigrid CG."""
+    import numpy as np
+    w, ctx = _ctx_for("paper5_n8-128_trig4", minres_max_iter=20000)
+    Lm = max(w["levels"])
+    out = dict(workload="paper5_n8-128_trig4", std_eps=1e-6, runs=10)
+    ctx.set_seed(w["seed"] + 99)
+    tol_min = (2e-6) ** 0.5
+    ref = ctx.estimate(tol_min / 10, n_init=100, dtypes=["f64"] * (Lm + 1), solver="direct", mixed=False)
+    out["reference"] = dict(estimate=ref["estimate"], tol=tol_min / 10)
+    for solver in ("minres", "mgcg"):
+        res_s = {}
+        for tol2 in (8e-6, 2e-6):
+            tol = tol2 ** 0.5
+            row = {}
+            for name, mixed in (("mpml", True), ("mlmc", False)):
+                ctx.set_seed(w["seed"])
+                ctx.estimate(tol, n_init=100, dtypes=["f64"] * (Lm + 1), solver=solver, mixed=mixed)
+                walls, gms, ests, Ls = [], [], [], []
+                for r in range(10):
+                    ctx.set_seed(w["seed"] + r)
+                    e = ctx.estimate(tol, n_init=100, dtypes=["f64"] * (Lm + 1), solver=solver, mixed=mixed)
+                    walls.append(e["wall_s"])
+                    gms.append(e["gpu_ms"])
+                    ests.append(e["estimate"])
+                    Ls.append(e["L"])
+                mse, ci = _ci95_mse(np.array(ests) - ref["estimate"])
+                row[name] = dict(median_wall_s=float(np.median(walls)), mean_gpu_ms=float(np.mean(gms)),
+                                 rmse=mse ** 0.5, L_counts={str(k): Ls.count(k) for k in sorted(set(Ls))})
+            row["wall_ratio_mlmc_over_mpml"] = row["mlmc"]["median_wall_s"] / row["mpml"]["median_wall_s"]
+            row["gpu_ratio_mlmc_over_mpml"] = row["mlmc"]["mean_gpu_ms"] / row["mpml"]["mean_gpu_ms"]
+            res_s["tol2_%g" % tol2] = row
+        out[solver] = res_s
+    ctx.close()
+    return out
+
+
 def cpu_single_and_lapack(oracle, si, w, ctx, levels, Ns, phis, budget):
     """One-core oracle time and LAPACK's banded Cholesky (dpbtrf/dpbtrs via
     SciPy, on the band matrices the oracle assembles; the assembly is not
@@ -693,7 +739,8 @@ def main():
     sel = [x for x in a.legs.split(",") if x]
     ctx_main = ctx
     for name in sel:
-        fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43, "paper5": leg_paper5}[name]
+        fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43, "paper5": leg_paper5,
+              "paper_iterative": leg_paper_iterative}[name]
         t0 = time.perf_counter()
         legs[name] = fn(a)
         legs[name]["leg_wall_s"] = time.perf_counter() - t0

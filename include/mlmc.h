@@ -130,6 +130,9 @@ typedef struct {
                               *    (2a(x,y) + 2a(x+h,y) + a(x+h,y+h) + a(x,y-h)) / 6 and edge
                               *    (x,y)-(x,y+h) gets (2a(x,y) + 2a(x,y+h) + a(x+h,y+h) + a(x-h,y)) / 6;
                               *    b = h^2 f and Q = h^2 sum u are the same for both. */
+    double std_eps;          /* standard MLMC (mlmc_estimate with mixed = 0) with an
+                              * iterative solver solves every system to this relative
+                              * residual (0: 1e-6, the paper's MINRES setting, Sec. 5.1) */
 } mlmc_config;
 
 typedef struct {
@@ -299,9 +302,11 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * and the deterministic cost C_l = (n_l-1)^gamma + (n_{l-1}-1)^gamma, adds a level
  * while |Y-hat_L| > (m^alpha - 1)/sqrt(2) TOL, and stops when that test and
  * sum_l s_l^2/N_l <= TOL^2/2 hold and no level needs more samples.
- * dtype_per_level[0..L_max] selects u_f per level (ignored for
- * MLMC_DIRECT/MLMC_MINRES).  mixed = 0 runs standard MLMC: every solve
- * uses eps = 0 targets replaced by the FP64 direct solve.  Each level
+ * dtype_per_level[0..L_max] selects u_f per level (ignored by the
+ * solvers without a factor).  mixed = 0 runs standard MLMC (Algorithm 4.1
+ * without its precision step): with MLMC_DIRECT or MLMC_DIRECT_IR every
+ * solve is the FP64 direct solve; with an iterative solver every solve runs
+ * that solver to the fixed tolerance cfg.std_eps.  Each level
  * streams its chunks on one of the context's queue streams; one
  * synchronisation per round, and within a round the host waits for the
  * finest level alone: when its samples make the level test add a level, that

@@ -1092,6 +1092,8 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
     const mlmc_config &c = ctx->cfg;
+    // tolerance of every solve of standard MLMC with an iterative solver
+    const double std_eps = (!mixed && is_iterative(solver)) ? (c.std_eps > 0.0 ? c.std_eps : 1e-6) : 0.0;
     const int Lmax = c.L_max;
     // Per-level chunk: as many samples as fit a per-level workspace budget, so
     // that the fine levels fill the GPU.  Each level has its own workspace and
@@ -1116,7 +1118,9 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     for (int l = 0; l <= Lmax; ++l) {
         mlmc_level_opts o{};
         o.factor_dtype = dtype_per_level ? dtype_per_level[l] : MLMC_F64;
-        o.solver = mixed ? solver : MLMC_DIRECT;
+        // standard MLMC: FP64 direct solves, or the iterative solver at the
+        // fixed tolerance std_eps (the paper's standard MLMC with MINRES)
+        o.solver = mixed ? solver : (is_iterative(solver) ? solver : MLMC_DIRECT);
         o.promote = 1;
         if (int rc_o = check_opts(ctx, &o, l, true)) return rc_o;
         int64_t ch = chunk_max;
@@ -1177,14 +1181,15 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         double eps_next[16] = {};
         if (L < Lmax) mlmc_accuracy_targets(ctx, L + 1, eps_next);
         struct job { int l; int64_t from, to; double ef, ec; };
-        const job next_job{L + 1, 0, n_init, mixed ? eps_next[L + 1] : 0.0, mixed ? eps_next[L] : 0.0};
+        const job next_job{L + 1, 0, n_init, mixed ? eps_next[L + 1] : std_eps, mixed ? eps_next[L] : std_eps};
         const bool early = N[L] <= done[L] && next_level_due(s1[L], done[L]);
         std::vector<job> jobs;
         // finest first: issuing level 0's many chunks takes the host milliseconds
         if (early) jobs.push_back(next_job);
         for (int l = L; l >= 0; --l)
             if (N[l] > done[l])
-                jobs.push_back({l, done[l], N[l], mixed ? eps[l] : 0.0, mixed && l > 0 ? eps[l - 1] : 0.0});
+                jobs.push_back({l, done[l], N[l], mixed ? eps[l] : std_eps,
+                                mixed ? (l > 0 ? eps[l - 1] : 0.0) : (l > 0 ? std_eps : 0.0)});
         auto job_chunks = [&](const job &jb) { return (int)((jb.to - jb.from + chunk[jb.l] - 1) / chunk[jb.l]); };
         // top every level up to N_l
         auto round_enqueue = [&](std::vector<std::pair<int, int64_t>> &recs) -> int {
@@ -1347,7 +1352,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         out->Yhat[l] = yhat[l];
         out->s2[l] = var[l];
         out->C[l] = cost(l);
-        out->eps[l] = mixed ? eps[l] : 0.0;
+        out->eps[l] = mixed ? eps[l] : std_eps;
     }
     for (int l = 0; l <= Lmax; ++l) {
         out->n_promoted[l] = n_prom[l];

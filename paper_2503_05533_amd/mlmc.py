@@ -40,7 +40,7 @@ class _Config(ctypes.Structure):
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("ir_max_iter", ctypes.c_int32), ("minres_max_iter", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("field", ctypes.c_int32), ("field_q", ctypes.c_double),
-                ("disc", ctypes.c_int32)]
+                ("disc", ctypes.c_int32), ("std_eps", ctypes.c_double)]
 
 
 class _LevelOpts(ctypes.Structure):
@@ -136,6 +136,7 @@ class Config:
     field: int = 0        # 0: exponential-covariance KL; 1: trigonometric field of sec. 5.1
     field_q: float = 2.0  # decay exponent q of the trigonometric field
     disc: int = 0         # 0: finite volumes (harmonic faces); 1: P1 elements on right triangles
+    std_eps: float = 0.0  # standard MLMC with an iterative solver: fixed tolerance (0: 1e-6)
 
 
 def _ptr(t):

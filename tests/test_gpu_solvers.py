@@ -246,3 +246,23 @@ def test_mgcg_reaches_eps_with_grid_independent_iterations(disc):
     # 16 -> 256 cells: MINRES needs ~25x the iterations; the V-cycle keeps CG within a small factor
     assert mean_it[-1] <= 3.0 * mean_it[0] + 5, mean_it
     ctx.close()
+
+
+@pytest.mark.parametrize("solver", ["mgcg", "minres"])
+def test_estimate_iterative_mpml_vs_standard(solver):
+    """Algorithm 4.1 with an iterative solver: adaptive MPML (targets
+    delta_l) and standard MLMC (every solve to std_eps = 1e-10) take the same
+    decisions and their estimates agree to solver error."""
+    torch = _torch()
+    n0, L_max, K, s2, lam, seed, tol, n_init = 4, 3, 16, 1.0, 0.3, 81, 4e-4, 200
+    ctx = _ctx(n0=n0, L_max=L_max, K=K, sigma2=s2, corr_len=lam, seed=seed, std_eps=1e-10, minres_max_iter=5000)
+    mp = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * (L_max + 1), solver=solver, mixed=True)
+    st = ctx.estimate(tol, n_init=n_init, dtypes=["f64"] * (L_max + 1), solver=solver, mixed=False)
+    _say(solver, "mpml", mp["L"], mp["N"], mp["estimate"], "mlmc", st["L"], st["N"], st["estimate"], st["eps"])
+    assert mp["converged"] and st["converged"]
+    assert mp["L"] == st["L"]
+    assert all(e == 1e-10 for e in st["eps"])
+    for x, y in zip(mp["N"], st["N"]):
+        assert abs(x - y) <= max(2, 1e-3 * y)
+    assert abs(mp["estimate"] - st["estimate"]) < 0.1 * tol
+    ctx.close()
