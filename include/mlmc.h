@@ -337,6 +337,58 @@ int mlmc_grad(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
               const double *grad_q_dev, const mlmc_level_opts *opts, double eps_adjoint,
               void *ws_dev, size_t ws_bytes, double *grad_xi_dev, void *stream);
 
+/* Multilevel Markov chain Monte Carlo with the same per-level solves (the
+ * extension of the concluding remark of Sec. 4: the accuracy rule is a
+ * statement about the quantity of interest, not about the sampler).
+ * Bayesian set-up: prior xi ~ N(0, I_K) (the field of the context), data
+ * d_j = u(x_j) + N(0, noise_sd^2) at n_obs observation nodes, log-likelihood
+ * of level l  -sum_j (d_j - u_l(x_j))^2 / (2 noise_sd^2).  E_{pi_L}[Q] is
+ * estimated by the telescoping sum E_{pi_0}[Q_0] + sum_l E[Y_l]:
+ *   level 0: `chains` independent preconditioned Crank-Nicolson chains
+ *   (xi' = sqrt(1 - b^2) xi + b w), Y_0 = Q_0 of the state;
+ *   level l >= 1: `chains` chains on the level-l posterior whose proposal is
+ *   the current state of a pCN chain on the level-(l-1) posterior, advanced
+ *   `subsample` steps per fine step, accepted with
+ *   min(1, L_l(xi') L_{l-1}(xi) / (L_l(xi) L_{l-1}(xi'))), and
+ *   Y_l = Q_l(fine state) - Q_{l-1}(coarse state) (Dodwell et al.'s
+ *   multilevel MCMC with an independence proposal from the coarse chain).
+ * All chains of a level step together: every step is one batched solve of
+ * `chains` samples with opts[l] (eps_fine on grid l, eps_coarse on grid
+ * l-1).  Chains start at xi = 0; the first burn_in steps are not recorded.
+ * Random numbers: the context's counter-based generator (mlmc_fill_xi) on
+ * reserved level indices 4096 + 8 l + k (k = 0 fine proposals, 1 coarse
+ * proposals, 2 fine acceptance, 3 coarse acceptance) at sample index
+ * step * chains + chain (coarse: (step * subsample + s) * chains + chain);
+ * a step's acceptance uniform is Phi(z) of the first normal.  Observation
+ * nodes must be interior nodes of the level-0 grid.  Allocates its device
+ * buffers for the call; synchronises the stream. */
+typedef struct {
+    int32_t L;                 /* finest level, 0..L_max */
+    int32_t chains;            /* chains per level (1..65536), the batch of every solve */
+    int32_t steps[16];         /* recorded steps per chain on level l */
+    int32_t burn_in;           /* steps per chain discarded at the start of every level */
+    int32_t subsample;         /* coarse pCN steps per fine step (levels >= 1) */
+    double pcn_beta;           /* pCN step size b, 0 < b <= 1 */
+    double noise_sd;           /* observation noise standard deviation */
+    int32_t n_obs;             /* observation nodes, 1..64 */
+    double obs_x[64], obs_y[64];  /* node coordinates (multiples of 1/n0, inside (0,1)) */
+    double obs_value[64];      /* observed values d_j */
+    mlmc_level_opts opts[16];  /* solver of level l's fine and coarse grids */
+    uint64_t seed;             /* generator seed of the chains' random numbers */
+} mlmc_mcmc_config;
+
+typedef struct {
+    double estimate;           /* sum_l Yhat[l] */
+    double Yhat[16];           /* mean of Y_l over chains and recorded steps */
+    double var_mean[16];       /* variance of Yhat[l] from the spread of the chain means */
+    double accept[16];         /* acceptance rate of level l's chains */
+    double accept_coarse[16];  /* of its coarse pCN chains (levels >= 1) */
+    int64_t solves;            /* batched solves issued */
+    double wall_s;
+} mlmc_mcmc_result;
+
+int mlmc_mcmc(mlmc_ctx *ctx, const mlmc_mcmc_config *cfg, mlmc_mcmc_result *out, void *stream);
+
 /* Kernel timing for measurement.  While enabled, the library brackets each
  * launch of the field, assembly, factor, solve and residual kernels with HIP
  * events on the caller's stream and records (kernel kind, grid n, samples).

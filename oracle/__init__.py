@@ -23,6 +23,10 @@ Functions and the passage each follows:
   level_estimates          -- Y-hat_l and s_l^2 of sec. 4.1
   adaptive_mpml            -- Algorithm 4.1 (sec. 4.3)
   cost_ratio_bound         -- bound of the cost-savings corollary, sec. 4.4
+  mlmcmc                   -- multilevel MCMC (the extension named in the
+                              remark on other sampling methods, sec. 4):
+                              pCN chains on level 0, two-level chains with
+                              an independence proposal from a coarse chain
 """
 import ctypes
 import math
@@ -357,3 +361,95 @@ def adaptive_mpml(sample_fn, n0, tol, L_max, n_init=1000, m=2, alpha=2.0, k_p=0.
                         bias_ok=abs(yhat[L]) <= bias_c, var_ok=var_ok, rounds=rounds,
                         history=history)
     raise RuntimeError("adaptive MPML did not terminate")
+
+
+# ---------------------------------------------------------------- multilevel MCMC
+
+def pde_forward(n, Phi, obs, noise_sd, disc=0):
+    """forward(xi[C, K]) -> (Q, log-likelihood) of the discrete PDE on grid n:
+    log L = -sum_j (d_j - u(x_j))^2 / (2 noise_sd^2) at the observation nodes
+    obs = [(x, y, d)] (nodes of the grid)."""
+    m = n - 1
+
+    def f(xi):
+        with disc_rule(disc):
+            q, u = solve_batch(n, Phi, xi, want_u=True)
+        ll = np.zeros(xi.shape[0])
+        for x, y, d in obs:
+            ix, iy = int(round(x * n)), int(round(y * n))
+            ll -= (d - u[:, (iy - 1) * m + (ix - 1)]) ** 2 / (2.0 * noise_sd ** 2)
+        return q, ll
+    return f
+
+
+def mlmcmc(forward, L, chains, K, steps, burn_in, subsample, beta, normals):
+    """Multilevel MCMC for E_{pi_L}[Q] = E_{pi_0}[Q_0] + sum_l E[Q_l - Q_{l-1}],
+    written from Dodwell, Ketelsen, Scheichl and Teckentrup's method (the
+    sampler the remark on other sampling methods names), every chain started
+    at xi = 0, the first burn_in steps not recorded:
+      level 0: preconditioned Crank-Nicolson, xi' = sqrt(1 - beta^2) xi + beta w,
+        accepted when Phi(z) < L_0(xi') / L_0(xi) (a prior-reversible proposal);
+      level l >= 1: a pCN chain on pi_{l-1} advanced `subsample` steps, whose
+        state is proposed to a chain on pi_l and accepted when
+        Phi(z) < L_l(xi') L_{l-1}(xi) / (L_l(xi) L_{l-1}(xi')) (an independence
+        proposal drawn from pi_{l-1}); Y_l = Q_l(fine state) - Q_{l-1}(coarse state).
+    forward(l, xi) -> (Q, log L) on level l; normals(stream, first, count, k)
+    -> [count, k] standard normals of the counter-based generator, streams
+    4096 + 8 l + {0 fine proposals, 1 coarse proposals, 2 fine, 3 coarse
+    acceptance}, index step * chains + chain (coarse: (step * subsample + s)
+    * chains + chain).  Returns per-level means, chain-mean variances of the
+    means, acceptance rates and the estimate."""
+    C = chains
+    c1 = math.sqrt(1.0 - beta * beta)
+
+    def accept(log_a, z, ll_new):
+        u = 0.5 * np.array([math.erfc(-v / math.sqrt(2.0)) for v in z])
+        with np.errstate(over="ignore"):
+            return np.isfinite(ll_new) & ((log_a >= 0.0) | (u < np.exp(np.minimum(log_a, 0.0))))
+
+    out = dict(Yhat=[], var_mean=[], accept=[], accept_coarse=[])
+    for l in range(L + 1):
+        base = 4096 + 8 * l
+        T = burn_in + steps[l]
+        th = np.zeros((C, K))
+        qf, llf = forward(l, th)
+        if l > 0:
+            tc = np.zeros((C, K))
+            qc, llc = forward(l - 1, tc)
+            llcf = llc.copy()
+        sums = np.zeros(C)
+        acc = np.zeros(C)
+        acc_c = np.zeros(C)
+        for k in range(T):
+            rec = k >= burn_in
+            if l == 0:
+                prop = c1 * th + beta * normals(base + 0, k * C, C, K)
+                qp, llp = forward(0, prop)
+                a = accept(llp - llf, normals(base + 2, k * C, C, 1)[:, 0], llp)
+                th[a], llf[a], qf[a] = prop[a], llp[a], qp[a]
+                if rec:
+                    acc += a
+                    sums += qf
+                continue
+            for sub in range(subsample):
+                idx = (k * subsample + sub) * C
+                prop = c1 * tc + beta * normals(base + 1, idx, C, K)
+                qp, llp = forward(l - 1, prop)
+                a = accept(llp - llc, normals(base + 3, idx, C, 1)[:, 0], llp)
+                tc[a], llc[a], qc[a] = prop[a], llp[a], qp[a]
+                if rec:
+                    acc_c += a
+            prop = tc.copy()
+            qp, llp = forward(l, prop)
+            a = accept((llp - llf) - (llc - llcf), normals(base + 2, k * C, C, 1)[:, 0], llp)
+            th[a], llf[a], qf[a], llcf[a] = prop[a], llp[a], qp[a], llc[a]
+            if rec:
+                acc += a
+                sums += qf - qc
+        means = sums / steps[l]
+        out["Yhat"].append(float(means.mean()))
+        out["var_mean"].append(float(means.var(ddof=1) / C) if C > 1 else 0.0)
+        out["accept"].append(float(acc.sum() / (C * steps[l])))
+        out["accept_coarse"].append(float(acc_c.sum() / (C * steps[l] * subsample)) if l else 0.0)
+    out["estimate"] = float(sum(out["Yhat"]))
+    return out

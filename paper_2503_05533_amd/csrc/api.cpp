@@ -1370,6 +1370,170 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     return MLMC_OK;
 }
 
+int mlmc_mcmc(mlmc_ctx *ctx, const mlmc_mcmc_config *mc, mlmc_mcmc_result *out, void *stream)
+{
+    if (!ctx) return MLMC_EINVAL;
+    if (!mc || !out) return fail(ctx, MLMC_EINVAL, "mcmc: null argument");
+    const mlmc_config &c = ctx->cfg;
+    if (mc->L < 0 || mc->L > c.L_max || mc->chains < 1 || mc->chains > 65536 || mc->burn_in < 0 ||
+        mc->subsample < 1 || !(mc->pcn_beta > 0.0 && mc->pcn_beta <= 1.0) || !(mc->noise_sd > 0.0) ||
+        mc->n_obs < 1 || mc->n_obs > 64)
+        return fail(ctx, MLMC_EINVAL, "mcmc: bad configuration");
+    int64_t total_steps = 0;
+    for (int l = 0; l <= mc->L; ++l) {
+        if (mc->steps[l] < 1) return fail(ctx, MLMC_EINVAL, "mcmc: steps[%d] < 1", l);
+        const int64_t st_l = (int64_t)(mc->burn_in + mc->steps[l]) * (l > 0 ? mc->subsample : 1);
+        if (st_l * mc->chains >= ((int64_t)1 << 32)) return fail(ctx, MLMC_EINVAL, "mcmc: too many draws");
+        total_steps += mc->burn_in + mc->steps[l];
+        if (int rc = check_opts(ctx, &mc->opts[l], l, true)) return rc;
+    }
+    // observation nodes: interior nodes of the level-0 grid
+    int obs_node[64];
+    for (int j = 0; j < mc->n_obs; ++j) {
+        const double fx = mc->obs_x[j] * 1024.0, fy = mc->obs_y[j] * 1024.0;
+        const double gx = mc->obs_x[j] * c.n0, gy = mc->obs_y[j] * c.n0;
+        if (!(gx > 0.5 && gx < c.n0 - 0.5 && gy > 0.5 && gy < c.n0 - 0.5) || std::fabs(gx - std::round(gx)) > 1e-9 ||
+            std::fabs(gy - std::round(gy)) > 1e-9 || !std::isfinite(mc->obs_value[j]))
+            return fail(ctx, MLMC_EINVAL, "mcmc: observation %d is not an interior node of the coarsest grid", j);
+        obs_node[j] = (int)std::lround(fx) + 1024 * (int)std::lround(fy);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    const int C = mc->chains, K = c.K;
+    // device buffers: states and proposals (C x K), per-chain scalars, the
+    // solve workspaces of the finest level's two grids
+    size_t need = 0;
+    auto take = [&](size_t b) { size_t o = need; need += align256(b); return o; };
+    const size_t o_obs = take(64 * 4), o_obsv = take(64 * 8);
+    const size_t o_tf = take((size_t)C * K * 8), o_tc = take((size_t)C * K * 8), o_pr = take((size_t)C * K * 8),
+                 o_w = take((size_t)C * K * 8), o_z = take((size_t)C * 8);
+    const size_t o_llf = take(C * 8), o_llcf = take(C * 8), o_qf = take(C * 8), o_llc = take(C * 8),
+                 o_qc = take(C * 8), o_qpf = take(C * 8), o_qpc = take(C * 8), o_dummy = take(C * 8);
+    const size_t o_accf = take(C * 8), o_accc = take(C * 8), o_sums = take(2 * (size_t)C * 8);
+    size_t wsf = 0, wsc = 0;
+    for (int l = 0; l <= mc->L; ++l) {
+        wsf = std::max(wsf, make_layout(c.n0 << l, C, mc->opts[l]).bytes);
+        if (l > 0) wsc = std::max(wsc, make_layout(c.n0 << (l - 1), C, mc->opts[l]).bytes);
+    }
+    const size_t o_wsf = take(wsf), o_wsc = take(wsc);
+    void *buf = nullptr;
+    HIPCHK(hipMalloc(&buf, need));
+    auto D = [&](size_t o) { return at<double>(buf, o); };
+    int rc = MLMC_OK;
+    std::vector<double> h_sums(2 * (size_t)C);
+    std::vector<int64_t> h_acc(C);
+    memset(out, 0, sizeof *out);
+    int64_t solves = 0;
+    double obs_v[64];
+    for (int j = 0; j < mc->n_obs; ++j) obs_v[j] = mc->obs_value[j];
+    const int *d_obs = at<int>(buf, o_obs);
+    const double *d_obsv = D(o_obsv);
+    auto run = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(at<int>(buf, o_obs), obs_node, mc->n_obs * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(D(o_obsv), obs_v, mc->n_obs * 8, hipMemcpyHostToDevice, st));
+        for (int l = 0; l <= mc->L; ++l) {
+            const mlmc_level_opts &o = mc->opts[l];
+            const int nf = c.n0 << l, nc = nf / 2;
+            const grid_layout Lf = make_layout(nf, C, o);
+            const grid_layout Lc = l > 0 ? make_layout(nc, C, o) : grid_layout{};
+            void *wf = at<void>(buf, o_wsf), *wc = at<void>(buf, o_wsc);
+            const uint32_t base = 4096 + 8 * (uint32_t)l;
+            auto solve = [&](bool fine, const double *xi, double *q) -> int {
+                ++solves;
+                return fine ? solve_grid(ctx, Lf, l, xi, o, o.eps_fine, wf, q, at<int32_t>(wf, Lf.off_iters), st)
+                            : solve_grid(ctx, Lc, l - 1, xi, o, o.eps_coarse, wc, q, at<int32_t>(wc, Lc.off_iters),
+                                         st);
+            };
+            // start at xi = 0
+            HIPCHK(hipMemsetAsync(D(o_tf), 0, (size_t)C * K * 8, st));
+            HIPCHK(hipMemsetAsync(D(o_tc), 0, (size_t)C * K * 8, st));
+            HIPCHK(hipMemsetAsync(D(o_accf), 0, (size_t)C * 8, st));
+            HIPCHK(hipMemsetAsync(D(o_accc), 0, (size_t)C * 8, st));
+            HIPCHK(hipMemsetAsync(D(o_sums), 0, 2 * (size_t)C * 8, st));
+            if (int e = solve(true, D(o_tf), D(o_qf))) return e;
+            HIPCHK(launch_mcmc_loglik(C, nf, mc->n_obs, d_obs, d_obsv, mc->noise_sd, at<double>(wf, Lf.off_x),
+                                      D(o_llf), st));
+            if (l > 0) {
+                if (int e = solve(false, D(o_tc), D(o_qc))) return e;
+                HIPCHK(launch_mcmc_loglik(C, nc, mc->n_obs, d_obs, d_obsv, mc->noise_sd, at<double>(wc, Lc.off_x),
+                                          D(o_llc), st));
+                HIPCHK(hipMemcpyAsync(D(o_llcf), D(o_llc), (size_t)C * 8, hipMemcpyDeviceToDevice, st));
+            }
+            const int nsteps = mc->burn_in + mc->steps[l];
+            for (int k = 0; k < nsteps; ++k) {
+                const int rec = k >= mc->burn_in;
+                if (l == 0) {
+                    HIPCHK(launch_fill_xi(mc->seed, base + 0, (int64_t)k * C, C, K, D(o_w), st));
+                    HIPCHK(launch_pcn_propose(C, K, mc->pcn_beta, D(o_tf), D(o_w), D(o_pr), st));
+                    if (int e = solve(true, D(o_pr), D(o_qpf))) return e;
+                    HIPCHK(launch_fill_xi(mc->seed, base + 2, (int64_t)k * C, C, 1, D(o_z), st));
+                    HIPCHK(launch_mcmc_accept(C, K, nf, 0, mc->n_obs, d_obs, d_obsv, mc->noise_sd,
+                                              at<double>(wf, Lf.off_x), D(o_qpf), D(o_pr), D(o_dummy), D(o_z),
+                                              D(o_tf), D(o_llf), D(o_dummy), D(o_qf), at<int64_t>(buf, o_accf), rec,
+                                              st));
+                    if (rec) HIPCHK(launch_mcmc_record(C, D(o_qf), nullptr, D(o_sums), st));
+                    continue;
+                }
+                for (int sub = 0; sub < mc->subsample; ++sub) {
+                    const int64_t idx = ((int64_t)k * mc->subsample + sub) * C;
+                    HIPCHK(launch_fill_xi(mc->seed, base + 1, idx, C, K, D(o_w), st));
+                    HIPCHK(launch_pcn_propose(C, K, mc->pcn_beta, D(o_tc), D(o_w), D(o_pr), st));
+                    if (int e = solve(false, D(o_pr), D(o_qpc))) return e;
+                    HIPCHK(launch_fill_xi(mc->seed, base + 3, idx, C, 1, D(o_z), st));
+                    HIPCHK(launch_mcmc_accept(C, K, nc, 0, mc->n_obs, d_obs, d_obsv, mc->noise_sd,
+                                              at<double>(wc, Lc.off_x), D(o_qpc), D(o_pr), D(o_dummy), D(o_z),
+                                              D(o_tc), D(o_llc), D(o_dummy), D(o_qc), at<int64_t>(buf, o_accc), rec,
+                                              st));
+                }
+                // the fine chain proposes the coarse chain's state
+                HIPCHK(hipMemcpyAsync(D(o_pr), D(o_tc), (size_t)C * K * 8, hipMemcpyDeviceToDevice, st));
+                if (int e = solve(true, D(o_pr), D(o_qpf))) return e;
+                HIPCHK(launch_fill_xi(mc->seed, base + 2, (int64_t)k * C, C, 1, D(o_z), st));
+                HIPCHK(launch_mcmc_accept(C, K, nf, 1, mc->n_obs, d_obs, d_obsv, mc->noise_sd,
+                                          at<double>(wf, Lf.off_x), D(o_qpf), D(o_pr), D(o_llc), D(o_z), D(o_tf),
+                                          D(o_llf), D(o_llcf), D(o_qf), at<int64_t>(buf, o_accf), rec, st));
+                if (rec) HIPCHK(launch_mcmc_record(C, D(o_qf), D(o_qc), D(o_sums), st));
+            }
+            // level statistics: mean over chains and steps, variance of the mean
+            // from the chain means (independent chains)
+            HIPCHK(hipMemcpyAsync(h_sums.data(), D(o_sums), 2 * (size_t)C * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h_acc.data(), D(o_accf), (size_t)C * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double T = (double)mc->steps[l];
+            double mean = 0.0, acc = 0.0;
+            for (int ch = 0; ch < C; ++ch) {
+                mean += h_sums[2 * ch] / T;
+                acc += (double)h_acc[ch];
+            }
+            mean /= C;
+            double v = 0.0;
+            for (int ch = 0; ch < C; ++ch) {
+                const double d = h_sums[2 * ch] / T - mean;
+                v += d * d;
+            }
+            out->Yhat[l] = mean;
+            out->var_mean[l] = C > 1 ? v / ((double)C * (C - 1)) : 0.0;
+            out->accept[l] = acc / ((double)C * T);
+            if (l > 0) {
+                HIPCHK(hipMemcpyAsync(h_acc.data(), D(o_accc), (size_t)C * 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                double ac = 0.0;
+                for (int ch = 0; ch < C; ++ch) ac += (double)h_acc[ch];
+                out->accept_coarse[l] = ac / ((double)C * T * mc->subsample);
+            }
+            out->estimate += mean;
+        }
+        return MLMC_OK;
+    };
+    rc = run();
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    out->solves = solves;
+    out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    (void)total_steps;
+    return rc;
+}
+
 int mlmc_profile(mlmc_ctx *ctx, int32_t enable)
 {
     if (!ctx) return MLMC_EINVAL;

@@ -111,6 +111,17 @@ size_t mgcg_floats_per_sample(int n);
 hipError_t launch_mgcg(int n, int S, double fconst, const double *a, double *x, double *vecs, float *mg,
                        double eps, int maxit, uint32_t *state, double *relres, double *q, int32_t *iters, int disc,
                        hipStream_t st);
+// Multilevel MCMC steps (mcmc.hip); obs_node[j] = fx + 1024 fy with the
+// node at (fx / 1024, fy / 1024).
+hipError_t launch_pcn_propose(int C, int K, double b, const double *theta, const double *w, double *out,
+                              hipStream_t st);
+hipError_t launch_mcmc_accept(int C, int K, int n, int mode, int n_obs, const int *obs_node, const double *obs_val,
+                              double noise_sd, const double *x, const double *qp, const double *prop,
+                              const double *llcp, const double *z, double *theta, double *ll, double *llc,
+                              double *q, int64_t *accepted, int count, hipStream_t st);
+hipError_t launch_mcmc_loglik(int C, int n, int n_obs, const int *obs_node, const double *obs_val, double noise_sd,
+                              const double *x, double *ll, hipStream_t st);
+hipError_t launch_mcmc_record(int C, const double *qf, const double *qc, double *sums, hipStream_t st);
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
                              double *gz, int disc, hipStream_t st);
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);

@@ -25,7 +25,7 @@ EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
            "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
            "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
            "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune",
-           "mlmc_sample_level_noalloc", "mlmc_set_seed"]
+           "mlmc_sample_level_noalloc", "mlmc_set_seed", "mlmc_mcmc"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -65,6 +65,21 @@ class _Result(ctypes.Structure):
                 ("eps", ctypes.c_double * 16), ("wall_s", ctypes.c_double),
                 ("gpu_ms", ctypes.c_double), ("n_promoted", ctypes.c_int64 * 16),
                 ("n_noconv", ctypes.c_int64 * 16)]
+
+
+class _MCMCConfig(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("chains", ctypes.c_int32), ("steps", ctypes.c_int32 * 16),
+                ("burn_in", ctypes.c_int32), ("subsample", ctypes.c_int32), ("pcn_beta", ctypes.c_double),
+                ("noise_sd", ctypes.c_double), ("n_obs", ctypes.c_int32),
+                ("obs_x", ctypes.c_double * 64), ("obs_y", ctypes.c_double * 64),
+                ("obs_value", ctypes.c_double * 64), ("opts", _LevelOpts * 16), ("seed", ctypes.c_uint64)]
+
+
+class _MCMCResult(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("Yhat", ctypes.c_double * 16),
+                ("var_mean", ctypes.c_double * 16), ("accept", ctypes.c_double * 16),
+                ("accept_coarse", ctypes.c_double * 16), ("solves", ctypes.c_int64),
+                ("wall_s", ctypes.c_double)]
 
 
 _lib = None
@@ -110,6 +125,7 @@ def load_library():
                                        i32, vp]
     lib.mlmc_autotune.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp, ctypes.c_size_t,
                                   ctypes.POINTER(i32), vp]
+    lib.mlmc_mcmc.argtypes = [vp, ctypes.POINTER(_MCMCConfig), ctypes.POINTER(_MCMCResult), vp]
     lib.mlmc_profile.argtypes = [vp, i32]
     lib.mlmc_profile_read.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
@@ -336,6 +352,28 @@ class MLMC:
                     C=list(r.C[:L + 1]), eps=list(r.eps[:L + 1]), wall_s=r.wall_s,
                     gpu_ms=r.gpu_ms, n_promoted=list(r.n_promoted[:L1]),
                     n_noconv=list(r.n_noconv[:L1]), rc=rc)
+
+    def mcmc(self, L, chains, steps, obs, noise_sd, burn_in=10, subsample=2, pcn_beta=0.5, opts=None,
+             seed=None):
+        """Multilevel MCMC (mlmc_mcmc): obs is a list of (x, y, value) at interior
+        nodes of the coarsest grid, steps a list of recorded steps per level,
+        opts a list of per-level option dicts (dtype, solver, eps_fine, eps_coarse)."""
+        c = _MCMCConfig()
+        c.L, c.chains, c.burn_in, c.subsample = int(L), int(chains), int(burn_in), int(subsample)
+        for l, k in enumerate(steps):
+            c.steps[l] = int(k)
+        c.pcn_beta, c.noise_sd, c.n_obs = float(pcn_beta), float(noise_sd), len(obs)
+        for j, (x, y, v) in enumerate(obs):
+            c.obs_x[j], c.obs_y[j], c.obs_value[j] = x, y, v
+        for l in range(L + 1):
+            o = (opts or [{}] * (L + 1))[l]
+            c.opts[l] = self._opts(**o)
+        c.seed = int(self.cfg.seed if seed is None else seed) & 0xFFFFFFFFFFFFFFFF
+        r = _MCMCResult()
+        rc = self._check(self.lib.mlmc_mcmc(self.h, ctypes.byref(c), ctypes.byref(r), _stream()), "mcmc")
+        return dict(estimate=r.estimate, Yhat=list(r.Yhat[:L + 1]), var_mean=list(r.var_mean[:L + 1]),
+                    accept=list(r.accept[:L + 1]), accept_coarse=list(r.accept_coarse[:L + 1]),
+                    solves=r.solves, wall_s=r.wall_s, rc=rc)
 
     def grad_from(self, level, xi, ws, grad_q=None, eps_adjoint=1e-10, dtype="f32",
                   solver="direct_ir", eps=1e-10):

@@ -74,6 +74,7 @@ int g_q = 0;
 extern "C" {
 hipError_t hipMalloc(void **p, size_t n) { *p = aligned_alloc(256, (n + 255) & ~(size_t)255); return *p ? hipSuccess : hipErrorOutOfMemory; }
 hipError_t hipFree(void *p) { free(p); return hipSuccess; }
+hipError_t hipMemsetAsync(void *, int, size_t, hipStream_t st) { return op(st); }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned int) { *p = malloc(n); return hipSuccess; }
 hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
 hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind)
@@ -178,6 +179,10 @@ bool factor_fuses_forward(int dtype, int n) { return use_blk(dtype, n) && (dtype
 hipError_t launch_ir(int, const ir_args &, hipStream_t st) { return op(st); }
 hipError_t launch_minres(int, int, double, const double *, const double *, const double *, const double *, double *, double *, void *, int, double, int, int, const int *, const int *, uint32_t *, double *, double *, int32_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_adjoint_gz(int, int, const double *, const double *, const double *, double *, int, hipStream_t st) { return op(st); }
+hipError_t launch_pcn_propose(int, int, double, const double *, const double *, double *, hipStream_t st) { return op(st); }
+hipError_t launch_mcmc_accept(int, int, int, int, int, const int *, const double *, double, const double *, const double *, const double *, const double *, const double *, double *, double *, double *, double *, int64_t *, int, hipStream_t st) { return op(st); }
+hipError_t launch_mcmc_loglik(int, int, int, const int *, const double *, double, const double *, double *, hipStream_t st) { return op(st); }
+hipError_t launch_mcmc_record(int, const double *, const double *, double *, hipStream_t st) { return op(st); }
 size_t mgcg_floats_per_sample(int n) { size_t t = 0; for (int l = 0; (n >> l) >= 2; ++l) { const size_t nl = n >> l, np = nl + 1; t += 2 * np * nl + 3 * np * np; } return (t + 63) & ~(size_t)63; }
 hipError_t launch_mgcg(int, int, double, const double *, double *, double *, float *, double, int, uint32_t *, double *, double *, int32_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_unpad(int, int, const double *, double *, hipStream_t st) { return op(st); }

@@ -266,3 +266,61 @@ def test_estimate_iterative_mpml_vs_standard(solver):
         assert abs(x - y) <= max(2, 1e-3 * y)
     assert abs(mp["estimate"] - st["estimate"]) < 0.1 * tol
     ctx.close()
+
+
+# ----------------------------------------------------------------- multilevel MCMC
+
+def _mcmc_setup():
+    K, s2, lam, seed, n0 = 3, 1.0, 0.3, 91, 4
+    obs_xy = [(0.5, 0.5), (0.25, 0.25), (0.75, 0.5)]
+    truth = np.array([[0.8, -0.5, 0.3]])
+    n_true = 16
+    _, u = oracle.solve_batch(n_true, oracle.kl_basis(n_true, K, s2, lam), truth, want_u=True)
+    m = n_true - 1
+    obs = [(x, y, float(u[0, (round(y * n_true) - 1) * m + round(x * n_true) - 1]) + 1e-4 * (j - 1))
+           for j, (x, y) in enumerate(obs_xy)]
+    return K, s2, lam, seed, n0, obs
+
+
+def test_mlmcmc_matches_oracle_fp64():
+    """mlmc_mcmc with FP64 direct solves against the oracle's multilevel MCMC
+    on the same random numbers: the same acceptance counts on every level and
+    the same level means (the chains are identical)."""
+    torch = _torch()
+    K, s2, lam, seed, n0, obs = _mcmc_setup()
+    L, C, steps, burn, sub, beta, noise = 2, 8, [12, 8, 6], 4, 2, 0.5, 2e-3
+    ctx = _ctx(n0=n0, L_max=L, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    opts = [dict(dtype="f64", solver="direct")] * (L + 1)
+    res = ctx.mcmc(L, C, steps, obs, noise, burn_in=burn, subsample=sub, pcn_beta=beta, opts=opts, seed=seed)
+    phis = {n0 << l: oracle.kl_basis(n0 << l, K, s2, lam) for l in range(L + 1)}
+    fw = {l: oracle.pde_forward(n0 << l, phis[n0 << l], obs, noise) for l in range(L + 1)}
+    normals = lambda stream, first, count, k: si.splitmix64_normals(seed, stream, first, count, k)
+    ref = oracle.mlmcmc(lambda l, xi: fw[l](xi), L, C, K, steps, burn, sub, beta, normals)
+    _say("gpu", res["Yhat"], res["accept"], res["accept_coarse"], "oracle", ref["Yhat"], ref["accept"],
+         ref["accept_coarse"])
+    assert res["accept"] == ref["accept"] and res["accept_coarse"] == ref["accept_coarse"]
+    for a, b in zip(res["Yhat"], ref["Yhat"]):
+        assert abs(a - b) <= 1e-11 * max(abs(b), 1e-3)
+    assert 0.05 < res["accept"][0] < 0.99
+    ctx.close()
+
+
+def test_mlmcmc_mixed_precision_solves():
+    """The same chains with the FP32 factor refined to the accuracy targets of
+    Sec. 4.5 on every level: the estimate stays within a small fraction of
+    the statistical error of the FP64 run (the rule is about the quantity of
+    interest, not the sampler)."""
+    torch = _torch()
+    K, s2, lam, seed, n0, obs = _mcmc_setup()
+    L, C, steps, burn, sub, beta, noise = 2, 256, [40, 30, 30], 10, 5, 0.7, 2e-3
+    ctx = _ctx(n0=n0, L_max=L, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    eps = ctx.accuracy_targets(L)
+    o64 = [dict(dtype="f64", solver="direct")] * (L + 1)
+    omx = [dict(dtype="f32", solver="direct_ir", eps_fine=eps[l], eps_coarse=eps[l - 1] if l else 0.0)
+           for l in range(L + 1)]
+    r64 = ctx.mcmc(L, C, steps, obs, noise, burn_in=burn, subsample=sub, pcn_beta=beta, opts=o64, seed=seed)
+    rmx = ctx.mcmc(L, C, steps, obs, noise, burn_in=burn, subsample=sub, pcn_beta=beta, opts=omx, seed=seed)
+    se = math.sqrt(sum(r64["var_mean"]))
+    _say("fp64", r64["estimate"], r64["accept"], "mixed", rmx["estimate"], rmx["accept"], "se", se)
+    assert abs(rmx["estimate"] - r64["estimate"]) <= 0.1 * se
+    ctx.close()

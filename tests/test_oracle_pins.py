@@ -611,3 +611,41 @@ def test_p1_adjoint_vs_central_differences():
             e[0, k] = 1e-6
             fd[k] = (oracle.solve_batch(n, Phi, xi + e)[0] - oracle.solve_batch(n, Phi, xi - e)[0]) / 2e-6
     assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def _toy_forward(a_of, c_of, d, s):
+    def f(l, xi):
+        return xi @ c_of(l), -((d - xi @ a_of(l)) ** 2) / (2.0 * s * s)
+    return f
+
+
+def test_mlmcmc_linear_gaussian_posterior():
+    """Multilevel MCMC on a linear-Gaussian toy whose posteriors are known in
+    closed form: prior N(0, I_2), level-l observation a_l . xi + N(0, s^2) of
+    d, quantity c_l . xi; E_{pi_L}[c_L . xi] = c_L^T P^{-1} a_L d / s^2 with
+    P = I + a_L a_L^T / s^2.  The telescoping estimate must match it within
+    five standard errors, and so must its level-0 term E_{pi_0}[c_0 . xi];
+    the corrections are far larger than that error (a wrong acceptance ratio
+    would bias them).  The coarse chain is subsampled 30 times per fine step
+    with pCN step 0.9 so that its proposals are nearly independent draws from
+    pi_{l-1}, as the method requires (with 3 steps of 0.5 the corrections
+    come out 40% short)."""
+    K, d, s = 2, 0.8, 0.5
+    a0, e = np.array([1.0, 0.5]), np.array([1.0, -1.0])
+    c0 = np.array([0.7, -0.4])
+    a_of = lambda l: a0 + 0.6 * 2.0 ** (-l) * e
+    c_of = lambda l: c0 + 0.4 * 2.0 ** (-l) * np.ones(2)
+
+    def exact(l):
+        a = a_of(l)
+        P = np.eye(K) + np.outer(a, a) / s ** 2
+        return float(c_of(l) @ np.linalg.solve(P, a * d / s ** 2))
+
+    normals = lambda stream, first, count, k: si.splitmix64_normals(77, stream, first, count, k)
+    L = 2
+    r = oracle.mlmcmc(_toy_forward(a_of, c_of, d, s), L, 1024, K, [200, 150, 150], 100, 30, 0.9, normals)
+    se = math.sqrt(sum(r["var_mean"]))
+    assert abs(r["estimate"] - exact(L)) <= 5 * se, (r["estimate"], exact(L), se)
+    assert abs(r["Yhat"][0] - exact(0)) <= 5 * math.sqrt(r["var_mean"][0])
+    assert abs(exact(L) - exact(0)) > 20 * se
+    assert 0.2 < r["accept"][0] < 0.95 and all(x > 0.3 for x in r["accept"][1:])
