@@ -33,6 +33,7 @@ Legs:
     each at fixed N_l, MSE against FP64 over many runs with shared xi, and
     the stored-bytes count; and its iterative-solver comparison (adaptive
     MPML against standard MLMC at a fixed 1e-6, MINRES and multigrid CG);
+    and multilevel MCMC with FP64 and mixed-precision solves;
   * CPU: the FP64 oracle on a bounded sample of the workload, host cores,
     one core, and LAPACK's banded Cholesky on the same systems.
 
@@ -125,7 +126,7 @@ def parse():
                    help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--ttr-runs", type=int, default=20, help="seeds of the time-to-RMSE leg")
-    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5,paper_iterative",
+    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5,paper_iterative,mlmcmc",
                    help="comma-separated other-workload legs to run (empty: none)")
     p.add_argument("--q43-runs", type=int, default=1000, help="runs of the quarter-precision leg")
     p.add_argument("--paper5-runs", type=int, default=300, help="runs of the Table 1 precision leg")
@@ -479,6 +480,43 @@ def leg_paper_iterative(a):
     return out
 
 
+def leg_mlmcmc(a):
+    """Multilevel MCMC (mlmc_mcmc) on the paper's first example (P1
+    elements, trigonometric field s = 4, q = 2, sigma = 2, h0 = 1/8, levels
+    8/16/32 cells): data at nine interior nodes from a fixed parameter, noise
+    1e-3; 1024 chains per level, 100/60/40 recorded steps after 20 of burn-in,
+    the coarse chain subsampled 10 times with pCN step 0.8; FP64 direct solves
+    against FP32 factors refined to the accuracy targets: wall time, device
+    solves, the estimate and its standard error, acceptance rates."""
+    import numpy as np
+    import torch
+    w, ctx = _ctx_for("paper5_n8-128_trig4")
+    L, C = 2, 1024
+    n_t = 64
+    xs = [0.25, 0.5, 0.75]
+    truth = torch.tensor([[0.6, -0.8, 0.5, -0.3]], dtype=torch.float64)
+    # data from a fixed parameter on a finer grid of the same library (FP64)
+    wt, ctx_t = _ctx_for("paper5_n8-128_trig4", n0=n_t, L_max=0)
+    out_t = ctx_t.solve(0, truth, dtype="f64", solver="direct", want_u=True)
+    u = out_t["u"].cpu().numpy()[0]
+    ctx_t.close()
+    obs = [(x, y, float(u[(round(y * n_t) - 1) * (n_t - 1) + round(x * n_t) - 1])) for y in xs for x in xs]
+    eps = ctx.accuracy_targets(L)
+    runs = {}
+    for name, opts in (("fp64", [dict(dtype="f64", solver="direct")] * (L + 1)),
+                       ("mixed", [dict(dtype="f32", solver="direct_ir", eps_fine=eps[l],
+                                       eps_coarse=eps[l - 1] if l else 0.0) for l in range(L + 1)])):
+        ctx.mcmc(L, 64, [4, 4, 4], obs, 1e-3, burn_in=2, subsample=2, pcn_beta=0.8, opts=opts)  # warm-up
+        r = ctx.mcmc(L, C, [100, 60, 40], obs, 1e-3, burn_in=20, subsample=10, pcn_beta=0.8, opts=opts)
+        r["se"] = float(np.sqrt(sum(r["var_mean"])))
+        runs[name] = r
+    ctx.close()
+    runs["speedup"] = runs["fp64"]["wall_s"] / runs["mixed"]["wall_s"]
+    runs["estimate_diff_over_se"] = abs(runs["mixed"]["estimate"] - runs["fp64"]["estimate"]) / runs["fp64"]["se"]
+    runs["chains"] = C
+    return runs
+
+
 def cpu_single_and_lapack(oracle, si, w, ctx, levels, Ns, phis, budget):
     """One-core oracle time and LAPACK's banded Cholesky (dpbtrf/dpbtrs via
     SciPy, on the band matrices the oracle assembles; the assembly is not
@@ -740,7 +778,7 @@ def main():
     ctx_main = ctx
     for name in sel:
         fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43, "paper5": leg_paper5,
-              "paper_iterative": leg_paper_iterative}[name]
+              "paper_iterative": leg_paper_iterative, "mlmcmc": leg_mlmcmc}[name]
         t0 = time.perf_counter()
         legs[name] = fn(a)
         legs[name]["leg_wall_s"] = time.perf_counter() - t0
