@@ -67,7 +67,8 @@ def kernel_src_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_2503_05533_amd", "csrc")
     src = b"".join(open(os.path.join(d, f), "rb").read()
-                   for f in ("factor_mfma.hip", "kernels.h", "dtypes.h", "ir_common.h"))
+                   for f in ("factor_mfma.hip", "refine_blk.hip", "blk_common.h", "kernels.h", "dtypes.h",
+                             "ir_common.h"))
     return hashlib.sha256(src).hexdigest()[:16]
 
 

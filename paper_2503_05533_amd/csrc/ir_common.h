@@ -131,16 +131,17 @@ __device__ inline resid_out wg_sum3(double a, double b, double c, double *red)
 // terms; x - 0.0 and r + 0.0 are exact), so that the loads of several
 // unknowns are in flight together (four, two for n <= 32, whose one-wave
 // refinement kernel keeps four waves per SIMD that way).  red holds 3 NT
-// doubles.
-template <int NT, int M>
+// doubles; D is the edge rule.
+template <int NT, int M, int D>
 __device__ inline resid_out residual_pass_m(double fconst, const double *__restrict__ as,
                                             const double *__restrict__ xs, double *__restrict__ rs,
-                                            double *red, int disc)
+                                            double *red)
 {
-    constexpr int m = M - 1, np = M + 1, TOT = m * M, IT = (TOT + NT - 1) / NT;
+    constexpr int disc = D;  // the edge rule, a compile-time constant here
+    constexpr int m = M - 1, np = M + 1, TOT = m * M, IT = (TOT + NT - 1) / NT, UNR = M <= 32 ? 2 : 4;
     const double h = 1.0 / M, bval = h * h * fconst;
     double rr = 0.0, bb = 0.0, sx = 0.0;
-#pragma unroll (M <= 32 ? 2 : 4)
+#pragma unroll UNR
     for (int k = 0; k < IT; ++k) {
         const int e = threadIdx.x + k * NT;
         const bool live = e < TOT;
@@ -148,11 +149,11 @@ __device__ inline resid_out residual_pass_m(double fconst, const double *__restr
         const int j = ec / M, i = ec % M;
         const bool in = live && i < m;
         // node of the unknown; for the pad entry (i = m) it is a boundary node
-        // whose neighbours are still inside the node array (values unused)
-        // (the pad's node stands for an interior one: its diagonal neighbours
-        // are outside the node array)
+        // whose axis neighbours are still inside the node array (values
+        // unused); P1 faces also read diagonal neighbours, outside the array
+        // for that node, so the pad then reads the node west of it instead
         const int p = (j + 1) * np + (i + 1);
-        const faces4 f = node_faces(disc, as, in ? p : p - 1, np);
+        const faces4 f = node_faces(disc, as, (disc && !in) ? p - 1 : p, np);
         const double aw = f.w, ae = f.e, asu = f.s, an = f.n;
         const double xv = xs[ec];
         const double xw = xs[ec > 0 ? ec - 1 : 0], xe = xs[ec + 1 < TOT ? ec + 1 : TOT - 1];
