@@ -127,7 +127,7 @@ def parse():
                    help="absolute tolerance of the time-to-RMSE leg (0 skips it)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--ttr-runs", type=int, default=20, help="seeds of the time-to-RMSE leg")
-    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5,paper_iterative,mlmcmc",
+    p.add_argument("--legs", default="c0,c2,c3,c4,q43,paper5,paper_iterative,mlmcmc,mimc",
                    help="comma-separated other-workload legs to run (empty: none)")
     p.add_argument("--q43-runs", type=int, default=1000, help="runs of the quarter-precision leg")
     p.add_argument("--paper5-runs", type=int, default=300, help="runs of the Table 1 precision leg")
@@ -518,6 +518,34 @@ def leg_mlmcmc(a):
     return runs
 
 
+def leg_mimc(a):
+    """Multi-index Monte Carlo (mlmc_mimc) on the step's field and grids: index
+    l the grid (16 to 128 cells), index k the field truncated to 16 2^k of its
+    64 modes, the total-degree set l + k <= 3 (9 indices) with
+    N = 20000 4^-l 2^-k samples; FP64 direct solves against FP32 factors
+    refined to the accuracy targets (grid l to delta_l): wall time of the
+    second of two identical calls, the estimate and its standard error, the
+    per-index means, device solves and convergence counts."""
+    import numpy as np
+    w, ctx = _ctx_for("mlmc4_n16-128_K64")
+    L, K0 = 3, 16
+    idx = [(l, k) for l in range(L + 1) for k in range(3) if l + k <= L]
+    N = [int(round(20000 * 4.0 ** (-l) * 2.0 ** (-k))) for l, k in idx]
+    eps = ctx.accuracy_targets(L)
+    runs = {"indices": idx, "N": N, "K0": K0}
+    for name, opts in (("fp64", [dict(dtype="f64", solver="direct")] * len(idx)),
+                       ("mixed", [dict(dtype="f32", solver="direct_ir", eps_fine=eps[l],
+                                       eps_coarse=eps[l - 1] if l else 0.0) for l, _ in idx])):
+        ctx.mimc(idx, N, K0, opts=opts)
+        r = ctx.mimc(idx, N, K0, opts=opts)
+        r["se"] = float(np.sqrt(r["var_estimate"]))
+        runs[name] = r
+    ctx.close()
+    runs["speedup"] = runs["fp64"]["wall_s"] / runs["mixed"]["wall_s"]
+    runs["estimate_diff_over_se"] = abs(runs["mixed"]["estimate"] - runs["fp64"]["estimate"]) / runs["fp64"]["se"]
+    return runs
+
+
 def cpu_single_and_lapack(oracle, si, w, ctx, levels, Ns, phis, budget):
     """One-core oracle time and LAPACK's banded Cholesky (dpbtrf/dpbtrs via
     SciPy, on the band matrices the oracle assembles; the assembly is not
@@ -779,7 +807,7 @@ def main():
     ctx_main = ctx
     for name in sel:
         fn = {"c0": leg_c0, "c2": leg_c2, "c3": leg_c3, "c4": leg_c4, "q43": leg_q43, "paper5": leg_paper5,
-              "paper_iterative": leg_paper_iterative, "mlmcmc": leg_mlmcmc}[name]
+              "paper_iterative": leg_paper_iterative, "mlmcmc": leg_mlmcmc, "mimc": leg_mimc}[name]
         t0 = time.perf_counter()
         legs[name] = fn(a)
         legs[name]["leg_wall_s"] = time.perf_counter() - t0

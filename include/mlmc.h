@@ -389,6 +389,48 @@ typedef struct {
 
 int mlmc_mcmc(mlmc_ctx *ctx, const mlmc_mcmc_config *cfg, mlmc_mcmc_result *out, void *stream);
 
+/* Multi-index Monte Carlo with the same per-grid solves (the second sampler
+ * of the concluding remark of Sec. 4, Haji-Ali, Nobile and Tempone's
+ * estimator): E[Q] is estimated by the sum over an index set of the sample
+ * means of the mixed differences
+ *   D_a = Q_(l,k) - Q_(l-1,k) - Q_(l,k-1) + Q_(l-1,k-1),   a = (l, k),
+ * terms with l - 1 < 0 or k - 1 < 0 left out.  Index l is the grid (n0 2^l
+ * cells per side); index k truncates the context's field to its first
+ * K_k = min(K, K0 2^k) modes (the modes are ordered by decreasing variance):
+ * Q_(l,k)(xi) = Q_l(xi with every coefficient from mode K_k on set to 0).
+ * Index i has N[i] independent samples, drawn with the context's generator
+ * (mlmc_fill_xi) on the reserved level index 8192 + i, sample index
+ * 0 .. N[i]-1; the (up to) four solves of a sample share its xi and run with
+ * opts[i]: eps_fine on grid l, eps_coarse on grid l - 1, the same factor
+ * dtype and solver on both.  Samples run in chunks that fit a 4 GiB solve
+ * workspace.  Per index the result holds the sample mean and variance of D_a
+ * (fixed-order sums), and the samples any of whose solves were promoted to
+ * FP64 or did not converge; the call returns MLMC_ENOCONV when any did not.
+ * Indices must be distinct, 1 <= K0 <= K, N[i] >= 2.  Allocates its device
+ * buffers for the call; synchronises the stream. */
+typedef struct {
+    int32_t n_idx;             /* indices in the set, 1..64 */
+    int32_t idx_l[64];         /* grid index l of index i, 0..L_max */
+    int32_t idx_k[64];         /* truncation index k of index i, 0..15 */
+    int64_t N[64];             /* samples of index i (>= 2) */
+    int32_t K0;                /* modes kept at truncation index 0 */
+    mlmc_level_opts opts[64];  /* solver of index i's grids */
+    uint64_t seed;             /* generator seed of the indices' xi */
+} mlmc_mimc_config;
+
+typedef struct {
+    double estimate;           /* sum_i mean[i] */
+    double var_estimate;       /* sum_i var[i] / N[i] */
+    double mean[64];           /* sample mean of D_a over index i's samples */
+    double var[64];            /* sample variance of D_a (N - 1 normalisation) */
+    int64_t n_promoted[64];    /* samples with a solve promoted to FP64 */
+    int64_t n_noconv[64];      /* samples with a solve that did not converge */
+    int64_t solves;            /* batched solves issued */
+    double wall_s;
+} mlmc_mimc_result;
+
+int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *cfg, mlmc_mimc_result *out, void *stream);
+
 /* Kernel timing for measurement.  While enabled, the library brackets each
  * launch of the field, assembly, factor, solve and residual kernels with HIP
  * events on the caller's stream and records (kernel kind, grid n, samples).

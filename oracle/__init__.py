@@ -27,6 +27,10 @@ Functions and the passage each follows:
                               remark on other sampling methods, sec. 4):
                               pCN chains on level 0, two-level chains with
                               an independence proposal from a coarse chain
+  mimc                     -- multi-index Monte Carlo (the second sampler of
+                              that remark): sample means of the mixed
+                              differences over a set of (grid, truncation)
+                              indices
 """
 import ctypes
 import math
@@ -453,3 +457,36 @@ def mlmcmc(forward, L, chains, K, steps, burn_in, subsample, beta, normals):
         out["accept_coarse"].append(float(acc_c.sum() / (C * steps[l] * subsample)) if l else 0.0)
     out["estimate"] = float(sum(out["Yhat"]))
     return out
+
+
+def mimc(indices, N, K0, K, solve, normals):
+    """Multi-index Monte Carlo, written from the definition of Haji-Ali, Nobile
+    and Tempone's estimator (the second sampler of the remark on other
+    sampling methods at the end of sec. 4): E[Q] ~ sum over the index set of
+    the sample mean of the mixed difference
+      D_(l,k)(xi) = Q_(l,k) - Q_(l-1,k) - Q_(l,k-1) + Q_(l-1,k-1),
+    terms with a negative index left out, over N[i] independent samples of
+    index i = (l, k); Q_(l,k)(xi) is the level-l quantity of xi with the
+    coefficients from mode min(K, K0 2^k) on set to zero (the field's modes
+    ordered by decreasing variance).  solve(l, xi) -> Q_l for the rows of xi;
+    normals(i, count) -> [count, K] samples of index i.  Returns the
+    per-index means and variances (N - 1 normalisation) and their sums."""
+    out = dict(mean=[], var=[])
+    for i, (l, k) in enumerate(indices):
+        xi = np.asarray(normals(i, N[i]), dtype=np.float64)
+        d = np.zeros(N[i])
+        for t in (0, 1):              # truncation k - t
+            if k - t < 0:
+                continue
+            xm = xi.copy()
+            xm[:, min(K, K0 << (k - t)):] = 0.0
+            for g in (0, 1):          # grid l - g
+                if l - g < 0:
+                    continue
+                d += (-1.0) ** (t + g) * np.asarray(solve(l - g, xm), dtype=np.float64)
+        out["mean"].append(float(d.mean()))
+        out["var"].append(float(d.var(ddof=1)))
+    out["estimate"] = float(sum(out["mean"]))
+    out["var_estimate"] = float(sum(v / n for v, n in zip(out["var"], N)))
+    return out
+

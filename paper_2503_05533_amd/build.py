@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmlmc.so")
 SOURCES = ["csrc/kernels.hip", "csrc/factor_mfma.hip", "csrc/refine_blk.hip", "csrc/minres.hip", "csrc/mgcg.hip",
-           "csrc/mcmc.hip", "csrc/scratch.hip",
+           "csrc/mcmc.hip", "csrc/mimc.hip", "csrc/scratch.hip",
            "csrc/api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

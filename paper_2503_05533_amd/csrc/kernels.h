@@ -122,6 +122,13 @@ hipError_t launch_mcmc_accept(int C, int K, int n, int mode, int n_obs, const in
 hipError_t launch_mcmc_loglik(int C, int n, int n_obs, const int *obs_node, const double *obs_val, double noise_sd,
                               const double *x, double *ll, hipStream_t st);
 hipError_t launch_mcmc_record(int C, const double *qf, const double *qc, double *sums, hipStream_t st);
+// Multi-index Monte Carlo: coefficients from mode `keep` on set to zero, and
+// the mixed difference q0 - q1 - q2 + q3 (NULL terms absent) with the
+// combined convergence state of its solves.
+hipError_t launch_mask_modes(int C, int K, int keep, const double *xi, double *out, hipStream_t st);
+hipError_t launch_mimc_combine(int C, const double *q0, const double *q1, const double *q2, const double *q3,
+                               const uint32_t *s0, const uint32_t *s1, const uint32_t *s2, const uint32_t *s3,
+                               double *y, uint32_t *st, hipStream_t stream);
 hipError_t launch_adjoint_gz(int n, int S, const double *a, const double *u, const double *lam,
                              double *gz, int disc, hipStream_t st);
 hipError_t launch_unpad(int n, int S, const double *x, double *u, hipStream_t st);

@@ -25,7 +25,7 @@ EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
            "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
            "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
            "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune",
-           "mlmc_sample_level_noalloc", "mlmc_set_seed", "mlmc_mcmc"]
+           "mlmc_sample_level_noalloc", "mlmc_set_seed", "mlmc_mcmc", "mlmc_mimc"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -82,6 +82,19 @@ class _MCMCResult(ctypes.Structure):
                 ("wall_s", ctypes.c_double)]
 
 
+class _MIMCConfig(ctypes.Structure):
+    _fields_ = [("n_idx", ctypes.c_int32), ("idx_l", ctypes.c_int32 * 64), ("idx_k", ctypes.c_int32 * 64),
+                ("N", ctypes.c_int64 * 64), ("K0", ctypes.c_int32), ("opts", _LevelOpts * 64),
+                ("seed", ctypes.c_uint64)]
+
+
+class _MIMCResult(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("var_estimate", ctypes.c_double),
+                ("mean", ctypes.c_double * 64), ("var", ctypes.c_double * 64),
+                ("n_promoted", ctypes.c_int64 * 64), ("n_noconv", ctypes.c_int64 * 64),
+                ("solves", ctypes.c_int64), ("wall_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -126,6 +139,7 @@ def load_library():
     lib.mlmc_autotune.argtypes = [vp, i32, i64, vp, ctypes.POINTER(_LevelOpts), vp, ctypes.c_size_t,
                                   ctypes.POINTER(i32), vp]
     lib.mlmc_mcmc.argtypes = [vp, ctypes.POINTER(_MCMCConfig), ctypes.POINTER(_MCMCResult), vp]
+    lib.mlmc_mimc.argtypes = [vp, ctypes.POINTER(_MIMCConfig), ctypes.POINTER(_MIMCResult), vp]
     lib.mlmc_profile.argtypes = [vp, i32]
     lib.mlmc_profile_read.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
@@ -374,6 +388,25 @@ class MLMC:
         return dict(estimate=r.estimate, Yhat=list(r.Yhat[:L + 1]), var_mean=list(r.var_mean[:L + 1]),
                     accept=list(r.accept[:L + 1]), accept_coarse=list(r.accept_coarse[:L + 1]),
                     solves=r.solves, wall_s=r.wall_s, rc=rc)
+
+    def mimc(self, indices, N, K0, opts=None, seed=None):
+        """Multi-index Monte Carlo (mlmc_mimc): indices a list of (l, k) (grid
+        index, truncation index: the first K0 * 2**k modes), N the samples per
+        index, opts a list of per-index option dicts (dtype, solver, eps_fine,
+        eps_coarse).  Returns the estimate and the per-index means, variances,
+        promotion and non-convergence counts."""
+        c = _MIMCConfig()
+        c.n_idx, c.K0 = len(indices), int(K0)
+        for i, (l, k) in enumerate(indices):
+            c.idx_l[i], c.idx_k[i], c.N[i] = int(l), int(k), int(N[i])
+            c.opts[i] = self._opts(**((opts or [{}] * len(indices))[i]))
+        c.seed = int(self.cfg.seed if seed is None else seed) & 0xFFFFFFFFFFFFFFFF
+        r = _MIMCResult()
+        rc = self._check(self.lib.mlmc_mimc(self.h, ctypes.byref(c), ctypes.byref(r), _stream()), "mimc")
+        n = len(indices)
+        return dict(estimate=r.estimate, var_estimate=r.var_estimate, mean=list(r.mean[:n]), var=list(r.var[:n]),
+                    n_promoted=list(r.n_promoted[:n]), n_noconv=list(r.n_noconv[:n]), solves=r.solves,
+                    wall_s=r.wall_s, rc=rc)
 
     def grad_from(self, level, xi, ws, grad_q=None, eps_adjoint=1e-10, dtype="f32",
                   solver="direct_ir", eps=1e-10):

@@ -183,6 +183,8 @@ hipError_t launch_pcn_propose(int, int, double, const double *, const double *, 
 hipError_t launch_mcmc_accept(int, int, int, int, int, const int *, const double *, double, const double *, const double *, const double *, const double *, const double *, double *, double *, double *, double *, int64_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_mcmc_loglik(int, int, int, const int *, const double *, double, const double *, double *, hipStream_t st) { return op(st); }
 hipError_t launch_mcmc_record(int, const double *, const double *, double *, hipStream_t st) { return op(st); }
+hipError_t launch_mask_modes(int, int, int, const double *, double *, hipStream_t st) { return op(st); }
+hipError_t launch_mimc_combine(int, const double *, const double *, const double *, const double *, const uint32_t *, const uint32_t *, const uint32_t *, const uint32_t *, double *, uint32_t *, hipStream_t st) { return op(st); }
 size_t mgcg_floats_per_sample(int n) { size_t t = 0; for (int l = 0; (n >> l) >= 2; ++l) { const size_t nl = n >> l, np = nl + 1; t += 2 * np * nl + 3 * np * np; } return (t + 63) & ~(size_t)63; }
 hipError_t launch_mgcg(int, int, double, const double *, double *, double *, float *, double, int, uint32_t *, double *, double *, int32_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_unpad(int, int, const double *, double *, hipStream_t st) { return op(st); }

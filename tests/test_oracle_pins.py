@@ -649,3 +649,49 @@ def test_mlmcmc_linear_gaussian_posterior():
     assert abs(r["Yhat"][0] - exact(0)) <= 5 * math.sqrt(r["var_mean"][0])
     assert abs(exact(L) - exact(0)) > 20 * se
     assert 0.2 < r["accept"][0] < 0.95 and all(x > 0.3 for x in r["accept"][1:])
+
+
+def test_mimc_box_telescopes_to_its_corner():
+    """With the same samples on every index of a full box {0..L} x {0..Kq},
+    the sum of the mixed differences telescopes to the corner quantity
+    Q_(L,Kq) exactly (up to rounding): a wrong sign, a wrong neighbour index or
+    a truncation that is not the one of the neighbouring index breaks it.  Two
+    boxes pin the truncation rule min(K, K0 2^k): Kq = 1 keeps 4 of 8 modes,
+    Kq = 2 all 8."""
+    n0, L, K, K0, s2, lam, seed = 4, 2, 8, 2, 1.0, 0.3, 123
+    phis = {l: oracle.kl_basis(n0 << l, K, s2, lam) for l in range(L + 1)}
+    solve = lambda l, xi: oracle.solve_batch(n0 << l, phis[l], xi)
+    xi = si.splitmix64_normals(seed, 0, 0, 6, K)
+    same = lambda i, count: xi[:count]
+    for Kq, keep in ((1, 4), (2, 8)):
+        idx = [(l, k) for l in range(L + 1) for k in range(Kq + 1)]
+        r = oracle.mimc(idx, [6] * len(idx), K0, K, solve, same)
+        xm = xi.copy()
+        xm[:, keep:] = 0.0
+        corner = float(np.mean(solve(L, xm)))
+        assert abs(r["estimate"] - corner) <= 1e-13 * abs(corner), (Kq, r["estimate"], corner)
+        # the truncation matters: the corner with all modes differs when Kq = 1
+        if Kq == 1:
+            assert abs(corner - float(np.mean(solve(L, xi)))) > 1e-6
+
+
+def test_mimc_toy_expectation():
+    """Independent samples per index on a toy with a known mean: Q_(l,k)(xi) =
+    sum_{j < K_k} c_j(l) xi_j^2 + b(l) . xi, so E[Q_(l,k)] = sum_{j < K_k} c_j(l)
+    (the linear term has mean zero).  Over the full box the estimator's mean is
+    the corner's, and the estimate must lie within five standard errors of it
+    (its variance estimate is sum_i var_i / N_i); the mixed differences shrink
+    with both indices, as MIMC needs."""
+    K, K0, L, Kq, seed = 8, 2, 2, 2, 99
+    c = lambda l: (1.0 + 0.5 * 2.0 ** (-2 * l)) * 0.6 ** np.arange(K)
+    b = lambda l: 0.3 * 2.0 ** (-l) * np.ones(K)
+    solve = lambda l, xi: (xi ** 2) @ c(l) + xi @ b(l)
+    normals = lambda i, count: si.splitmix64_normals(seed, 8192 + i, 0, count, K)
+    idx = [(l, k) for l in range(L + 1) for k in range(Kq + 1)]
+    N = [4000 // (1 + l + k) for (l, k) in idx]
+    r = oracle.mimc(idx, N, K0, K, solve, normals)
+    exact = float(np.sum(c(L)[:min(K, K0 << Kq)]))
+    se = math.sqrt(r["var_estimate"])
+    assert abs(r["estimate"] - exact) <= 5 * se, (r["estimate"], exact, se)
+    v = dict(zip(idx, r["var"]))
+    assert v[(2, 2)] < v[(1, 1)] < v[(0, 0)]
