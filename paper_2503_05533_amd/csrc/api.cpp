@@ -1559,8 +1559,10 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
     size_t wsf = 0, wsc = 0;
     for (int i = 0; i < mi->n_idx; ++i) {
         const int l = mi->idx_l[i];
-        const size_t per = make_layout(c.n0 << l, 1, mi->opts[i]).bytes +
-                           (l > 0 ? make_layout(c.n0 << (l - 1), 1, mi->opts[i]).bytes : 0);
+        // bytes per sample from a 4096-sample layout (the promotion pool is a
+        // fraction of the batch)
+        const size_t per = (make_layout(c.n0 << l, 4096, mi->opts[i]).bytes +
+                            (l > 0 ? make_layout(c.n0 << (l - 1), 4096, mi->opts[i]).bytes : 0) + 4095) / 4096;
         Ci[i] = std::min<int64_t>({mi->N[i], (int64_t)1 << 20, std::max<int64_t>(1, (int64_t)(budget / per))});
         C = std::max(C, Ci[i]);
         wsf = std::max(wsf, make_layout(c.n0 << l, Ci[i], mi->opts[i]).bytes);

@@ -1,7 +1,7 @@
 // Host-only driver of the C ABI against the stub runtime: the multi-level
 // step (graph and eager, FP32 refinement and FP64 direct) with the four-level
 // workload shapes, three times each, then the adaptive estimator (mixed and
-// standard).  Run under AddressSanitizer by tests/test_host_logic.py, once
+// standard), the no-allocation entry point and the multi-index driver.  Run under AddressSanitizer by tests/test_host_logic.py, once
 // as is and once with the stub reporting a non-converged sample per chunk.
 #include <cstdio>
 #include <cstdlib>
@@ -67,6 +67,35 @@ int main()
                                            nullptr, &st, nullptr);
             printf("noalloc n=%lld rc=%d\n", (long long)ns[k], rc);
         }
+    }
+    {
+        // multi-index Monte Carlo: three indices (chunked by the driver's
+        // budget), then a repeated index
+        mlmc_mimc_config mc{};
+        mc.n_idx = 3;
+        const int il[3] = {0, 1, 3}, ik[3] = {0, 1, 0};
+        const int64_t nn[3] = {1000, 500, 300};
+        double eps[16];
+        mlmc_accuracy_targets(ctx, 3, eps);
+        for (int i = 0; i < 3; ++i) {
+            mc.idx_l[i] = il[i];
+            mc.idx_k[i] = ik[i];
+            mc.N[i] = nn[i];
+            mc.opts[i].factor_dtype = MLMC_F32;
+            mc.opts[i].solver = MLMC_DIRECT_IR;
+            mc.opts[i].eps_fine = eps[il[i]];
+            mc.opts[i].eps_coarse = il[i] ? eps[il[i] - 1] : 0.0;
+            mc.opts[i].promote = 1;
+        }
+        mc.K0 = 16;
+        mc.seed = 5;
+        mlmc_mimc_result mr;
+        rc = mlmc_mimc(ctx, &mc, &mr, nullptr);
+        printf("mimc rc=%d solves=%lld noconv0=%lld\n", rc, (long long)mr.solves, (long long)mr.n_noconv[0]);
+        mc.idx_l[2] = 1;
+        mc.idx_k[2] = 1;
+        rc = mlmc_mimc(ctx, &mc, &mr, nullptr);
+        printf("mimc repeated rc=%d\n", rc);
     }
     mlmc_destroy(ctx);
     return 0;

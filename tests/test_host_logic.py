@@ -42,6 +42,13 @@ def test_host_scheduling_under_asan(tmp_path):
     assert noalloc == ["noalloc n=64 rc=0", "noalloc n=200000 rc=-2"], r.stdout
     est = [l for l in lines if l.startswith("estimate")]
     assert len(est) == 2 and all(" rc=0 " in l and " L=3 " in l and " noconv0=0 " in l for l in est), r.stdout
+    # multi-index driver: one solve per (grid, truncation) term and chunk:
+    # (0,0) 1 term, (1,1) 4 terms, (3,0) 2 terms in two chunks (its 300
+    # samples need ~17.5 MB each, the FP32 factor and an FP64 promotion slot
+    # on the 128-cell grid plus the 64-cell grid, against the 4 GiB budget);
+    # a repeated index is refused
+    mimc = [l for l in lines if l.startswith("mimc")]
+    assert mimc == ["mimc rc=0 solves=9 noconv0=0", "mimc repeated rc=-1"], r.stdout
     # every chunk reports a non-converged sample: the estimator stops after
     # its first round with MLMC_ENOCONV and the counts per level
     env["STUB_NOCONV"] = "1"
@@ -52,3 +59,5 @@ def test_host_scheduling_under_asan(tmp_path):
     for l in est:
         assert " rc=1 " in l and " L=1 " in l and " conv=0 " in l, l
         assert int(l.split("noconv0=")[1].split()[0]) >= 1, l
+    mimc = [l for l in r.stdout.splitlines() if l.startswith("mimc rc=")]
+    assert mimc == ["mimc rc=1 solves=9 noconv0=1"], r.stdout
