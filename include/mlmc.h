@@ -402,10 +402,13 @@ int mlmc_mcmc(mlmc_ctx *ctx, const mlmc_mcmc_config *cfg, mlmc_mcmc_result *out,
  * (mlmc_fill_xi) on the reserved level index 8192 + i, sample index
  * 0 .. N[i]-1; the (up to) four solves of a sample share its xi and run with
  * opts[i]: eps_fine on grid l, eps_coarse on grid l - 1, the same factor
- * dtype and solver on both.  Samples run in chunks that fit a 4 GiB solve
- * workspace.  Per index the result holds the sample mean and variance of D_a
- * (fixed-order sums), and the samples any of whose solves were promoted to
- * FP64 or did not converge; the call returns MLMC_ENOCONV when any did not.
+ * dtype and solver on both.  The indices are spread over the context's
+ * queue streams (most expensive first onto the least loaded), each stream
+ * running its indices' samples in chunks that fit a 4 GiB solve workspace
+ * of its own.  Per index the result holds the sample mean and variance of
+ * D_a (per-chunk fixed-order sums, added in chunk order), and the samples
+ * any of whose solves were promoted to FP64 or did not converge; the call
+ * returns MLMC_ENOCONV when any did not.
  * Indices must be distinct, 1 <= K0 <= K, N[i] >= 2.  Allocates its device
  * buffers for the call; synchronises the stream. */
 typedef struct {

@@ -1539,10 +1539,9 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
     if (!ctx) return MLMC_EINVAL;
     if (!mi || !out) return fail(ctx, MLMC_EINVAL, "mimc: null argument");
     const mlmc_config &c = ctx->cfg;
-    const int K = c.K;
-    if (mi->n_idx < 1 || mi->n_idx > 64 || mi->K0 < 1 || mi->K0 > K)
-        return fail(ctx, MLMC_EINVAL, "mimc: bad configuration");
-    for (int i = 0; i < mi->n_idx; ++i) {
+    const int K = c.K, NI = mi->n_idx;
+    if (NI < 1 || NI > 64 || mi->K0 < 1 || mi->K0 > K) return fail(ctx, MLMC_EINVAL, "mimc: bad configuration");
+    for (int i = 0; i < NI; ++i) {
         const int l = mi->idx_l[i], k = mi->idx_k[i];
         if (l < 0 || l > c.L_max || k < 0 || k > 15 || mi->N[i] < 2 || mi->N[i] > ((int64_t)1 << 32))
             return fail(ctx, MLMC_EINVAL, "mimc: bad index %d", i);
@@ -1552,81 +1551,137 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
     }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
-    // chunk of index i: the samples whose fine and coarse solve workspaces fit
-    // the budget (at most all of the index's samples)
+    if (int rc = ensure_queues(ctx, 1 + kQueues)) return rc;
+    // Index i runs in chunks of Ci[i] samples whose fine and coarse solve
+    // workspaces fit the budget; the indices are spread over the context's
+    // queue streams (most expensive first onto the least loaded; cost
+    // samples x n^3.5 x terms) and each stream runs its indices' chunks in
+    // order in buffers of its own.
     const size_t budget = (size_t)4 << 30;
-    int64_t Ci[64], C = 1;
-    size_t wsf = 0, wsc = 0;
-    for (int i = 0; i < mi->n_idx; ++i) {
+    int64_t Ci[64], nch[64], sbase[64];
+    int qof[64];
+    double load[kQueues] = {};
+    std::vector<int> order(NI);
+    int64_t nsum = 0;
+    for (int i = 0; i < NI; ++i) {
         const int l = mi->idx_l[i];
         // bytes per sample from a 4096-sample layout (the promotion pool is a
         // fraction of the batch)
         const size_t per = (make_layout(c.n0 << l, 4096, mi->opts[i]).bytes +
                             (l > 0 ? make_layout(c.n0 << (l - 1), 4096, mi->opts[i]).bytes : 0) + 4095) / 4096;
         Ci[i] = std::min<int64_t>({mi->N[i], (int64_t)1 << 20, std::max<int64_t>(1, (int64_t)(budget / per))});
-        C = std::max(C, Ci[i]);
-        wsf = std::max(wsf, make_layout(c.n0 << l, Ci[i], mi->opts[i]).bytes);
-        if (l > 0) wsc = std::max(wsc, make_layout(c.n0 << (l - 1), Ci[i], mi->opts[i]).bytes);
+        nch[i] = (mi->N[i] + Ci[i] - 1) / Ci[i];
+        sbase[i] = nsum;
+        nsum += nch[i];
+        order[i] = i;
+    }
+    auto cost = [&](int i) {
+        const double nn = (double)(c.n0 << mi->idx_l[i]);
+        return (double)mi->N[i] * std::pow(nn, 3.5) * (mi->idx_l[i] ? 2 : 1) * (mi->idx_k[i] ? 2 : 1);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    for (int i : order) {
+        int q = 0;
+        for (int t = 1; t < kQueues; ++t)
+            if (load[t] < load[q]) q = t;
+        qof[i] = q;
+        load[q] += cost(i);
+    }
+    // per queue: the largest chunk and workspaces of its indices
+    struct qbuf { int64_t C = 0; size_t wsf = 0, wsc = 0, o_xi, o_xm, o_y, o_sy, o_q[4], o_s[4], o_wsf, o_wsc; };
+    qbuf Q[kQueues];
+    for (int i = 0; i < NI; ++i) {
+        const int l = mi->idx_l[i];
+        qbuf &B = Q[qof[i]];
+        B.C = std::max(B.C, Ci[i]);
+        B.wsf = std::max(B.wsf, make_layout(c.n0 << l, Ci[i], mi->opts[i]).bytes);
+        if (l > 0) B.wsc = std::max(B.wsc, make_layout(c.n0 << (l - 1), Ci[i], mi->opts[i]).bytes);
     }
     size_t need = 0;
-    auto take = [&](size_t b) { size_t o = need; need += align256(b); return o; };
-    const size_t o_xi = take((size_t)C * K * 8), o_xm = take((size_t)C * K * 8), o_y = take((size_t)C * 8),
-                 o_sy = take((size_t)C * 4), o_sums = take(8 * 8);
-    size_t o_q[4], o_s[4];
-    for (int e = 0; e < 4; ++e) {
-        o_q[e] = take((size_t)C * 8);
-        o_s[e] = take((size_t)C * 4);
+    auto take = [&](size_t b) { size_t o = need; need += align256(std::max<size_t>(b, 1)); return o; };
+    const size_t o_sums = take((size_t)nsum * 8 * 8);
+    for (int q = 0; q < kQueues; ++q) {
+        qbuf &B = Q[q];
+        if (B.C == 0) continue;
+        B.o_xi = take((size_t)B.C * K * 8);
+        B.o_xm = take((size_t)B.C * K * 8);
+        B.o_y = take((size_t)B.C * 8);
+        B.o_sy = take((size_t)B.C * 4);
+        for (int e = 0; e < 4; ++e) {
+            B.o_q[e] = take((size_t)B.C * 8);
+            B.o_s[e] = take((size_t)B.C * 4);
+        }
+        B.o_wsf = take(B.wsf);
+        B.o_wsc = take(B.wsc);
     }
-    const size_t o_wsf = take(wsf), o_wsc = take(std::max<size_t>(wsc, 256));
     void *buf = nullptr;
     HIPCHK(hipMalloc(&buf, need));
     memset(out, 0, sizeof *out);
     int64_t solves = 0;
-    double h[8];
+    std::vector<double> h((size_t)nsum * 8);
     auto run = [&]() -> int {
-        for (int i = 0; i < mi->n_idx; ++i) {
+        hipEvent_t fork = ctx->qevents[0];
+        HIPCHK(hipEventRecord(fork, st));
+        for (int q = 0; q < kQueues; ++q)
+            if (Q[q].C) HIPCHK(hipStreamWaitEvent(ctx->qstreams[q], fork, 0));
+        for (int i : order) {
             const int l = mi->idx_l[i], k = mi->idx_k[i];
             const mlmc_level_opts &o = mi->opts[i];
             const int nf = c.n0 << l;
-            double sy = 0.0, sy2 = 0.0;
-            int64_t npro = 0, nnc = 0;
-            for (int64_t first = 0; first < mi->N[i]; first += Ci[i]) {
-                const int64_t cc = std::min(Ci[i], mi->N[i] - first);
+            const qbuf &B = Q[qof[i]];
+            hipStream_t sq = ctx->qstreams[qof[i]];
+            for (int64_t ch = 0; ch < nch[i]; ++ch) {
+                const int64_t first = ch * Ci[i], cc = std::min(Ci[i], mi->N[i] - first);
                 const grid_layout Lf = make_layout(nf, cc, o);
                 const grid_layout Lc = l > 0 ? make_layout(nf / 2, cc, o) : grid_layout{};
-                void *wf = at<void>(buf, o_wsf), *wc = at<void>(buf, o_wsc);
-                HIPCHK(launch_fill_xi(mi->seed, 8192 + i, first, cc, K, at<double>(buf, o_xi), st));
-                // e = 2 t + g: truncation t (0: K_k, 1: K_{k-1}), grid g (0: l, 1: l - 1)
+                void *wf = at<void>(buf, B.o_wsf), *wc = at<void>(buf, B.o_wsc);
+                HIPCHK(launch_fill_xi(mi->seed, 8192 + i, first, cc, K, at<double>(buf, B.o_xi), sq));
+                // term e = 2 t + g: truncation t (0: K_k, 1: K_{k-1}), grid g (0: l, 1: l - 1)
                 bool have[4] = {false, false, false, false};
                 for (int t = 0; t < (k > 0 ? 2 : 1); ++t) {
                     const int64_t keep = std::min<int64_t>(K, (int64_t)mi->K0 << (k - t));
-                    HIPCHK(launch_mask_modes((int)cc, K, (int)keep, at<double>(buf, o_xi), at<double>(buf, o_xm), st));
+                    HIPCHK(launch_mask_modes((int)cc, K, (int)keep, at<double>(buf, B.o_xi), at<double>(buf, B.o_xm),
+                                             sq));
                     for (int g = 0; g < (l > 0 ? 2 : 1); ++g) {
                         const int e = 2 * t + g;
                         const grid_layout &G = g ? Lc : Lf;
                         void *w = g ? wc : wf;
                         ++solves;
-                        if (int rc = solve_grid(ctx, G, l - g, at<double>(buf, o_xm), o, g ? o.eps_coarse : o.eps_fine,
-                                                w, at<double>(buf, o_q[e]), at<int32_t>(w, G.off_iters), st))
+                        if (int rc = solve_grid(ctx, G, l - g, at<double>(buf, B.o_xm), o,
+                                                g ? o.eps_coarse : o.eps_fine, w, at<double>(buf, B.o_q[e]),
+                                                at<int32_t>(w, G.off_iters), sq))
                             return rc;
-                        HIPCHK(hipMemcpyAsync(at<uint32_t>(buf, o_s[e]), at<uint32_t>(w, G.off_state),
-                                              (size_t)cc * 4, hipMemcpyDeviceToDevice, st));
+                        HIPCHK(hipMemcpyAsync(at<uint32_t>(buf, B.o_s[e]), at<uint32_t>(w, G.off_state),
+                                              (size_t)cc * 4, hipMemcpyDeviceToDevice, sq));
                         have[e] = true;
                     }
                 }
-                auto Q = [&](int e) { return have[e] ? at<double>(buf, o_q[e]) : nullptr; };
-                auto S = [&](int e) { return have[e] ? at<uint32_t>(buf, o_s[e]) : nullptr; };
-                HIPCHK(launch_mimc_combine((int)cc, Q(0), Q(1), Q(2), Q(3), S(0), S(1), S(2), S(3),
-                                           at<double>(buf, o_y), at<uint32_t>(buf, o_sy), st));
-                HIPCHK(launch_pair_sums((int)cc, at<double>(buf, o_y), nullptr, at<uint32_t>(buf, o_sy), nullptr,
-                                        nullptr, nullptr, nullptr, nullptr, at<double>(buf, o_sums), st));
-                HIPCHK(hipMemcpyAsync(h, at<double>(buf, o_sums), 8 * 8, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                // chunk sums added in chunk order (fixed order)
-                sy += h[0];
-                sy2 += h[1];
-                npro += (int64_t)h[4];
-                nnc += (int64_t)h[5];
+                auto Qe = [&](int e) { return have[e] ? at<double>(buf, B.o_q[e]) : nullptr; };
+                auto Se = [&](int e) { return have[e] ? at<uint32_t>(buf, B.o_s[e]) : nullptr; };
+                HIPCHK(launch_mimc_combine((int)cc, Qe(0), Qe(1), Qe(2), Qe(3), Se(0), Se(1), Se(2), Se(3),
+                                           at<double>(buf, B.o_y), at<uint32_t>(buf, B.o_sy), sq));
+                HIPCHK(launch_pair_sums((int)cc, at<double>(buf, B.o_y), nullptr, at<uint32_t>(buf, B.o_sy), nullptr,
+                                        nullptr, nullptr, nullptr, nullptr,
+                                        at<double>(buf, o_sums) + (size_t)(sbase[i] + ch) * 8, sq));
+            }
+        }
+        for (int q = 0; q < kQueues; ++q) {
+            if (!Q[q].C) continue;
+            HIPCHK(hipEventRecord(ctx->qevents[1 + q], ctx->qstreams[q]));
+            HIPCHK(hipStreamWaitEvent(st, ctx->qevents[1 + q], 0));
+        }
+        HIPCHK(hipMemcpyAsync(h.data(), at<double>(buf, o_sums), (size_t)nsum * 8 * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < NI; ++i) {
+            // chunk sums added in chunk order (fixed order)
+            double sy = 0.0, sy2 = 0.0;
+            int64_t npro = 0, nnc = 0;
+            for (int64_t ch = 0; ch < nch[i]; ++ch) {
+                const double *hh = &h[(size_t)(sbase[i] + ch) * 8];
+                sy += hh[0];
+                sy2 += hh[1];
+                npro += (int64_t)hh[4];
+                nnc += (int64_t)hh[5];
             }
             const double N = (double)mi->N[i], mean = sy / N;
             out->mean[i] = mean;
@@ -1639,12 +1694,13 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
         return MLMC_OK;
     };
     int rc = run();
+    for (hipStream_t q : ctx->qstreams) (void)hipStreamSynchronize(q);
     (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
     out->solves = solves;
     out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return rc;
-    for (int i = 0; i < mi->n_idx; ++i)
+    for (int i = 0; i < NI; ++i)
         if (out->n_noconv[i] > 0) return fail(ctx, MLMC_ENOCONV, "mimc: index %d has %lld non-converged samples", i,
                                               (long long)out->n_noconv[i]);
     return MLMC_OK;
