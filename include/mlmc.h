@@ -24,6 +24,7 @@
  *     Work is enqueued asynchronously on it unless stated otherwise.
  *   - Return codes: MLMC_OK (0); MLMC_ENOCONV (1): the call completed but at
  *     least one sample did not reach its target (see its status bits);
+ *     MLMC_PAUSED (2): a resumable estimate stopped at its round limit;
  *     negative codes mean the call failed and outputs are undefined.  The
  *     text of the last error of a context is returned by mlmc_last_error.
  *   - One context per host thread; calls on one context are not re-entrant.
@@ -40,6 +41,7 @@ extern "C" {
 
 #define MLMC_OK 0
 #define MLMC_ENOCONV 1
+#define MLMC_PAUSED 2   /* mlmc_estimate_resumable stopped after max_rounds: resume from its state */
 #define MLMC_EINVAL (-1)  /* bad argument: null/misaligned pointer, level out of range, NaN */
 #define MLMC_ENOMEM (-2)  /* workspace smaller than mlmc_workspace_bytes */
 #define MLMC_EHIP (-3)    /* HIP runtime error (text via mlmc_last_error) */
@@ -321,6 +323,40 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
  * that round (converged = 0, n_noconv per level). */
 int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
                   mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream);
+
+/* Estimator state at a round boundary of Algorithm 4.1 (checkpoint and
+ * resume): everything the later rounds depend on.  Level l's next sample
+ * index is done[l], so a run resumed from a state draws the same samples,
+ * adds their sums in the same order and ends with the same result as an
+ * uninterrupted run. */
+typedef struct {
+    int32_t L;                 /* finest level so far (1..L_max) */
+    int32_t rounds;            /* rounds completed */
+    int64_t N[16];             /* target samples of level l (l <= L) */
+    int64_t done[16];          /* samples taken on level l: its next sample index */
+    double s1[16], s2[16];     /* sums of Y_l and Y_l^2, in chunk order */
+    int64_t n_promoted[16];    /* samples re-solved in FP64 so far */
+    int64_t n_noconv[16];      /* samples that missed their target so far */
+    double gpu_ms;             /* device time so far */
+    double tol;                /* the call's parameters, checked on resume */
+    int32_t n_init, mixed, solver;
+    int32_t dtype[16];         /* dtype_per_level (0 when NULL) */
+    uint64_t seed;             /* the context's generator seed */
+} mlmc_estimate_state;
+
+/* mlmc_estimate with a checkpoint.  resume = NULL starts afresh; otherwise
+ * the rounds continue from that state, whose parameters and seed must be
+ * this call's and this context's (MLMC_EINVAL otherwise).  max_rounds > 0
+ * stops after that many rounds of this call: the call then returns
+ * MLMC_PAUSED if the estimator had not finished.  state_out (may be NULL)
+ * receives the state after the last completed round; out holds the
+ * estimate over the levels so far (a level added in the last round counts
+ * with the samples it has).  Otherwise as mlmc_estimate, which equals this
+ * call with resume = NULL, max_rounds = 0 and state_out = NULL. */
+int mlmc_estimate_resumable(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
+                            mlmc_solver solver, int32_t mixed, const mlmc_estimate_state *resume,
+                            int32_t max_rounds, mlmc_estimate_state *state_out, mlmc_result *out,
+                            void *stream);
 
 /* Adjoint gradient dQ/dxi on grid `level` for the n samples of the
  * preceding mlmc_solve on the same workspace with the same opts (solver

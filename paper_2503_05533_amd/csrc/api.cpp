@@ -1085,7 +1085,16 @@ int mlmc_autotune(mlmc_ctx *ctx, int32_t level, int64_t n, const double *xi_dev,
 int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
                   mlmc_solver solver, int32_t mixed, mlmc_result *out, void *stream)
 {
-    if (!ctx || !out || !(tol > 0.0) || n_init < 2 || ctx->cfg.L_max < 1)
+    return mlmc_estimate_resumable(ctx, tol, n_init, dtype_per_level, solver, mixed, nullptr, 0, nullptr, out,
+                                   stream);
+}
+
+int mlmc_estimate_resumable(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *dtype_per_level,
+                            mlmc_solver solver, int32_t mixed, const mlmc_estimate_state *resume,
+                            int32_t max_rounds, mlmc_estimate_state *state_out, mlmc_result *out,
+                            void *stream)
+{
+    if (!ctx || !out || !(tol > 0.0) || n_init < 2 || ctx->cfg.L_max < 1 || ctx->cfg.L_max > 15)
         return fail(ctx, MLMC_EINVAL, "estimate: bad arguments");
     if (!dtype_per_level && solver == MLMC_DIRECT_IR)
         return fail(ctx, MLMC_EINVAL, "estimate: dtype_per_level is NULL");
@@ -1155,8 +1164,26 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     std::vector<int64_t> N = {n_init, n_init}, done = {0, 0};
     std::vector<double> s1 = {0, 0}, s2 = {0, 0};
     std::vector<double> yhat, var;
+    int32_t dts[16] = {};
+    for (int l = 0; l <= Lmax; ++l) dts[l] = dtype_per_level ? (int32_t)dtype_per_level[l] : 0;
+    int start_round = 0;
+    if (resume) {
+        const mlmc_estimate_state &R = *resume;
+        bool ok = R.L >= 1 && R.L <= Lmax && R.rounds >= 0 && R.tol == tol && R.n_init == n_init &&
+                  R.mixed == mixed && R.solver == (int32_t)solver && R.seed == c.seed;
+        for (int l = 0; l <= Lmax && ok; ++l) ok = R.dtype[l] == dts[l];
+        for (int l = 0; l <= R.L && ok; ++l)
+            ok = R.done[l] >= 0 && R.N[l] >= 0 && std::isfinite(R.s1[l]) && std::isfinite(R.s2[l]);
+        if (!ok) return fail(ctx, MLMC_EINVAL, "estimate: the resume state does not match this call or context");
+        L = R.L;
+        N.assign(R.N, R.N + L + 1);
+        done.assign(R.done, R.done + L + 1);
+        s1.assign(R.s1, R.s1 + L + 1);
+        s2.assign(R.s2, R.s2 + L + 1);
+        start_round = R.rounds;
+    }
     const double bias_c = (std::pow((double)c.m, c.alpha) - 1.0) / std::sqrt(2.0) * tol;
-    double gpu_ms = 0.0;
+    double gpu_ms = resume ? resume->gpu_ms : 0.0;
     double *hbuf = nullptr;  // pinned: 8 sums per chunk of a round
     int hcap = 0;
     int rc = MLMC_OK;
@@ -1165,8 +1192,14 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     // target; the latter, or non-finite level sums, end the call (every Y_l
     // of Algorithm 4.1 must reach its accuracy)
     int64_t n_prom[16] = {}, n_nc[16] = {};
-    bool inexact = false;
-    for (int round = 0; round < 200; ++round) {
+    if (resume)
+        for (int l = 0; l <= Lmax; ++l) {
+            n_prom[l] = resume->n_promoted[l];
+            n_nc[l] = resume->n_noconv[l];
+        }
+    bool inexact = false, paused = false;
+    int rounds = start_round;
+    for (int round = start_round; round < 200; ++round) {
         double eps[16];
         mlmc_accuracy_targets(ctx, L, eps);
         // Algorithm 4.1 adds level L + 1 (with n_init samples) when |Y_L| is
@@ -1313,23 +1346,30 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
             var[l] = std::max(s2[l] / (double)done[l] - yhat[l] * yhat[l], 0.0);
             tot += std::sqrt(var[l] * cost(l));
         }
+        rounds = round + 1;
         if (inexact) break;  // no N_l update from inexact or non-finite sums
         for (int l = 0; l <= L; ++l)
             N[l] = std::max<int64_t>(done[l], (int64_t)std::ceil(std::sqrt(var[l] / cost(l)) * 2.0 / (tol * tol) * tot));
+        bool finished = false;
         if (std::fabs(yhat[L]) > bias_c && L < Lmax) {
             ++L;
             N.push_back(n_init);
             done.push_back(next_done);
             s1.push_back(next_s1);
             s2.push_back(next_s2);
-            continue;
+        } else {
+            bool need_more = false;
+            for (int l = 0; l <= L; ++l) need_more |= N[l] > done[l];
+            if (!need_more) {
+                double v = 0.0;
+                for (int l = 0; l <= L; ++l) v += var[l] / (double)done[l];
+                converged = (std::fabs(yhat[L]) <= bias_c) && v <= tol * tol / 2.0 * (1 + 1e-12);
+                finished = true;
+            }
         }
-        bool need_more = false;
-        for (int l = 0; l <= L; ++l) need_more |= N[l] > done[l];
-        if (!need_more) {
-            double v = 0.0;
-            for (int l = 0; l <= L; ++l) v += var[l] / (double)done[l];
-            converged = (std::fabs(yhat[L]) <= bias_c) && v <= tol * tol / 2.0 * (1 + 1e-12);
+        if (finished) break;
+        if (max_rounds > 0 && rounds - start_round >= max_rounds) {
+            paused = true;
             break;
         }
     }
@@ -1339,6 +1379,38 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     (void)hipStreamSynchronize(st);
     if (hbuf) (void)hipHostFree(hbuf);
     if (rc < 0) return rc;
+    if (state_out) {
+        mlmc_estimate_state &S = *state_out;
+        memset(&S, 0, sizeof S);
+        S.L = L;
+        S.rounds = rounds;
+        for (int l = 0; l <= L; ++l) {
+            S.N[l] = N[l];
+            S.done[l] = done[l];
+            S.s1[l] = s1[l];
+            S.s2[l] = s2[l];
+        }
+        for (int l = 0; l <= Lmax; ++l) {
+            S.n_promoted[l] = n_prom[l];
+            S.n_noconv[l] = n_nc[l];
+            S.dtype[l] = dts[l];
+        }
+        S.gpu_ms = gpu_ms;
+        S.tol = tol;
+        S.n_init = n_init;
+        S.mixed = mixed;
+        S.solver = (int32_t)solver;
+        S.seed = c.seed;
+    }
+    // level means and variances from the sums (a level added in the last
+    // round counts with the samples it has)
+    yhat.assign(L + 1, 0.0);
+    var.assign(L + 1, 0.0);
+    for (int l = 0; l <= L; ++l)
+        if (done[l] > 0) {
+            yhat[l] = s1[l] / (double)done[l];
+            var[l] = std::max(s2[l] / (double)done[l] - yhat[l] * yhat[l], 0.0);
+        }
     memset(out, 0, sizeof *out);
     out->L = L;
     out->converged = converged;
@@ -1347,7 +1419,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
     mlmc_accuracy_targets(ctx, L, eps);
     for (int l = 0; l <= L; ++l) {
         est += yhat[l];
-        v += var[l] / (double)done[l];
+        v += done[l] > 0 ? var[l] / (double)done[l] : 0.0;
         out->N[l] = done[l];
         out->Yhat[l] = yhat[l];
         out->s2[l] = var[l];
@@ -1367,7 +1439,7 @@ int mlmc_estimate(mlmc_ctx *ctx, double tol, int32_t n_init, const mlmc_dtype *d
         fail(ctx, MLMC_ENOCONV, "estimate: samples missed their accuracy target or level sums are not finite");
         return MLMC_ENOCONV;
     }
-    return MLMC_OK;
+    return paused ? MLMC_PAUSED : MLMC_OK;
 }
 
 int mlmc_mcmc(mlmc_ctx *ctx, const mlmc_mcmc_config *mc, mlmc_mcmc_result *out, void *stream)

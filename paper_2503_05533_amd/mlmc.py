@@ -25,7 +25,7 @@ EXPORTS = ["mlmc_create", "mlmc_destroy", "mlmc_last_error", "mlmc_level_cells",
            "mlmc_accuracy_targets", "mlmc_get_kl_basis", "mlmc_workspace_bytes", "mlmc_fill_xi",
            "mlmc_solve", "mlmc_sample_level", "mlmc_estimate", "mlmc_grad", "mlmc_profile",
            "mlmc_profile_read", "mlmc_levels_workspace_bytes", "mlmc_sample_levels", "mlmc_autotune",
-           "mlmc_sample_level_noalloc", "mlmc_set_seed", "mlmc_mcmc", "mlmc_mimc"]
+           "mlmc_sample_level_noalloc", "mlmc_set_seed", "mlmc_mcmc", "mlmc_mimc", "mlmc_estimate_resumable"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -65,6 +65,34 @@ class _Result(ctypes.Structure):
                 ("eps", ctypes.c_double * 16), ("wall_s", ctypes.c_double),
                 ("gpu_ms", ctypes.c_double), ("n_promoted", ctypes.c_int64 * 16),
                 ("n_noconv", ctypes.c_int64 * 16)]
+
+
+class _EstimateState(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("rounds", ctypes.c_int32), ("N", ctypes.c_int64 * 16),
+                ("done", ctypes.c_int64 * 16), ("s1", ctypes.c_double * 16), ("s2", ctypes.c_double * 16),
+                ("n_promoted", ctypes.c_int64 * 16), ("n_noconv", ctypes.c_int64 * 16),
+                ("gpu_ms", ctypes.c_double), ("tol", ctypes.c_double), ("n_init", ctypes.c_int32),
+                ("mixed", ctypes.c_int32), ("solver", ctypes.c_int32), ("dtype", ctypes.c_int32 * 16),
+                ("seed", ctypes.c_uint64)]
+
+
+def _state_to_dict(st):
+    """A plain (JSON-serialisable) copy of an estimator state."""
+    d = {}
+    for name, typ in _EstimateState._fields_:
+        v = getattr(st, name)
+        d[name] = list(v) if hasattr(typ, "_length_") else v
+    return d
+
+
+def _state_from_dict(d):
+    st = _EstimateState()
+    for name, typ in _EstimateState._fields_:
+        if hasattr(typ, "_length_"):
+            getattr(st, name)[:] = list(d[name])
+        else:
+            setattr(st, name, d[name])
+    return st
 
 
 class _MCMCConfig(ctypes.Structure):
@@ -140,6 +168,9 @@ def load_library():
                                   ctypes.POINTER(i32), vp]
     lib.mlmc_mcmc.argtypes = [vp, ctypes.POINTER(_MCMCConfig), ctypes.POINTER(_MCMCResult), vp]
     lib.mlmc_mimc.argtypes = [vp, ctypes.POINTER(_MIMCConfig), ctypes.POINTER(_MIMCResult), vp]
+    lib.mlmc_estimate_resumable.argtypes = [vp, dbl, i32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, i32,
+                                            ctypes.POINTER(_EstimateState), i32, ctypes.POINTER(_EstimateState),
+                                            ctypes.POINTER(_Result), vp]
     lib.mlmc_profile.argtypes = [vp, i32]
     lib.mlmc_profile_read.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
@@ -353,19 +384,27 @@ class MLMC:
                                            _ptr(ws), ws.numel(), ch, _stream()), "autotune")
         return list(ch)
 
-    def estimate(self, tol, n_init=1000, dtypes=None, solver="direct_ir", mixed=True):
+    def estimate(self, tol, n_init=1000, dtypes=None, solver="direct_ir", mixed=True, resume=None,
+                 max_rounds=0):
+        """Algorithm 4.1 (mlmc_estimate_resumable).  resume: a state dict of an
+        earlier call (result["state"]) to continue from; max_rounds > 0 stops
+        after that many rounds (rc == 2, MLMC_PAUSED, when not finished).  The
+        returned "state" is JSON-serialisable."""
         L1 = self.cfg.L_max + 1
         dts = (ctypes.c_int * L1)(*[DTYPES[d] for d in (dtypes or ["f32"] * L1)])
         r = _Result()
-        rc = self._check(self.lib.mlmc_estimate(self.h, float(tol), int(n_init), dts, SOLVERS[solver],
-                                                1 if mixed else 0, ctypes.byref(r), _stream()),
-                         "estimate")
+        st_out = _EstimateState()
+        st_in = _state_from_dict(resume) if resume is not None else None
+        rc = self._check(self.lib.mlmc_estimate_resumable(
+            self.h, float(tol), int(n_init), dts, SOLVERS[solver], 1 if mixed else 0,
+            ctypes.byref(st_in) if st_in is not None else None, int(max_rounds), ctypes.byref(st_out),
+            ctypes.byref(r), _stream()), "estimate")
         L = r.L
         return dict(estimate=r.estimate, var_est=r.var_est, L=L, converged=bool(r.converged),
                     N=list(r.N[:L + 1]), Yhat=list(r.Yhat[:L + 1]), s2=list(r.s2[:L + 1]),
                     C=list(r.C[:L + 1]), eps=list(r.eps[:L + 1]), wall_s=r.wall_s,
                     gpu_ms=r.gpu_ms, n_promoted=list(r.n_promoted[:L1]),
-                    n_noconv=list(r.n_noconv[:L1]), rc=rc)
+                    n_noconv=list(r.n_noconv[:L1]), rc=rc, state=_state_to_dict(st_out))
 
     def mcmc(self, L, chains, steps, obs, noise_sd, burn_in=10, subsample=2, pcn_beta=0.5, opts=None,
              seed=None):

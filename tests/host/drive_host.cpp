@@ -1,7 +1,8 @@
 // Host-only driver of the C ABI against the stub runtime: the multi-level
 // step (graph and eager, FP32 refinement and FP64 direct) with the four-level
 // workload shapes, three times each, then the adaptive estimator (mixed and
-// standard), the no-allocation entry point and the multi-index driver.  Run under AddressSanitizer by tests/test_host_logic.py, once
+// standard), its checkpoint and resume, the no-allocation entry point and the
+// multi-index driver.  Run under AddressSanitizer by tests/test_host_logic.py, once
 // as is and once with the stub reporting a non-converged sample per chunk.
 #include <cstdio>
 #include <cstdlib>
@@ -50,6 +51,28 @@ int main()
             printf("estimate mixed=%d rc=%d L=%d N0=%lld noconv0=%lld conv=%d %s\n", mixed, rc, res.L,
                    (long long)res.N[0], (long long)res.n_noconv[0], res.converged, rc ? mlmc_last_error(ctx) : "");
         }
+    }
+    {
+        // checkpoint and resume: one round per call from a saved state reaches
+        // the uninterrupted run's levels, sample counts and estimate
+        mlmc_dtype dts[4] = {MLMC_F32, MLMC_F32, MLMC_F32, MLMC_F32};
+        mlmc_result full, part;
+        rc = mlmc_estimate(ctx, 2e-5, 1000, dts, MLMC_DIRECT_IR, 1, &full, nullptr);
+        mlmc_estimate_state sa, sb;
+        int calls = 0;
+        rc = mlmc_estimate_resumable(ctx, 2e-5, 1000, dts, MLMC_DIRECT_IR, 1, nullptr, 1, &sa, &part, nullptr);
+        ++calls;
+        while (rc == MLMC_PAUSED && calls < 100) {
+            sb = sa;
+            rc = mlmc_estimate_resumable(ctx, 2e-5, 1000, dts, MLMC_DIRECT_IR, 1, &sb, 1, &sa, &part, nullptr);
+            ++calls;
+        }
+        bool same = part.L == full.L && part.estimate == full.estimate && part.converged == full.converged;
+        for (int l = 0; l <= full.L; ++l) same = same && part.N[l] == full.N[l];
+        printf("resume rc=%d calls=%d rounds=%d same=%d\n", rc, calls, sa.rounds, (int)same);
+        // a state from another tolerance is refused
+        rc = mlmc_estimate_resumable(ctx, 1e-5, 1000, dts, MLMC_DIRECT_IR, 1, &sb, 1, &sa, &part, nullptr);
+        printf("resume mismatch rc=%d\n", rc);
     }
     {
         // the no-allocation entry point: a level that fits the scratch, then one that does not

@@ -48,7 +48,8 @@ def test_binding_refuses_without_gpu():
 
 STRUCTS = [("_Config", "mlmc_config"), ("_LevelOpts", "mlmc_level_opts"), ("_LevelStats", "mlmc_level_stats"),
            ("_Result", "mlmc_result"), ("_MCMCConfig", "mlmc_mcmc_config"), ("_MCMCResult", "mlmc_mcmc_result"),
-           ("_MIMCConfig", "mlmc_mimc_config"), ("_MIMCResult", "mlmc_mimc_result")]
+           ("_MIMCConfig", "mlmc_mimc_config"), ("_MIMCResult", "mlmc_mimc_result"),
+           ("_EstimateState", "mlmc_estimate_state")]
 
 
 def test_binding_structs_match_the_header(tmp_path):

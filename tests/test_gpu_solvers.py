@@ -210,6 +210,35 @@ def test_estimate_mixed_matches_fp64(case):
     ctx.close()
 
 
+@pytest.mark.parametrize("case", EST_CASES, ids=["n0_4", "n0_16"])
+def test_estimate_checkpoint_resume(case):
+    """Checkpoint and resume of Algorithm 4.1: stopping after every round and
+    continuing from the saved state (through JSON, as a restarted process
+    would) gives the uninterrupted run's L, sample counts and estimate bit for
+    bit; a state of another tolerance is refused."""
+    import json
+    from paper_2503_05533_amd import MLMCError
+    _torch()
+    n0, L_max, K, s2, lam, seed, tol, n_init = case
+    ctx = _ctx(n0=n0, L_max=L_max, K=K, sigma2=s2, corr_len=lam, seed=seed + 2)
+    dts = ["f32"] * (L_max + 1)
+    full = ctx.estimate(tol, n_init=n_init, dtypes=dts, solver="direct_ir", mixed=True)
+    r = ctx.estimate(tol, n_init=n_init, dtypes=dts, solver="direct_ir", mixed=True, max_rounds=1)
+    calls = 1
+    while r["rc"] == 2:
+        state = json.loads(json.dumps(r["state"]))
+        r = ctx.estimate(tol, n_init=n_init, dtypes=dts, solver="direct_ir", mixed=True, resume=state, max_rounds=1)
+        calls += 1
+        assert calls < 100
+    _say("full", full["L"], full["N"], full["estimate"], "resumed", r["L"], r["N"], r["estimate"], "calls", calls)
+    assert calls >= 3
+    assert r["rc"] == 0 and r["L"] == full["L"] and r["N"] == full["N"]
+    assert r["estimate"] == full["estimate"] and r["converged"] == full["converged"]
+    with pytest.raises(MLMCError):
+        ctx.estimate(2 * tol, n_init=n_init, dtypes=dts, solver="direct_ir", mixed=True, resume=state)
+    ctx.close()
+
+
 # ----------------------------------------------------------------- multigrid-preconditioned CG
 
 @pytest.mark.parametrize("disc", [0, 1])

@@ -1,7 +1,9 @@
-"""Host logic of the library without a GPU: the C-ABI entry points that
-schedule work (multi-level step in both schedules, the adaptive estimator
-with its per-level streams and early start of a due level) built with g++
-under AddressSanitizer against a stub HIP runtime (tests/host/)."""
+"""Host logic without a GPU: the library's C-ABI entry points that schedule
+work (multi-level step in both schedules, the adaptive estimator with its
+per-level streams, early start of a due level and checkpoint/resume, the
+no-allocation entry point, the multi-index driver) built with g++ under
+AddressSanitizer against a stub HIP runtime (tests/host/), and the oracle
+under AddressSanitizer and UndefinedBehaviorSanitizer."""
 import os
 import shutil
 import subprocess
@@ -42,6 +44,11 @@ def test_host_scheduling_under_asan(tmp_path):
     assert noalloc == ["noalloc n=64 rc=0", "noalloc n=200000 rc=-2"], r.stdout
     est = [l for l in lines if l.startswith("estimate")]
     assert len(est) == 2 and all(" rc=0 " in l and " L=3 " in l and " noconv0=0 " in l for l in est), r.stdout
+    # checkpoint/resume: one round per call reaches the uninterrupted result
+    res = [l for l in lines if l.startswith("resume")]
+    assert len(res) == 2 and res[0].startswith("resume rc=0 ") and res[0].endswith(" same=1"), r.stdout
+    assert int(res[0].split("calls=")[1].split()[0]) >= 2, r.stdout
+    assert res[1] == "resume mismatch rc=-1", r.stdout
     # multi-index driver: one solve per (grid, truncation) term and chunk:
     # (0,0) 1 term, (1,1) 4 terms, (3,0) 2 terms in two chunks (its 300
     # samples need ~17.5 MB each, the FP32 factor and an FP64 promotion slot
@@ -61,3 +68,19 @@ def test_host_scheduling_under_asan(tmp_path):
         assert int(l.split("noconv0=")[1].split()[0]) >= 1, l
     mimc = [l for l in r.stdout.splitlines() if l.startswith("mimc rc=")]
     assert mimc == ["mimc rc=1 solves=9 noconv0=1"], r.stdout
+
+
+def test_oracle_under_asan_ubsan(tmp_path):
+    """Every oracle entry point (both edge rules, grids 4-16, OpenMP on two
+    threads) under AddressSanitizer (with leak detection) and
+    UndefinedBehaviorSanitizer, any report fatal."""
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    exe = str(tmp_path / "drive_oracle")
+    subprocess.run(["gcc", "-std=c99", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-fopenmp", os.path.join(ROOT, "oracle", "oracle.c"), os.path.join(HOST, "drive_oracle.c"),
+                    "-lm", "-o", exe], check=True, capture_output=True, timeout=300)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert r.stdout.startswith("oracle ok=1 threads=2 "), r.stdout
