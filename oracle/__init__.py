@@ -16,6 +16,10 @@ Functions and the passage each follows:
   solve_batch              -- exact discrete solution, Q = integral of u
                               (sec. 5.1 QoI)
   ir_f32_batch             -- Algorithm 2.1 with (u_f,u_s,u,u_r) = (s,s,d,d)
+  ir_lowp_batch            -- the same with the factor and substitutions of
+                              the scaled system simulated in FP16, BF16 or
+                              FP32 (every operation rounded, Sec. 2.1's
+                              simulated low precision)
   grad_batch               -- adjoint dQ/dxi (not in the paper; exact
                               derivative of the discrete Q)
   accuracy_targets         -- delta_l of sec. 4.5 (sqrt(k_p) h_l^2, k_p h_L^2)
@@ -57,8 +61,9 @@ def build(force=True):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=False)
+        src = os.path.join(_HERE, "oracle.c")
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(src) > os.path.getmtime(_LIB_PATH):
+            build(force=True)
         lib = ctypes.CDLL(_LIB_PATH)
         D = ctypes.POINTER(ctypes.c_double)
         I = ctypes.POINTER(ctypes.c_int)
@@ -74,6 +79,10 @@ def _load():
         lib.oracle_relres_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, D, D]
         lib.oracle_ir_f32_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, c_double, c_int,
                                             D, I, D]
+        lib.oracle_ir_lowp_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, c_double, c_int, c_int,
+                                             D, I, D]
+        lib.oracle_round_lowp.argtypes = [c_double, c_int]
+        lib.oracle_round_lowp.restype = c_double
         lib.oracle_grad_batch.argtypes = [c_int, c_int, D, c_int, D, c_double, D, D, D]
         lib.oracle_energy.argtypes = [c_int, c_int, D, D, D]
         lib.oracle_energy.restype = c_double
@@ -194,6 +203,30 @@ def ir_f32_batch(n, Phi, xi, delta, imax=10, f=1.0):
     rr = np.zeros(S)
     nf = _load().oracle_ir_f32_batch(n, Phi.shape[1], _p(_f64(Phi)), S, _p(xi), f, delta, imax,
                                      _p(Q), _pi(trips), _p(rr))
+    return Q, trips, rr, nf
+
+
+LOWP_FORMATS = {"f16": 0, "bf16": 1, "f32": 2}
+
+
+def round_lowp(v, fmt):
+    """v rounded to "f16", "bf16" or "f32" (nearest, ties to even) as the
+    simulated low precision rounds every result."""
+    return _load().oracle_round_lowp(float(v), LOWP_FORMATS[fmt])
+
+
+def ir_lowp_batch(n, Phi, xi, delta, fmt, imax=10, f=1.0):
+    """Algorithm 2.1 with the factorisation and substitutions of the scaled
+    system simulated in a low precision (every operation rounded: "f16",
+    "bf16" or "f32"), residual and update in FP64; returns (Q, trips, relres,
+    n_fail), trips -1 for a factorisation that broke down."""
+    xi = _f64(np.atleast_2d(xi))
+    S = xi.shape[0]
+    Q = np.zeros(S)
+    trips = np.zeros(S, dtype=np.int32)
+    rr = np.zeros(S)
+    nf = _load().oracle_ir_lowp_batch(n, Phi.shape[1], _p(_f64(Phi)), S, _p(xi), f, delta, imax,
+                                      LOWP_FORMATS[fmt], _p(Q), _pi(trips), _p(rr))
     return Q, trips, rr, nf
 
 

@@ -465,6 +465,144 @@ int oracle_ir_f32_batch(int n, int K, const double *Phi, int S, const double *xi
 }
 
 /*
+ * Rounding to a binary floating-point format with p significand bits,
+ * minimum normal exponent emin and largest finite value vmax, to nearest
+ * with ties to even (the default rounding mode of nearbyint): every value is
+ * a multiple of its binade's spacing 2^(e - p + 1), subnormals of 2^(emin -
+ * p + 1); beyond vmax the result is infinite.  FP16: p = 11, emin = -14,
+ * vmax = 65504; BF16: p = 8, emin = -126.
+ */
+static double round_fmt(double v, int p, int emin, double vmax)
+{
+    if (v == 0.0 || !isfinite(v)) return v;
+    int e;
+    frexp(v, &e);
+    int ex = e - 1 < emin ? emin : e - 1;
+    double q = ldexp(1.0, ex - (p - 1));
+    double r = nearbyint(v / q) * q;
+    return fabs(r) > vmax ? copysign(INFINITY, v) : r;
+}
+
+typedef struct { int p, emin; double vmax; } lowp_fmt;
+static const lowp_fmt LOWP_FMTS[3] = {{11, -14, 65504.0}, {8, -126, 3.3895313892515355e38},
+                                      {24, -126, 3.4028234663852886e38}};
+static double rnd(const lowp_fmt *f, double v) { return round_fmt(v, f->p, f->emin, f->vmax); }
+
+/* v rounded to format fmt (0 FP16, 1 BF16, 2 FP32), for the tests. */
+double oracle_round_lowp(double v, int fmt)
+{
+    return fmt >= 0 && fmt <= 2 ? rnd(&LOWP_FMTS[fmt], v) : NAN;
+}
+
+/* Band Cholesky-Crout and the two substitutions with every operation's
+ * result rounded to the format (products, differences, square roots and
+ * quotients separately: no fused operations), the simulation of a factor
+ * computed in that precision. */
+static int band_cholesky_lowp(const lowp_fmt *f, int N, int bw, double *Ab)
+{
+#define L_(i, j) Ab[(size_t)(i) * (bw + 1) + ((i) - (j))]
+    for (int j = 0; j < N; ++j) {
+        int k0 = j - bw > 0 ? j - bw : 0;
+        double s = L_(j, j);
+        for (int k = k0; k < j; ++k) s = rnd(f, s - rnd(f, L_(j, k) * L_(j, k)));
+        if (!(s > 0.0) || !isfinite(s)) return -1;
+        double ljj = rnd(f, sqrt(s));
+        L_(j, j) = ljj;
+        int iend = j + bw < N - 1 ? j + bw : N - 1;
+        for (int i = j + 1; i <= iend; ++i) {
+            int ki = i - bw > 0 ? i - bw : 0;
+            double t = L_(i, j);
+            for (int k = ki; k < j; ++k) t = rnd(f, t - rnd(f, L_(i, k) * L_(j, k)));
+            L_(i, j) = rnd(f, t / ljj);
+        }
+    }
+    return 0;
+#undef L_
+}
+
+static void band_solve_lowp(const lowp_fmt *f, int N, int bw, const double *Lb, double *x)
+{
+    for (int i = 0; i < N; ++i) {
+        int k0 = i - bw > 0 ? i - bw : 0;
+        double s = x[i];
+        for (int k = k0; k < i; ++k) s = rnd(f, s - rnd(f, Lb[(size_t)i * (bw + 1) + (i - k)] * x[k]));
+        x[i] = rnd(f, s / Lb[(size_t)i * (bw + 1)]);
+    }
+    for (int i = N - 1; i >= 0; --i) {
+        int k1 = i + bw < N - 1 ? i + bw : N - 1;
+        double s = x[i];
+        for (int k = i + 1; k <= k1; ++k) s = rnd(f, s - rnd(f, Lb[(size_t)k * (bw + 1) + (k - i)] * x[k]));
+        x[i] = rnd(f, s / Lb[(size_t)i * (bw + 1)]);
+    }
+}
+
+/*
+ * Algorithm 2.1 with (u_f, u_s, u, u_r) = (x, x, d, d) for a low precision
+ * x simulated by rounding every operation (fmt 0: FP16, 1: BF16, 2: FP32):
+ * the system is scaled symmetrically to unit diagonal (S A S, S =
+ * diag(A)^(-1/2), the scaling the paper recommends against overflow in low
+ * precision), stored and factorised in x; x0 = S (SAS)^(-1) S b by
+ * substitution in x; then residual in double, stop when ||r||/||b|| < delta
+ * (strict), correction t = S (SAS)^(-1) S r in x, update in double.  At most
+ * imax corrections.  trips[s] = corrections applied, or -1 when the
+ * factorisation broke down (a pivot not positive or not finite).  Returns the
+ * number of samples that did not reach delta.
+ */
+int oracle_ir_lowp_batch(int n, int K, const double *Phi, int S, const double *xi, double fconst, double delta,
+                         int imax, int fmt, double *Q, int *trips, double *relres)
+{
+    if (fmt < 0 || fmt > 2) return -1;
+    const lowp_fmt *f = &LOWP_FMTS[fmt];
+    int m = n - 1, N = m * m, bw = m, np = (n + 1) * (n + 1);
+    double h = 1.0 / n;
+    int nfail = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfail)
+    for (int s = 0; s < S; ++s) {
+        double *a = (double *)malloc(sizeof(double) * np);
+        double *aE = (double *)malloc(sizeof(double) * (n + 1) * n);
+        double *aN = (double *)malloc(sizeof(double) * (n + 1) * n);
+        double *Ab = (double *)malloc(sizeof(double) * (size_t)N * (bw + 1));
+        double *b = (double *)malloc(sizeof(double) * N);
+        double *x = (double *)malloc(sizeof(double) * N);
+        double *r = (double *)malloc(sizeof(double) * N);
+        double *t = (double *)malloc(sizeof(double) * N);
+        double *sc = (double *)malloc(sizeof(double) * N);
+        build_system(n, K, Phi, xi + (size_t)s * K, NULL, fconst, NULL, a, aE, aN, Ab, b);
+        for (int P = 0; P < N; ++P) sc[P] = 1.0 / sqrt(Ab[(size_t)P * (bw + 1)]);
+        for (int P = 0; P < N; ++P)
+            for (int d = 0; d <= bw && d <= P; ++d)
+                Ab[(size_t)P * (bw + 1) + d] = rnd(f, sc[P] * Ab[(size_t)P * (bw + 1) + d] * sc[P - d]);
+        int it = 0;
+        double rr = INFINITY;
+        int broke = band_cholesky_lowp(f, N, bw, Ab) != 0;
+        if (!broke) {
+            for (int P = 0; P < N; ++P) t[P] = rnd(f, sc[P] * b[P]);
+            band_solve_lowp(f, N, bw, Ab, t);
+            for (int P = 0; P < N; ++P) x[P] = sc[P] * t[P];
+            double nb = norm2(N, b);
+            for (;;) {
+                stencil_apply(n, aE, aN, x, r);
+                for (int P = 0; P < N; ++P) r[P] = b[P] - r[P];
+                rr = norm2(N, r) / nb;
+                if (rr < delta || it >= imax || !isfinite(rr)) break;
+                for (int P = 0; P < N; ++P) t[P] = rnd(f, sc[P] * r[P]);
+                band_solve_lowp(f, N, bw, Ab, t);
+                for (int P = 0; P < N; ++P) x[P] += sc[P] * t[P];
+                ++it;
+            }
+        }
+        double q = 0.0;
+        for (int P = 0; P < N; ++P) q += broke ? 0.0 : x[P];
+        Q[s] = h * h * q;
+        trips[s] = broke ? -1 : it;
+        relres[s] = rr;
+        if (!(rr < delta)) nfail += 1;
+        free(a); free(aE); free(aN); free(Ab); free(b); free(x); free(r); free(t); free(sc);
+    }
+    return nfail;
+}
+
+/*
  * Adjoint gradient of Q = h^2 sum u with respect to xi (FP64).
  * Solves A lambda = w with w = h^2 * 1 (the gradient of Q in u), then
  * dQ/dZ_e = -sum over edges (e,o) of (lambda_e - lambda_o)(u_e - u_o)

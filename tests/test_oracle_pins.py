@@ -695,3 +695,43 @@ def test_mimc_toy_expectation():
     assert abs(r["estimate"] - exact) <= 5 * se, (r["estimate"], exact, se)
     v = dict(zip(idx, r["var"]))
     assert v[(2, 2)] < v[(1, 1)] < v[(0, 0)]
+
+
+def test_lowp_rounding_matches_ieee_conversions():
+    """The simulated low precisions round like IEEE conversions: FP16 as
+    numpy's float16 cast (ties to even, subnormals, overflow to inf), FP32 as
+    the float32 cast, BF16 as round-to-nearest-even of a float32's upper 16
+    bits (for values exact in FP32)."""
+    rng = np.random.default_rng(5)
+    vals = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-9, 6, 2000),
+                           [1 + 2 ** -11, 1 + 3 * 2 ** -11, 65504.0, 65519.0, 65520.0, 2 ** -24, 3 * 2 ** -26,
+                            -2 ** -25, 0.0, -7.25]])
+    with np.errstate(over="ignore"):
+        for v in vals:
+            assert oracle.round_lowp(v, "f16") == float(np.float16(v)), v
+            assert oracle.round_lowp(v, "f32") == float(np.float32(v)), v
+    for v in rng.standard_normal(2000).astype(np.float32) * np.float32(1000.0):
+        b = np.array([v], dtype=np.float32).view(np.uint32)[0]
+        r = (int(b) + 0x7FFF + ((int(b) >> 16) & 1)) >> 16 << 16
+        ref = float(np.array([r & 0xFFFFFFFF], dtype=np.uint32).view(np.float32)[0])
+        assert oracle.round_lowp(float(v), "bf16") == ref, v
+
+
+def test_lowp_refinement_follows_the_convergence_condition():
+    """Algorithm 2.1 with the factor simulated in a low precision: in FP32 the
+    16-cell systems need no correction and the 64-cell ones converge; in FP16
+    each 16-cell sample needs at least one correction and converges (u_f
+    kappa < 1), and every converged Q is within its residual bound of the
+    exact solve."""
+    K = 64
+    for n, delta in ((16, 8.7e-4), (64, 5.5e-5)):
+        phi = oracle.kl_basis(n, K, 1.0, 0.3)
+        xi = si.splitmix64_normals(11, 0, 0, 8, K)
+        Qd = oracle.solve_batch(n, phi, xi)
+        Q, tr, rr, nf = oracle.ir_lowp_batch(n, phi, xi, delta, "f32")
+        assert nf == 0 and (n > 16 or tr.max() == 0)
+        assert np.all(np.abs(Q - Qd) / Qd <= 4 * rr)
+        if n == 16:
+            Q, tr, rr, nf = oracle.ir_lowp_batch(n, phi, xi, delta, "f16")
+            assert nf == 0 and tr.min() >= 1
+            assert np.all(np.abs(Q - Qd) / Qd <= 4 * rr)
