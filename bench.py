@@ -757,7 +757,9 @@ def main():
         ms64 = timed(plan_d, a.steps, a.warmup)
         log("fp64 %.3f ms/step" % ms64)
         fp64 = dict(ms_per_step=ms64, samples_per_s=total / (ms64 / 1e3),
-                    per_level_samples_per_s=None if a.no_per_level else per_level(o64))
+                    per_level_samples_per_s=None if a.no_per_level else per_level(o64),
+                    path="FP64 direct solves with the same block LDL^T (explicit inverse Schur "
+                         "complements) kernels in FP64, no refinement; same schedule")
         del plan_d
 
     # ---- time to RMSE: Algorithm 4.1 at an absolute tolerance, R seeds
