@@ -16,6 +16,10 @@
 
 namespace mlmc {
 
+#ifndef TWISTED_ON
+#define TWISTED_ON 1
+#endif
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 // Four consecutive stored entries, accessed as one vector load or store.
@@ -72,6 +76,19 @@ template <> __device__ constexpr int drow<double>(int lr, int r) { return 4 * r 
 // Waves per sample and block slots per wave for block size M with G waves
 // per row pair; a single block row (M = 16) is one wave with one block.
 template <int M, int G> constexpr int blk_waves() { return M >= 32 ? G * (M / 16) / 2 : 1; }
+
+// Twisted (both-ends) elimination of the block layout: the block rows
+// 0 .. k-1 are eliminated top-down and m-1 .. k+1 bottom-up (m = M - 1 is odd,
+// k = (m - 1) / 2), each by a group of waves of one workgroup, and the middle
+// block row k last; the stored block of row j is the inverse Schur
+// complement of its chain (-C_j^{-1} above k, -D_j^{-1} below k) and of the
+// middle, -E_k^{-1}.  Used where the two groups' LDS still lets two
+// workgroups share a CU: the FP32-arithmetic factors up to M = 128, FP64 at
+// M = 64 (Tac: the arithmetic type).
+template <typename Tac, int M> constexpr bool twisted()
+{
+    return TWISTED_ON && M >= 32 && (sizeof(Tac) == 4 ? M <= 128 : M == 64);
+}
 template <int M, int G> constexpr int blk_slots() { return M >= 32 ? (M / 16 + G) / G : 1; }
 
 // Block ownership: the NB block rows are paired (p, NB-1-p), which together

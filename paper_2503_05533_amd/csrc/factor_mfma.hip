@@ -18,6 +18,15 @@
 // row), each in the MFMA result layout: entry (row drow(l/16, r), col l%16) of
 // block b at offset (b*64 + l)*4 + r, so that a lane's four entries of a block
 // are one contiguous vector access.
+//
+// Where twisted<Tac, M>() holds (blk_common.h) the workgroup has two wave
+// groups: the first forms C_0 .. C_{k-1} from the top, the second
+// D_{m-1} .. D_{k+1} from the bottom (D_{m-1} = T_{m-1},
+// D_j = T_j - B_{j+1} D_{j+1}^{-1} B_{j+1}), both at once, and the middle
+// block E_k = T_k - B_k C_{k-1}^{-1} B_k - B_{k+1} D_{k+1}^{-1} B_{k+1} is
+// summed from the two groups' registers and inverted by the first.  Block row
+// j of the stored factor holds -C_j^{-1}, -E_k^{-1} or -D_j^{-1}; the solve
+// (refine_blk.hip) runs the matching sweeps.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,9 +48,14 @@ template <typename Tac, int M> constexpr bool factor_fwd_ok() { return sizeof(Ta
 // H16: for the FP16/BF16 factors, form the products in the storage format
 // (one 16x16x16 MFMA per block product); false: four FP32 16x16x4 products
 // (the autotuner chooses per grid, as the faster factorisation can cost more
-// corrections).
+// corrections).  Where twisted<Tac, M>() holds, two wave groups eliminate
+// from both ends (blk_common.h): the chain of one sample is half as long.
+template <typename Tst, int M> constexpr int factor_groups()
+{
+    return twisted<typename store_traits<Tst>::acc, M>() ? 2 : 1;
+}
 template <typename Tst, int M, bool H16 = true>
-__global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S, const double *__restrict__ beta,
+__global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>())) void k_factor_mfma(int S, const double *__restrict__ beta,
                                                              const double *__restrict__ gam,
                                                              Tst *__restrict__ factor,
                                                              const int *__restrict__ idx,
@@ -56,27 +70,44 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
     constexpr int NB = M / 16, NBL = NB * (NB + 1) / 2, W = blk_waves<M, 1>(), SPW = blk_slots<M, 1>();
     constexpr int m = M - 1, LD = 17, NT = 64 * W;
     constexpr bool FWD = factor_fwd_ok<Tac, M>();
-    __shared__ Tac Vb[2][M * LD];      // panel columns C[:, K], double-buffered
-    __shared__ Tac Pw[W][16 * LD];     // per wave: -P^{-1}
-    __shared__ Tac Uw[W][2][16 * LD];  // per wave: U of its two block rows
-    __shared__ Tac bj[2][M], gj[2][M];
+    constexpr bool TW = twisted<Tac, M>();
+    constexpr int NG = TW ? 2 : 1, KM = (m - 1) / 2, STEPS = TW ? KM + 1 : m;
+    // per wave group (the twisted elimination's two chains; one group otherwise)
+    __shared__ Tac Vb_[NG][2][M * LD];      // panel columns C[:, K], double-buffered
+    __shared__ Tac Pw_[NG][W][16 * LD];     // per wave: -P^{-1}
+    __shared__ Tac Uw_[NG][W][2][16 * LD];  // per wave: U of its two block rows
+    __shared__ Tac bj_[NG][2][M], gj_[NG][2][M];
     // forward sweep (fz != NULL): right-hand side of the block, and per wave
     // its row sums and column partials, each in its own slot (fixed-order sum)
-    __shared__ Tac gfw[FWD ? M : 1];
-    __shared__ Tac partR[FWD ? W : 1][FWD ? M : 1];
-    __shared__ Tac partC[FWD ? W : 1][2][FWD ? M : 1];
+    __shared__ Tac gfw_[NG][FWD ? M : 1];
+    __shared__ Tac partR_[NG][FWD ? W : 1][FWD ? M : 1];
+    __shared__ Tac partC_[NG][FWD ? W : 1][2][FWD ? M : 1];
     __shared__ int bad;
     const int b = blockIdx.x;
     if (count && b >= *count) return;
     const int s = idx ? idx[b] : b;
     const int64_t slot = slot_base + b;
-    const int t = threadIdx.x, l = t & 63;
+    // group 0 walks the block rows from the top, group 1 (twisted) from the
+    // bottom: chain step j is row rowof(j), coupled to the previous step's row
+    // by the beta stored at row brow(j) (j >= 1)
+    const int grp = TW ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT) : 0;
+    auto &Vb = Vb_[grp];
+    auto &Pw = Pw_[grp];
+    auto &Uw = Uw_[grp];
+    auto &bj = bj_[grp];
+    auto &gj = gj_[grp];
+    auto &gfw = gfw_[grp];
+    auto &partR = partR_[grp];
+    auto &partC = partC_[grp];
+    auto rowof = [&](int jj) { return grp ? m - 1 - jj : jj; };
+    auto brow = [&](int jj) { return grp ? m - jj : jj; };
+    const int t = (int)threadIdx.x - grp * NT, l = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lr = l >> 4, lc = l & 15;
     const double *bs = beta + (size_t)s * m * M;
     const double *gs = gam + (size_t)s * m * M;
     Tst *fs = factor + (size_t)slot * m * NBL * 256;
-    if (t == 0) bad = 0;
+    if (threadIdx.x == 0) bad = 0;
     const bool fwd = FWD && fz != nullptr;
     const double *fscs = fwd ? fsc + (size_t)s * m * M : nullptr;
     double *fzs = fwd ? fz + (size_t)s * m * M : nullptr;
@@ -94,19 +125,24 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
     // coefficients of block 0 now, of block j+1 prefetched during block j
     double pb = 0.0, pg = 0.0;
     if (t < M) {
-        pb = bs[t];
-        pg = gs[t];
+        pb = grp ? 0.0 : bs[t];
+        pg = gs[rowof(0) * M + t];
     }
-    bool okw = true;
+    bool okw = true, okc = true;
 
-    for (int j = 0; j < m; ++j) {
-        const int jb = j & 1;
+    for (int j = 0; j < STEPS; ++j) {
+        const int jb = j & 1, row = rowof(j);
+        // the middle block row (twisted): the top group forms T + B F B, the
+        // bottom group B G B, their sum is E_k; only the top group's result
+        // (and flags) count
+        const bool mid = TW && j == KM, skipT = mid && grp == 1;
+        if (mid) okc = okw;
         if (t < M) {
             bj[jb][t] = (Tac)pb;
             gj[jb][t] = (Tac)pg;
-            if (j + 1 < m) {
-                pb = bs[(j + 1) * M + t];
-                pg = gs[(j + 1) * M + t];
+            if (j + 1 < STEPS) {
+                pb = bs[brow(j + 1) * M + t];
+                pg = gs[rowof(j + 1) * M + t];
             }
         }
         __syncthreads();
@@ -126,9 +162,34 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                 Tac tv = (R == C + 1) ? gc : (Tac)0;
                 tv = (C == R + 1) ? gr : tv;
                 tv = (R == C) ? (Tac)1 : tv;
-                acc[q][r] = bj[jb][R] * acc[q][r] * bc + tv;
+                acc[q][r] = bj[jb][R] * acc[q][r] * bc + (skipT ? (Tac)0 : tv);
             }
             __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (TW) {
+            if (mid) {
+                // E_k = (T + B F B) + (B G B), passed four slots per wave at a
+                // time through the bottom group's panel buffer (idle until its
+                // panel loop); both groups then run the panel loop, the bottom
+                // one on its own part (its results are not used)
+                Tac *XB = &Vb_[1][0][0];
+                static_assert(4 * W * 256 <= 2 * M * LD, "exchange buffer");
+#pragma unroll
+                for (int q0 = 0; q0 < SPW; q0 += 4) {
+                    if (grp == 1)
+#pragma unroll
+                        for (int q = q0; q < q0 + 4 && q < SPW; ++q)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) XB[(w * 4 + (q - q0)) * 256 + l * 4 + r] = acc[q][r];
+                    __syncthreads();
+                    if (grp == 0)
+#pragma unroll
+                        for (int q = q0; q < q0 + 4 && q < SPW; ++q)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) acc[q][r] += XB[(w * 4 + (q - q0)) * 256 + l * 4 + r];
+                    __syncthreads();
+                }
+            }
         }
         for (int K = 0; K < NB; ++K) {
             int wk = w;
@@ -239,7 +300,8 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
         }
         // store -C_j^{-1}
         asm volatile("" : "+s"(wj));
-        Tst *fb = fs + (size_t)j * NBL * 256;
+        Tst *fb = fs + (size_t)row * NBL * 256;
+        const bool keep = !(mid && grp == 1);
 #pragma unroll
         for (int q = 0; q < SPW; ++q) {
             int I, J;
@@ -248,7 +310,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
             quad<Tst> qv;
 #pragma unroll
             for (int r = 0; r < 4; ++r) qv.v[r] = store_traits<Tst>::store(acc[q][r]);
-            *(quad<Tst> *)(fb + ((size_t)bb * 64 + l) * 4) = qv;
+            if (keep) *(quad<Tst> *)(fb + ((size_t)bb * 64 + l) * 4) = qv;
             __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (FWD) {
@@ -258,10 +320,19 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
                 // reduced across 16-lane rows, transposed contributions of the
                 // off-diagonal tiles across the four lane rows
                 if (t < M) {
-                    const Tac gv = (Tac)(fscs[j * M + t] * (t < m ? frhs : 0.0));
-                    gfw[t] = j > 0 ? gv - (Tac)bs[j * M + t] * zc : gv;
+                    const Tac gv = (Tac)(fscs[row * M + t] * (t < m ? frhs : 0.0));
+                    // the bottom group's part of the middle row: -beta_{k+1} w_{k+1}
+                    gfw[t] = skipT ? -(Tac)bs[brow(j) * M + t] * zc
+                                   : (j > 0 ? gv - (Tac)bs[brow(j) * M + t] * zc : gv);
                 }
                 __syncthreads();
+                if constexpr (TW) {
+                    if (mid) {
+                        // g_k - beta_k z_{k-1} - beta_{k+1} w_{k+1}
+                        if (grp == 0 && t < M) gfw[t] += gfw_[1][t];
+                        __syncthreads();
+                    }
+                }
                 asm volatile("" : "+s"(wj));
                 Tac ra0[4] = {0, 0, 0, 0}, ra1[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -303,14 +374,15 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>())) void k_factor_mfma(int S,
 #pragma unroll
                     for (int ww = 0; ww < W; ++ww) v += partR[ww][t] + partC[ww][0][t] + partC[ww][1][t];
                     zc = -v;
-                    fzs[j * M + t] = (double)zc;
+                    if (keep) fzs[row * M + t] = (double)zc;
                 }
             }
         }
     }
+    if (TW && grp == 1) okw = okc;
     if (!okw) bad = 1;
     __syncthreads();
-    if (t == 0 && bad) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
+    if (threadIdx.x == 0 && bad) atomicOr(&state[s], ST_NONFINITE | ST_BREAKDOWN);
 }
 
 // Factorisation of one sample per 16 lanes, 16 samples per workgroup: the
@@ -573,12 +645,14 @@ hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *g
         else
             hipLaunchKernelGGL((k_factor_rows16<Tst, false, 0>), gr, dim3(256), 0, st, nb, a, sc, beta,
                                (Tst *)factor, idx, count, slot_base, state, frhs, fz, x0);
-    } else if (variant == 1 && mfma_in_storage<Tst>()) {
-        hipLaunchKernelGGL((k_factor_mfma<Tst, M, false>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta,
-                           gam, (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
     } else {
-        hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), dim3(64 * blk_waves<M, 1>()), 0, st, nb, beta, gam,
-                           (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
+        const dim3 block(64 * blk_waves<M, 1>() * factor_groups<Tst, M>());
+        if (variant == 1 && mfma_in_storage<Tst>())
+            hipLaunchKernelGGL((k_factor_mfma<Tst, M, false>), dim3(nb), block, 0, st, nb, beta, gam,
+                               (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
+        else
+            hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), block, 0, st, nb, beta, gam, (Tst *)factor, idx,
+                               count, slot_base, state, sc, frhs, fz);
     }
     return hipGetLastError();
 }

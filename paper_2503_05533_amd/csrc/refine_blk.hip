@@ -231,6 +231,161 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ir_rows_wav
 
 // ------------------------------------------------------------------ block solve
 
+// The solve with the twisted factor (blk_common.h): with k = (m - 1) / 2,
+// F_j = -C_j^{-1} (j < k), -D_j^{-1} (j > k) and -E_k^{-1}, the forward
+// sweeps of both chains and the middle,
+//   z_j = -F_j (g_j - beta_j z_{j-1})          j = 0 .. k-1
+//   w_j = -F_j (g_j - beta_{j+1} w_{j+1})      j = m-1 .. k+1
+//   x_k = -F_k (g_k - beta_k z_{k-1} - beta_{k+1} w_{k+1}),
+// then the back sweeps outwards from the middle,
+//   x_j = z_j + F_j beta_{j+1} x_{j+1}         j = k-1 .. 0
+//   x_j = w_j + F_j beta_j x_{j-1}             j = k+1 .. m-1,
+// one block after the other (2m - 1 steps, as the one-sided solve).  zs
+// keeps z, x_k and w at their block rows (the factorisation's forward sweep
+// leaves the same).  Step s visits block row tw_row(s): s < 2k the two
+// forward chains, s = 2k the middle, s > 2k the two back chains.
+template <int m> __device__ __forceinline__ int tw_row(int s)
+{
+    constexpr int k = (m - 1) / 2;
+    // independent selects (no branch chain)
+    int r = k + 1 + (s - m - k);
+    r = s < m + k ? k - 1 - (s - m) : r;
+    r = s == 2 * k ? k : r;
+    r = s < 2 * k ? m - 1 + k - s : r;
+    r = s < k ? s : r;
+    return r;
+}
+template <typename Tst, int M, int DEPTH, typename Tac, typename Buf, typename LoadF, typename ApplyF,
+          typename GatherF>
+__device__ __forceinline__ void solve_twisted(const double *__restrict__ scs, const double *__restrict__ bs,
+                                              const double *__restrict__ rs, double rhs_const,
+                                              double *__restrict__ xs, int accumulate, double *__restrict__ zs,
+                                              bool fwd_done, bool own, int t, Tac *g, Buf &bA, Buf &bB, Buf &bC,
+                                              LoadF &load, ApplyF &apply, GatherF &gather)
+{
+    constexpr int m = M - 1, k = (m - 1) / 2, NS = 2 * m - 1, NF = 2 * k;
+    const double rc = t < m ? rhs_const : 0.0;
+    // Steps [s0, s1) with the rotation of solve_blk_pass: step s applies its
+    // block while the block of step s + DEPTH (clamped to s1 - 1; a redundant
+    // load is harmless) streams in; upd(s) is the owner threads' update.
+    auto run = [&](int s0, int s1, auto &&upd) {
+        auto step = [&](int s, Buf &use, Buf &fill) {
+            if constexpr (DEPTH > 0) {
+                load(tw_row<m>(s + DEPTH < s1 ? s + DEPTH : s1 - 1), fill);
+                apply(use);
+            } else {
+                load(tw_row<m>(s), bA);
+                apply(bA);
+            }
+            __syncthreads();
+            if (own) upd(s);
+            __syncthreads();
+        };
+        if constexpr (DEPTH >= 1) load(tw_row<m>(s0), bA);
+        if constexpr (DEPTH == 2) load(tw_row<m>(s0 + 1 < s1 ? s0 + 1 : s0), bB);
+        __syncthreads();
+        int s = s0;
+        if constexpr (DEPTH == 2) {
+            for (; s + 3 <= s1; s += 3) {
+                step(s, bA, bC);
+                step(s + 1, bB, bA);
+                step(s + 2, bC, bB);
+            }
+            if (s < s1) step(s++, bA, bC);
+            if (s < s1) step(s++, bB, bA);
+        } else if constexpr (DEPTH == 1) {
+            for (; s + 2 <= s1; s += 2) {
+                step(s, bA, bB);
+                step(s + 1, bB, bA);
+            }
+            if (s < s1) step(s++, bA, bB);
+        } else {
+            for (; s < s1; ++s) step(s, bA, bA);
+        }
+    };
+    // The inputs of an update are read one step ahead and combined only when
+    // used (an operation on a value in flight would wait for it, and with it
+    // for the block loads issued before).
+    double l_sc = 0.0, l_r = 0.0, l_b = 0.0, l_z = 0.0, l_x = 0.0;
+    double b_k = 0.0, b_k1 = 0.0;
+    if (own) {
+        b_k = bs[k * M + t];
+        b_k1 = bs[(k + 1) * M + t];
+    }
+    Tac sav = 0;  // z_{k-1}, then x_k
+    // inputs of back step q: z (or w), scaling and old x of its row, and the
+    // beta that couples the next back step's row to it
+    auto fetch_b = [&](int q) {
+        q = q < NS ? q : NS - 1;
+        const int j = tw_row<m>(q);
+        const int ib0 = q + 1 < m + k ? j : j + 1;
+        l_z = zs[j * M + t];
+        l_sc = scs[j * M + t];
+        l_x = accumulate ? xs[j * M + t] : 0.0;
+        l_b = bs[(ib0 < m ? ib0 : m - 1) * M + t];
+    };
+    if (!fwd_done) {
+        // inputs of forward step q's right-hand side: the scaled rhs of its
+        // row and the beta coupling it to the step before (beta_q on the top
+        // chain, beta_{j+1} on the bottom one, beta_{k+1} at the middle; none
+        // at the first bottom step)
+        auto fetch_f = [&](int q) {
+            q = q < NF ? q : NF;
+            const int j = tw_row<m>(q);
+            l_sc = scs[j * M + t];
+            l_r = rs ? rs[j * M + t] : rc;
+            l_b = bs[(q <= k ? j : j + 1) * M + t];
+        };
+        if (own) {
+            g[t] = (Tac)(scs[t] * (rs ? rs[t] : rc));
+            fetch_f(1);
+        }
+        run(0, NF, [&](int s) {
+            const Tac v = -gather(t);
+            zs[tw_row<m>(s) * M + t] = (double)v;
+            sav = s == k - 1 ? v : sav;
+            // g of step s + 1; the middle also takes -beta_k z_{k-1}
+            const Tac cb = s + 1 == k ? (Tac)0 : -(Tac)l_b;
+            const Tac cm = s + 1 == NF ? -(Tac)b_k * sav : (Tac)0;
+            g[t] = (Tac)(l_sc * l_r) + cb * v + cm;
+            fetch_f(s + 2);
+        });
+        // the middle block row
+        double m_sc = 0.0, m_x = 0.0;
+        if (own) {
+            m_sc = scs[k * M + t];
+            m_x = accumulate ? xs[k * M + t] : 0.0;
+        }
+        load(k, bA);
+        apply(bA);
+        __syncthreads();
+        if (own) {
+            sav = -gather(t);
+            zs[k * M + t] = (double)sav;
+            xs[k * M + t] = m_x + m_sc * (double)sav;
+            g[t] = (Tac)b_k * sav;
+            fetch_b(m);
+        }
+        __syncthreads();
+    } else if (own) {
+        // the factorisation left z, x_k and w: the back sweeps start at once
+        sav = (Tac)zs[k * M + t];
+        const double d = scs[k * M + t] * (double)sav;
+        xs[k * M + t] = accumulate ? xs[k * M + t] + d : d;
+        g[t] = (Tac)b_k * sav;
+        fetch_b(m);
+    }
+    run(m, NS, [&](int s) {
+        const Tac v = (Tac)l_z + gather(t);
+        const double d = l_sc * (double)v;
+        xs[tw_row<m>(s) * M + t] = accumulate ? l_x + d : d;
+        // g of step s + 1: beta x of the row before; the first bottom step
+        // takes beta_{k+1} x_k
+        g[t] = s + 1 == m + k ? (Tac)b_k1 * sav : (Tac)l_b * v;
+        fetch_b(s + 1);
+    });
+}
+
 // x (+)= S Ahat^{-1} S rhs for one sample with the block-layout factor fs
 // (all threads of the workgroup call it).  Wave w holds the blocks of its
 // row pair; per Schur block it forms its share of F g: row sums of its
@@ -338,6 +493,11 @@ __device__ __forceinline__ void solve_blk_pass(const double *__restrict__ scs, c
     // Thread t < M owns vector entry t of every block; its inputs of the next
     // block are loaded one block ahead.
     const bool own = t < M;
+    if constexpr (twisted<Tac, M>()) {
+        solve_twisted<Tst, M, DEPTH>(scs, bs, rs, rhs_const, xs, accumulate, zs, fwd_done, own, t, g, bA, bB, bC,
+                                     load, apply, gather);
+        return;
+    }
     // forward: z_j = -F_j (s_j r_j - beta_j z_{j-1})
     Tac xc = 0;
     double v_sc = 0.0, v_b = 0.0, v_r = 0.0;
