@@ -56,11 +56,11 @@ DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}  # factor storage bytes
 # HBM bytes per sample measured with FETCH_SIZE / WRITE_SIZE counters (scaled
 # by a copy kernel of known size) for the mixed FP32 step; valid only while the
 # kernel sources hash to TRAFFIC_SRC (otherwise the field is reported as null).
-TRAFFIC_SRC = "c4afe50bb374f9b8"
-TRAFFIC = {("factor", 128, "f32"): 5.2381e6, ("factor", 64, "f32"): 0.7834e6,
+TRAFFIC_SRC = "f7a0fbb23c41e652"
+TRAFFIC = {("factor", 128, "f32"): 5.3064e6, ("factor", 64, "f32"): 0.7963e6,
            ("factor", 32, "f32"): 0.1299e6, ("factor", 16, "f32"): 0.0467e6,
-           ("solve", 128, "f32"): 17.0702e6, ("solve", 64, "f32"): 2.5141e6,
-           ("solve", 32, "f32"): 0.1488e6, ("solve", 16, "f32"): 0.0052e6}
+           ("solve", 128, "f32"): 16.8310e6, ("solve", 64, "f32"): 2.5282e6,
+           ("solve", 32, "f32"): 0.1486e6, ("solve", 16, "f32"): 0.0052e6}
 
 
 def kernel_src_hash():
