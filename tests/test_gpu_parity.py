@@ -323,8 +323,8 @@ def test_error_codes():
 # ----------------------------------------------------------------- forced conditions
 
 @pytest.mark.parametrize("n,dtype,solver", [(16, "f32", "direct_ir"), (32, "f32", "direct_ir"),
-                                            (64, "f32", "direct_ir"), (32, "f64", "direct"),
-                                            (64, "f64", "direct")])
+                                            (64, "f32", "direct_ir"), (128, "f32", "direct_ir"),
+                                            (32, "f64", "direct"), (64, "f64", "direct")])
 def test_nonfinite_xi_flags_only_its_sample(n, dtype, solver):
     """A NaN in one xi row: that sample ends flagged non-finite and not
     converged (after promotion, for the low-precision factor), the call
@@ -332,9 +332,9 @@ def test_nonfinite_xi_flags_only_its_sample(n, dtype, solver):
     field tiles, waves and workgroups with it) still matches the oracle."""
     torch = _torch()
     K, s2, lam, seed = 16, 1.0, 0.3, 21
-    level = {16: 0, 32: 1, 64: 2}[n]
+    level = {16: 0, 32: 1, 64: 2, 128: 3}[n]
     S, bad = 40, 5
-    ctx = _ctx(n0=16, L_max=2, K=K, sigma2=s2, corr_len=lam, seed=seed)
+    ctx = _ctx(n0=16, L_max=max(level, 2), K=K, sigma2=s2, corr_len=lam, seed=seed)
     xi = si.splitmix64_normals(seed, level, 0, S, K)
     xi_bad = xi.copy()
     xi_bad[bad, 3] = float("nan")
