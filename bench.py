@@ -689,8 +689,10 @@ def main():
             trips[n] = (s0 + Ns[i], t0_ + Ns[i] * t)
     trips = {n: v[1] / v[0] for n, v in trips.items()}
 
-    # ---- roofline of the dominant kernel of the mixed step
-    (kind, n), r = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    # ---- roofline of the dominant kernel of the mixed step: the longest
+    # launch (the levels run concurrently, and the step's critical path runs
+    # through its longest kernel)
+    (kind, n), r = max(prof.items(), key=lambda kv: kv[1]["ms"] / kv[1]["launches"])
     avg_ms = r["ms"] / r["launches"]
     per_launch = r["samples"] / r["launches"]
     if kind == "factor":

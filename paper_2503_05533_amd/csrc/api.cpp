@@ -431,9 +431,11 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
 // (promote != 0, low-precision factor) are compacted on the device and
 // re-solved with an FP64 factor in a second pass, up to promo_slots of them.
 // q (S doubles, device) receives Q; iters the corrections per sample.
+// ev_main (optional) is recorded on st after the set-up kernels, before the
+// factorisation (or the iterative solver).
 int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
                const mlmc_level_opts &o, double eps, void *ws, double *q, int32_t *iters,
-               hipStream_t st)
+               hipStream_t st, hipEvent_t ev_main = nullptr)
 {
     const int n = L.n, S = (int)L.S, K = ctx->cfg.K, P = (n + 1) * (n + 1);
     if (S == 0) return MLMC_OK;
@@ -446,6 +448,7 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     // the n = 16 factorisation forms the scaled operator itself
     if (o.solver == MLMC_MGCG) {
         HIPCHK(launch_init_state(S, state, relres, st));
+        if (ev_main) HIPCHK(hipEventRecord(ev_main, st));
         PROF(5, n, S, launch_mgcg(n, S, ctx->cfg.f, a, at<double>(ws, L.off_x), at<double>(ws, L.off_mgv),
                                   at<float>(ws, L.off_mgh), eps, ctx->cfg.minres_max_iter, state, relres, q, iters,
                                   ctx->cfg.disc, st));
@@ -453,6 +456,7 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     }
     if (is_minres(o.solver) || !factor_forms_coeffs(n)) PROF(1, n, S, launch_coeffs(n, S, a, sc, gam, beta, ctx->cfg.disc, st));
     HIPCHK(launch_init_state(S, state, relres, st));
+    if (ev_main) HIPCHK(hipEventRecord(ev_main, st));
     if (is_minres(o.solver)) {
         // MINRES: FP64 vectors, a restart from the true residual at most 8
         // times; MINRES-IR: FP32 inner vectors, up to ir_max_iter refinements
@@ -533,11 +537,16 @@ int level_enqueue(mlmc_ctx *ctx, int level, int64_t n, const double *xi, const m
 // spread over exactly kQueues streams created back to back: the most
 // expensive grid (the fine grid of the finest level, a latency-bound chain
 // of factor and refinement) alone on the first, the others longest first
-// onto the least loaded of the rest.  A level's pairing and sums are
-// enqueued after all grids (so that no grid waits behind them), on the
-// stream of its fine grid, after an event of its coarse grid.  Cost model:
-// samples x n^3.5 (between the n^3 of the solves and the n^4 of the
-// factorisation).
+// onto the least loaded of the rest.  The other queues start only when the
+// first grid's factorisation is next in its queue (an event after its
+// set-up kernels): its workgroups then take their CUs before the other
+// grids' kernels fill them, and run at the rate they have alone (started
+// together, the other grids' workgroups held the LDS and registers that
+// the factorisation's workgroups waited for, and the chain took 1.8x its
+// time alone).  A level's pairing and sums are enqueued after all grids (so
+// that no grid waits behind them), on the stream of its fine grid, after an
+// event of its coarse grid.  Cost model: samples x n^3.5 (between the n^3 of
+// the solves and the n^4 of the factorisation).
 constexpr int kQueues = 4;
 
 // The context's kQueues streams (created back to back, default priority) and
@@ -562,7 +571,7 @@ int enqueue_levels_queued(mlmc_ctx *ctx, int n_levels, const int32_t *levels, co
                           const std::vector<level_layout> &LL, const std::vector<size_t> &off,
                           double *const *y_dev, hipStream_t os)
 {
-    if (int rc = ensure_queues(ctx, 1 + 2 * (size_t)n_levels + kQueues)) return rc;
+    if (int rc = ensure_queues(ctx, 2 + 2 * (size_t)n_levels + kQueues)) return rc;
     struct job { int li, coarse; double cost; };
     std::vector<job> jobs;
     for (int i = 0; i < n_levels; ++i) {
@@ -589,10 +598,13 @@ int enqueue_levels_queued(mlmc_ctx *ctx, int n_levels, const int32_t *levels, co
     HIPCHK(hipEventRecord(fork, os));
     bool used[kQueues] = {};
     for (size_t k = 0; k < jobs.size(); ++k) used[qof[k]] = true;
-    for (int q = 0; q < kQueues; ++q)
-        if (used[q]) HIPCHK(hipStreamWaitEvent(ctx->qstreams[q], fork, 0));
+    if (used[0]) HIPCHK(hipStreamWaitEvent(ctx->qstreams[0], fork, 0));
+    hipEvent_t head = ctx->qevents[1 + 2 * (size_t)n_levels + kQueues];
     std::vector<int> fine_q(n_levels, 0), coarse_q(n_levels, 0);
     for (size_t k = 0; k < jobs.size(); ++k) {
+        if (k == 1)
+            for (int q = 1; q < kQueues; ++q)
+                if (used[q]) HIPCHK(hipStreamWaitEvent(ctx->qstreams[q], head, 0));
         const job &J = jobs[k];
         const int i = J.li;
         hipStream_t sq = ctx->qstreams[qof[k]];
@@ -602,7 +614,8 @@ int enqueue_levels_queued(mlmc_ctx *ctx, int n_levels, const int32_t *levels, co
         const grid_layout &G = J.coarse ? L.coarse : L.fine;
         void *wg = at<void>(w, J.coarse ? L.off_coarse : L.off_fine);
         int rc = solve_grid(ctx, G, levels[i] - J.coarse, xi_dev[i], o, J.coarse ? o.eps_coarse : o.eps_fine, wg,
-                            at<double>(w, J.coarse ? L.off_qc : L.off_qf), at<int32_t>(wg, G.off_iters), sq);
+                            at<double>(w, J.coarse ? L.off_qc : L.off_qf), at<int32_t>(wg, G.off_iters), sq,
+                            k == 0 ? head : nullptr);
         if (rc) return rc;
         if (J.coarse) {
             coarse_q[i] = qof[k];
