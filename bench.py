@@ -93,16 +93,19 @@ def factor_entries(n, dtype):
 def refine_bytes(n, trips, dtype):
     """Algorithmic HBM bytes per sample of the refinement kernel: each of the
     `trips` corrections reads the factor twice (forward and backward block
-    sweeps), the initial solve once where the factorisation ran the forward
-    sweep (the low-precision factors, and FP64 at n = 16) and twice for
-    FP64 elsewhere, each solve also the row couplings and scaling; every
-    residual (1 + trips) reads the nodal coefficient and the iterate; x is
-    written."""
+    sweeps); the initial solve reads it not at all where the factorisation
+    ran both sweeps (n = 16, and the low-precision factors' twisted layouts
+    at n = 32..128), once where it ran the forward sweep (the low-precision
+    factors elsewhere) and twice for FP64; each solve also the row couplings
+    and scaling; every residual (1 + trips) reads the nodal coefficient and
+    the iterate; x is written."""
     m = n - 1
     N = m * n
     f_pass = factor_entries(n, dtype) * DT_BYTES[dtype]
-    fused = dtype != "f64" or n == 16
-    initial = (1 if fused else 2) * f_pass + 3 * N * 8
+    if n == 16 or (dtype != "f64" and n <= 128):
+        initial = 0
+    else:
+        initial = (1 if dtype != "f64" else 2) * f_pass + 3 * N * 8
     per_corr = 2 * f_pass + 3 * N * 8
     per_resid = (n + 1) ** 2 * 8 + N * 8
     return initial + trips * per_corr + (1 + trips) * per_resid + N * 8

@@ -397,7 +397,8 @@ int refine(mlmc_ctx *ctx, const grid_layout &L, void *ws, int dt, bool direct, d
     g.q = q;
     g.iters = iters;
     g.variant = ctx->ir_variant[dt][ilog2(n)];
-    g.fwd_done = fwd_done ? 1 : 0;
+    // 2: the factorisation also ran the back sweep (x0 in x; block layouts)
+    g.fwd_done = !fwd_done ? 0 : (n > 16 && factor_solves_initial(dt, n) ? 2 : 1);
     g.disc = ctx->cfg.disc;
     PROF(3, n, S, launch_ir(dt, g, st));
     if (L.promo_slots > 0 && dt != MLMC_F64) {
@@ -490,7 +491,7 @@ int solve_grid(mlmc_ctx *ctx, const grid_layout &L, int level, const double *xi,
     double *x = at<double>(ws, L.off_x);
     PROF(2, n, S, launch_factor(dt, n, S, a, sc, beta, gam, factor, nullptr, nullptr, 0, state, h * h * ctx->cfg.f,
                                 fwd ? at<double>(ws, L.off_z) : nullptr,
-                                fwd && factor_solves_initial(n) ? x : nullptr, ctx->cfg.disc,
+                                fwd && factor_solves_initial(dt, n) ? x : nullptr, ctx->cfg.disc,
                                 ctx->factor_variant[dt][ilog2(n)], st));
     return refine(ctx, L, ws, dt, direct, ctx->cfg.f, eps, x, q, iters, st, fwd);
 }

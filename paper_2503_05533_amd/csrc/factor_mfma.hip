@@ -63,7 +63,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
                                                              int64_t slot_base,
                                                              uint32_t *__restrict__ state,
                                                              const double *__restrict__ fsc, double frhs,
-                                                             double *__restrict__ fz)
+                                                             double *__restrict__ fz, double *__restrict__ x0)
 {
     using Tac = typename store_traits<Tst>::acc;
     using V4 = typename vec4_of<Tac>::type;
@@ -82,6 +82,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
     __shared__ Tac gfw_[NG][FWD ? M : 1];
     __shared__ Tac partR_[NG][FWD ? W : 1][FWD ? M : 1];
     __shared__ Tac partC_[NG][FWD ? W : 1][2][FWD ? M : 1];
+    __shared__ Tac xk_[(FWD && TW) ? M : 1];  // x_k, passed to the bottom group's back sweep
     __shared__ int bad;
     const int b = blockIdx.x;
     if (count && b >= *count) return;
@@ -129,6 +130,52 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
         pg = gs[rowof(0) * M + t];
     }
     bool okw = true, okc = true;
+    // The wave's partials of F g (g in gfw, entries of F by fval(slot, r)):
+    // row sums of its tiles reduced across 16-lane rows, transposed
+    // contributions of the off-diagonal tiles across the four lane rows, each
+    // in its own slot (the solve's fixed-order scheme).
+    auto partials = [&](int wj, auto &&fval) {
+        Tac ra0[4] = {0, 0, 0, 0}, ra1[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < SPW; ++q) {
+            int I, J;
+            slot_blk<NB, 1>(wj, q, I, J);
+            Tac f[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f[r] = fval(q, r);
+            const Tac gjv = gfw[16 * J + lc];
+            const bool first = (I == wj);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (first)
+                    ra0[r] = fma(f[r], gjv, ra0[r]);
+                else
+                    ra1[r] = fma(f[r], gjv, ra1[r]);
+            }
+            if (I != J) {
+                Tac c = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c = fma(f[r], gfw[16 * I + drow<Tac>(lr, r)], c);
+                c = rows4_total(c);
+                if (lr == 0) partC[wj][first ? 0 : 1][16 * J + lc] = c;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const Tac v0 = row16_total(ra0[r]);
+            const Tac v1 = row16_total(ra1[r]);
+            if (lc == 15) {
+                partR[wj][16 * wj + drow<Tac>(lr, r)] = v0;
+                if (NB > 1) partR[wj][16 * (NB - 1 - wj) + drow<Tac>(lr, r)] = v1;
+            }
+        }
+    };
+    auto gathered = [&](auto i) {
+        Tac v = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) v += partR[ww][i] + partC[ww][0][i] + partC[ww][1][i];
+        return v;
+    };
 
     for (int j = 0; j < STEPS; ++j) {
         const int jb = j & 1, row = rowof(j);
@@ -334,49 +381,68 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
                     }
                 }
                 asm volatile("" : "+s"(wj));
-                Tac ra0[4] = {0, 0, 0, 0}, ra1[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int q = 0; q < SPW; ++q) {
-                    int I, J;
-                    slot_blk<NB, 1>(wj, q, I, J);
-                    Tac f[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) f[r] = store_traits<Tst>::load(store_traits<Tst>::store(acc[q][r]));
-                    const Tac gjv = gfw[16 * J + lc];
-                    const bool first = (I == wj);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (first)
-                            ra0[r] = fma(f[r], gjv, ra0[r]);
-                        else
-                            ra1[r] = fma(f[r], gjv, ra1[r]);
-                    }
-                    if (I != J) {
-                        Tac c = 0;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) c = fma(f[r], gfw[16 * I + drow<Tac>(lr, r)], c);
-                        c = rows4_total(c);
-                        if (lr == 0) partC[wj][first ? 0 : 1][16 * J + lc] = c;
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const Tac v0 = row16_total(ra0[r]);
-                    const Tac v1 = row16_total(ra1[r]);
-                    if (lc == 15) {
-                        partR[wj][16 * wj + drow<Tac>(lr, r)] = v0;
-                        if (NB > 1) partR[wj][16 * (NB - 1 - wj) + drow<Tac>(lr, r)] = v1;
-                    }
-                }
+                partials(wj, [&](int q, int r) {
+                    return store_traits<Tst>::load(store_traits<Tst>::store(acc[q][r]));
+                });
                 __syncthreads();
                 if (t < M) {
-                    Tac v = 0;
-#pragma unroll
-                    for (int ww = 0; ww < W; ++ww) v += partR[ww][t] + partC[ww][0][t] + partC[ww][1][t];
-                    zc = -v;
+                    zc = -gathered(t);
                     if (keep) fzs[row * M + t] = (double)zc;
                 }
             }
+        }
+    }
+    if constexpr (TW && FWD) {
+        if (fwd && x0) {
+            // The back sweeps of the initial solve, both chains at once, from
+            // the middle outwards with the blocks as stored (each wave reads back
+            // the tiles it wrote): x_j = z_j + F_j beta_{j+1} x_{j+1} (top),
+            // x_j = w_j + F_j beta_j x_{j-1} (bottom); x0 = S x.
+            double *xs0 = x0 + (size_t)s * m * M;
+            if (grp == 0 && t < M) {
+                xk_[t] = zc;
+                xs0[KM * M + t] = fscs[KM * M + t] * (double)zc;
+            }
+            __syncthreads();
+            Tac xp = t < M ? xk_[t] : (Tac)0;
+            // step jj: block row KM - 1 - jj (top) or KM + 1 + jj (bottom); the
+            // next step's tiles load while this one is applied (two buffers that
+            // rotate by unrolling)
+            auto brow_of = [&](int jj) { return grp ? KM + 1 + jj : KM - 1 - jj; };
+            auto ld = [&](int jj, quad<Tst> (&dst)[SPW]) {
+                int wq = w;
+                asm volatile("" : "+s"(wq));
+                const Tst *fb = fs + (size_t)brow_of(jj) * NBL * 256;
+#pragma unroll
+                for (int q = 0; q < SPW; ++q) {
+                    int I, J;
+                    slot_blk<NB, 1>(wq, q, I, J);
+                    dst[q] = *(const quad<Tst> *)(fb + ((size_t)(I * (I + 1) / 2 + J) * 64 + l) * 4);
+                }
+            };
+            auto bstep = [&](int jj, quad<Tst> (&use)[SPW], quad<Tst> (&fill)[SPW]) {
+                const int row = brow_of(jj);
+                const int bi = grp ? row : row + 1;
+                ld(jj + 1 < KM ? jj + 1 : KM - 1, fill);  // a redundant last load is harmless
+                if (t < M) gfw[t] = (Tac)bs[bi * M + t] * xp;
+                __syncthreads();
+                int wj = w;
+                asm volatile("" : "+s"(wj));
+                partials(wj, [&](int q, int r) { return store_traits<Tst>::load(use[q].v[r]); });
+                __syncthreads();
+                if (t < M) {
+                    xp = (Tac)fzs[row * M + t] + gathered(t);
+                    xs0[row * M + t] = fscs[row * M + t] * (double)xp;
+                }
+            };
+            quad<Tst> tA[SPW], tB[SPW];
+            ld(0, tA);
+            int jj = 0;
+            for (; jj + 2 <= KM; jj += 2) {
+                bstep(jj, tA, tB);
+                bstep(jj + 1, tB, tA);
+            }
+            if (jj < KM) bstep(jj, tA, tB);
         }
     }
     if (TW && grp == 1) okw = okc;
@@ -649,10 +715,10 @@ hipError_t lf(int nb, const double *a, double *sc, double *beta, const double *g
         const dim3 block(64 * blk_waves<M, 1>() * factor_groups<Tst, M>());
         if (variant == 1 && mfma_in_storage<Tst>())
             hipLaunchKernelGGL((k_factor_mfma<Tst, M, false>), dim3(nb), block, 0, st, nb, beta, gam,
-                               (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz);
+                               (Tst *)factor, idx, count, slot_base, state, sc, frhs, fz, x0);
         else
             hipLaunchKernelGGL((k_factor_mfma<Tst, M>), dim3(nb), block, 0, st, nb, beta, gam, (Tst *)factor, idx,
-                               count, slot_base, state, sc, frhs, fz);
+                               count, slot_base, state, sc, frhs, fz, x0);
     }
     return hipGetLastError();
 }
@@ -700,6 +766,18 @@ hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, dou
 bool factor_fuses_forward(int dtype, int n)
 {
     return use_blk(dtype, n) && (dtype != 0 || n == 16);
+}
+
+bool factor_solves_initial(int dtype, int n)
+{
+    if (n == 16) return true;
+    if (!factor_fuses_forward(dtype, n)) return false;
+    switch (n) {
+    case 32: return twisted<float, 32>();
+    case 64: return twisted<float, 64>();
+    case 128: return twisted<float, 128>();
+    }
+    return false;
 }
 
 }  // namespace mlmc

@@ -51,7 +51,7 @@ struct ir_args {
     double *relres, *q;
     int32_t *iters;
     int variant;  // refinement-kernel variant (0: built-in default; n >= 64: waves per row pair)
-    int fwd_done;  // the factorisation wrote the forward sweep of the initial solve to z
+    int fwd_done;  // the factorisation wrote the forward sweep of the initial solve to z (2: all of it, x0 in x)
     int disc;      // edge coefficients: 0 harmonic means (finite volumes), 1 P1 elements
 };
 
@@ -75,8 +75,9 @@ hipError_t launch_coeffs(int n, int S, const double *a, double *sc, double *gam,
 // values).  With fz != NULL (and factor_fuses_forward) it also runs the
 // forward sweep of the solve for the right-hand side frhs (constant, interior
 // unknowns) scaled by sc, writing z to fz (the refinement's z buffer); where
-// factor_solves_initial(n), with x0 != NULL, the back sweep as well, writing
-// the initial solve to x0.  variant (the autotuner's choice, 0 default): 1
+// factor_solves_initial(dtype, n), with x0 != NULL, the back sweep as well,
+// writing the initial solve to x0 (n = 16, and the twisted block layouts,
+// whose two wave groups run the two back sweeps at once).  variant (the autotuner's choice, 0 default): 1
 // forms the FP16/BF16 factors' MFMA products in FP32 instead of their format.
 hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                          const double *gam, void *factor, const int *idx, const int *count,
@@ -84,11 +85,11 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double 
                          int disc, int variant, hipStream_t st);
 bool factor_fuses_forward(int dtype, int n);
 inline bool factor_forms_coeffs(int n) { return n == 16; }
-inline bool factor_solves_initial(int n) { return n == 16; }
+bool factor_solves_initial(int dtype, int n);
 // Initial solve + refinement loop of Algorithm 2.1, one workgroup per sample
-// (16 samples per workgroup at n = 16).  fwd_done: the factorisation ran the
-// forward sweep (z in the z buffer), or at n = 16 the whole initial solve
-// (x0 in x).
+// (16 samples per workgroup at n = 16).  fwd_done: 1, the factorisation ran
+// the forward sweep (z in the z buffer), or at n = 16 the whole initial solve
+// (x0 in x); 2 (block layouts), the whole initial solve (x0 in x).
 hipError_t launch_ir(int dtype, const ir_args &g, hipStream_t st);
 hipError_t launch_factor_blk(int dtype, int n, int nblocks, const double *a, double *sc, double *beta,
                              const double *gam, void *factor, const int *idx, const int *count,

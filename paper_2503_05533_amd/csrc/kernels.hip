@@ -762,7 +762,7 @@ hipError_t launch_factor(int dtype, int n, int nblocks, const double *a, double 
 {
     if (nblocks == 0) return hipSuccess;
     if (fz && !factor_fuses_forward(dtype, n)) return hipErrorInvalidValue;
-    if (x0 && (!fz || idx || !factor_solves_initial(n))) return hipErrorInvalidValue;
+    if (x0 && (!fz || idx || !factor_solves_initial(dtype, n))) return hipErrorInvalidValue;
     if (use_blk(dtype, n))
         return launch_factor_blk(dtype, n, nblocks, a, sc, beta, gam, factor, idx, count, slot_base, state,
                                  frhs, fz, x0, disc, variant, st);

@@ -662,7 +662,8 @@ __global__ __launch_bounds__((64 * blk_waves<M, G>())) __attribute__((amdgpu_wav
     double *xs = x + vo, *rsb = r + vo, *zs = zbuf + vo;
     const double *as = a + (size_t)s * (n + 1) * (n + 1);
     const double h = 1.0 / n;
-    solve_blk_pass<Tst, M, G, PREF>(scs, bs, fs, nullptr, h * h * fconst, xs, 0, zs, fwd_done != 0);
+    // fwd_done 2: the factorisation ran the whole initial solve (x0 in x)
+    if (fwd_done != 2) solve_blk_pass<Tst, M, G, PREF>(scs, bs, fs, nullptr, h * h * fconst, xs, 0, zs, fwd_done != 0);
     uint32_t st = state[s] & ~(uint32_t)ST_DONE;
     double prev = INFINITY, rel = INFINITY, sx = 0.0;
     int trip = 0;

@@ -176,6 +176,7 @@ hipError_t launch_grad_gemm(int, int, int, const double *, const double *, const
 hipError_t launch_coeffs(int, int, const double *, double *, double *, double *, int, hipStream_t st) { return op(st); }
 hipError_t launch_factor(int, int, int, const double *, double *, double *, const double *, void *, const int *, const int *, int64_t, uint32_t *, double, double *, double *, int, int, hipStream_t st) { return op(st); }
 bool factor_fuses_forward(int dtype, int n) { return use_blk(dtype, n) && (dtype != 0 || n == 16); }
+bool factor_solves_initial(int dtype, int n) { return n == 16 || (factor_fuses_forward(dtype, n) && n <= 128); }
 hipError_t launch_ir(int, const ir_args &, hipStream_t st) { return op(st); }
 hipError_t launch_minres(int, int, double, const double *, const double *, const double *, const double *, double *, double *, void *, int, double, int, int, const int *, const int *, uint32_t *, double *, double *, int32_t *, int, hipStream_t st) { return op(st); }
 hipError_t launch_adjoint_gz(int, int, const double *, const double *, const double *, double *, int, hipStream_t st) { return op(st); }
