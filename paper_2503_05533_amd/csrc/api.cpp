@@ -1637,12 +1637,14 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
     }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
-    if (int rc = ensure_queues(ctx, 1 + kQueues)) return rc;
+    if (int rc = ensure_queues(ctx, 2 + kQueues)) return rc;
     // Index i runs in chunks of Ci[i] samples whose fine and coarse solve
     // workspaces fit the budget; the indices are spread over the context's
     // queue streams (most expensive first onto the least loaded; cost
     // samples x n^3.5 x terms) and each stream runs its indices' chunks in
-    // order in buffers of its own.
+    // order in buffers of its own.  As in the multi-level step, the other
+    // queues start when the most expensive index's first factorisation is
+    // next in its queue.
     const size_t budget = (size_t)4 << 30;
     int64_t Ci[64], nch[64], sbase[64];
     int qof[64];
@@ -1706,10 +1708,11 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
     int64_t solves = 0;
     std::vector<double> h((size_t)nsum * 8);
     auto run = [&]() -> int {
-        hipEvent_t fork = ctx->qevents[0];
+        hipEvent_t fork = ctx->qevents[0], head = ctx->qevents[1 + kQueues];
         HIPCHK(hipEventRecord(fork, st));
-        for (int q = 0; q < kQueues; ++q)
-            if (Q[q].C) HIPCHK(hipStreamWaitEvent(ctx->qstreams[q], fork, 0));
+        const int q0 = qof[order[0]];
+        HIPCHK(hipStreamWaitEvent(ctx->qstreams[q0], fork, 0));
+        bool gated = false;
         for (int i : order) {
             const int l = mi->idx_l[i], k = mi->idx_k[i];
             const mlmc_level_opts &o = mi->opts[i];
@@ -1735,8 +1738,13 @@ int mlmc_mimc(mlmc_ctx *ctx, const mlmc_mimc_config *mi, mlmc_mimc_result *out, 
                         ++solves;
                         if (int rc = solve_grid(ctx, G, l - g, at<double>(buf, B.o_xm), o,
                                                 g ? o.eps_coarse : o.eps_fine, w, at<double>(buf, B.o_q[e]),
-                                                at<int32_t>(w, G.off_iters), sq))
+                                                at<int32_t>(w, G.off_iters), sq, gated ? nullptr : head))
                             return rc;
+                        if (!gated) {
+                            gated = true;
+                            for (int q = 0; q < kQueues; ++q)
+                                if (q != q0 && Q[q].C) HIPCHK(hipStreamWaitEvent(ctx->qstreams[q], head, 0));
+                        }
                         HIPCHK(hipMemcpyAsync(at<uint32_t>(buf, B.o_s[e]), at<uint32_t>(w, G.off_state),
                                               (size_t)cc * 4, hipMemcpyDeviceToDevice, sq));
                         have[e] = true;
