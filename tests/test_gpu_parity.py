@@ -225,7 +225,10 @@ def test_imax_zero_flags_samples():
 def test_initial_solve_residual(n, S):
     """Algorithm 2.1's initial solve alone (no correction): the forward and
     back sweeps, wherever they run (fused into the factorisation: both at
-    n = 16, the forward one for the low-precision factors elsewhere).  With the FP32 factor its relative residual is of the order of a
+    n = 16 and for the low-precision factors' twisted layouts at n = 32..128,
+    there from both ends of the grid, the back sweeps outwards from the middle
+    block row; in the refinement kernel for FP64).  With the FP32 factor its
+    relative residual is of the order of a
     textbook FP32 band-Cholesky solve of the same systems (the oracle's; the
     block-inverse factor measures at 0.6-0.8 of it); with FP16 storage at
     n <= 32 and BF16 at n = 16 it is below 1/2, where refinement contracts."""
