@@ -39,7 +39,8 @@ namespace mlmc {
 
 // Whether the factorisation also runs the forward sweep of the initial solve
 // (z_j = -F_j (s_j rhs - beta_j z_{j-1}) with each F_j as it is formed), so
-// that the solve starts with the back sweep: the FP32/BF16/FP16 factors.  In
+// that the solve starts with the back sweep (or, where the twisted layout's
+// factorisation runs that too, with the residual): the FP32/BF16/FP16 factors.  In
 // FP64 the partial sums would add 12-50 KB of LDS to a workgroup that already
 // holds 36-130 KB, crowding out the kernels of the other levels that share
 // its CU in the multi-level step (measured: slower and erratic steps).
