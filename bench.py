@@ -56,10 +56,10 @@ DT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}  # factor storage bytes
 # HBM bytes per sample measured with FETCH_SIZE / WRITE_SIZE counters (scaled
 # by a copy kernel of known size) for the mixed FP32 step; valid only while the
 # kernel sources hash to TRAFFIC_SRC (otherwise the field is reported as null).
-TRAFFIC_SRC = "d55c14ea6bbb7c13"  # counters taken at 66cff330e30e7dec; since then a comment edit only (device code identical)
-TRAFFIC = {("factor", 128, "f32"): 10.4681e6, ("factor", 64, "f32"): 1.5580e6,
+TRAFFIC_SRC = "815c97f5bfbd08c8"
+TRAFFIC = {("factor", 128, "f32"): 10.4705e6, ("factor", 64, "f32"): 1.5585e6,
            ("factor", 32, "f32"): 0.2540e6, ("factor", 16, "f32"): 0.0467e6,
-           ("solve", 128, "f32"): 11.6575e6, ("solve", 64, "f32"): 1.7648e6,
+           ("solve", 128, "f32"): 11.6568e6, ("solve", 64, "f32"): 1.7648e6,
            ("solve", 32, "f32"): 0.0249e6, ("solve", 16, "f32"): 0.0052e6}
 
 

@@ -12,7 +12,7 @@
 // 16 x 16 blocks of C live in MFMA accumulator registers (one wave owns every
 // W-th block); the rank-16 trailing update runs on v_mfma 16x16x4 (FP32 for
 // the FP32/BF16/FP16 factors, FP64 for the FP64 factor); -P^{-1} is formed
-// inside every wave by 16 broadcast sweep steps.
+// by one wave of the group in 16 broadcast sweep steps and shared through LDS.
 //
 // Stored factor: per Schur block j, NBL = NB(NB+1)/2 lower blocks b (row by
 // row), each in the MFMA result layout: entry (row drow(l/16, r), col l%16) of
@@ -75,7 +75,7 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
     constexpr int NG = TW ? 2 : 1, KM = (m - 1) / 2, STEPS = TW ? KM + 1 : m;
     // per wave group (the twisted elimination's two chains; one group otherwise)
     __shared__ Tac Vb_[NG][2][M * LD];      // panel columns C[:, K], double-buffered
-    __shared__ Tac Pw_[NG][W][16 * LD];     // per wave: -P^{-1}
+    __shared__ Tac Pw_[NG][16 * LD];        // -P^{-1} of the group's panel
     __shared__ Tac Uw_[NG][W][2][16 * LD];  // per wave: U of its two block rows
     __shared__ Tac bj_[NG][2][M], gj_[NG][2][M];
     // forward sweep (fz != NULL): right-hand side of the block, and per wave
@@ -259,9 +259,13 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
             }
             __syncthreads();
             asm volatile("" : "+s"(wk));
-            // every wave: -P^{-1} (redundantly), then U for its two block rows
-            Tac *P = Pw[wk];
-            {
+            // one wave of the group forms -P^{-1} (the sweeping wave rotates over
+            // the SIMDs with K, the two groups' on different SIMDs; the others
+            // wait at the barrier rather than repeat the sweep: the kernel is
+            // issue-bound where two workgroups share a CU), then every wave
+            // forms U for its two block rows
+            Tac *P = Pw;
+            if (W == 1 || wk == (K + 2 * grp) % W) {
                 Tac p[4];  // lane 16 g + i: P[i][4g .. 4g+3]
 #pragma unroll
                 for (int c = 0; c < 4; ++c) p[c] = V[(16 * K + lc) * LD + 4 * lr + c];
@@ -269,7 +273,10 @@ __global__ __launch_bounds__((64 * blk_waves<M, 1>() * factor_groups<Tst, M>()))
 #pragma unroll
                 for (int c = 0; c < 4; ++c) P[lc * LD + 4 * lr + c] = p[c];
             }
-            wave_lds_sync();
+            if constexpr (W > 1)
+                __syncthreads();
+            else
+                wave_lds_sync();
             // -P^{-1}[4kc+lr][lc] (= [lc][4kc+lr] by symmetry) is the B operand of U and
             // the A operand of row K; U rows are re-read in the A layout per block below
             // (operands are re-read from LDS rather than held, to bound registers).
